@@ -1,0 +1,540 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+Each test names the passage of the paper (or the mathematical fact) it pins.
+A plausible slip in the oracle -- a dropped slope term, a wrong sign of the
+drift, a transposed axis, the wrong time level, an unnormalised weight, a wrong
+end-node rule -- fails at least one of them.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+from numpy.polynomial.hermite import hermgauss
+from scipy.interpolate import PchipInterpolator
+
+import oracle
+import workloads as W
+from analytic import p_exit_images, p_exit_series
+
+# ---------------------------------------------------------------------------
+# Gauss-Hermite rule (Section 3.1.3, Eq. (expec)-(quad); Remark 2)
+# ---------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("q", list(range(1, 33)))
+def test_gh_matches_library(q):
+    a, w = oracle.gh_rule(q)
+    ha, hw = hermgauss(q)
+    np.testing.assert_allclose(a, ha, rtol=0, atol=2e-13 * max(1.0, np.abs(ha).max()))
+    np.testing.assert_allclose(w, hw / math.sqrt(math.pi), rtol=1e-11, atol=1e-15)
+    assert abs(w.sum() - 1.0) < 1e-14
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 6, 8, 16])
+def test_gh_gaussian_moments(q):
+    """E[xi^k] under rho = pi^{-1/2} e^{-xi^2}: 0 for odd k, (k-1)!!/2^{k/2} for
+    even k; the q-point rule is exact up to degree 2q-1 (Remark 2)."""
+    a, w = oracle.gh_rule(q)
+    for k in range(0, 2 * q):
+        got = float(np.sum(w * a ** k))
+        if k % 2:
+            exact = 0.0
+        else:
+            exact = float(np.prod(np.arange(k - 1, 0, -2))) / 2 ** (k // 2) if k else 1.0
+        scale = float(np.sum(w * np.abs(a) ** k))     # rounding scale of the sum
+        assert abs(got - exact) <= 1e-13 * max(1.0, scale), (q, k, got, exact)
+
+
+def test_gh_symmetric_and_max_nodes():
+    for q, amax in [(3, 1.224745), (6, 2.350605), (8, 2.930637), (16, 4.688739)]:
+        a, w = oracle.gh_rule(q)
+        assert np.all(a == -a[::-1]) and np.all(w == w[::-1])
+        assert abs(a.max() - amax) < 1e-6
+
+
+def test_tensor_rule_weights():
+    nodes, weights = oracle.tensor_rule(4, 2)
+    assert nodes.shape == (16, 2)
+    assert abs(weights.sum() - 1.0) < 1e-14
+    # E[xi_0^2 xi_1^2] = 1/4 for the product density
+    assert abs(np.sum(weights * nodes[:, 0] ** 2 * nodes[:, 1] ** 2) - 0.25) < 1e-14
+    # last dimension fastest
+    a, _ = oracle.gh_rule(4)
+    assert nodes[1, 1] == a[1] and nodes[1, 0] == a[0]
+
+
+# ---------------------------------------------------------------------------
+# Cell location
+# ---------------------------------------------------------------------------
+
+
+def test_cell_matches_searchsorted():
+    rng = np.random.default_rng(1)
+    x = np.sort(rng.uniform(-1, 3, size=37))
+    zs = np.concatenate([rng.uniform(-2, 4, size=2000), x, [x[0], x[-1], -5.0, 9.0]])
+    for z in zs:
+        ref = int(np.clip(np.searchsorted(x, z, side="right") - 1, 0, len(x) - 2))
+        assert oracle.cell(x, z) == ref, z
+
+
+# ---------------------------------------------------------------------------
+# Cubic Hermite interpolant (Section 3.1.2) and PCHIP slopes (Eq. (e300))
+# ---------------------------------------------------------------------------
+
+
+def _problem_on(nodes_list, periodic=None):
+    periodic = periodic or [False] * len(nodes_list)
+    axes = [W.Axis(np.asarray(x), p) for x, p in zip(nodes_list, periodic)]
+    return W.Problem(axes=axes, coef_kind="const", coef=(0.0,) * len(axes), D=0.1,
+                     region_kind="box", gh_q=3, dt=0.01, n_steps=1)
+
+
+def test_hermite_exact_on_cubics_1d():
+    rng = np.random.default_rng(2)
+    x = np.sort(np.concatenate([[0.0, 1.0], rng.uniform(0, 1, 20)]))
+    p = np.polynomial.Polynomial([0.3, -1.2, 2.5, -0.7])
+    prob = _problem_on([x])
+    u, g = p(x), p.deriv()(x)[None, :]
+    for z in rng.uniform(0, 1, 200):
+        assert abs(oracle.interp(prob, u, g, [z]) - p(z)) < 1e-13
+        dz = oracle.interp(prob, u, g, [z], grad=True)[0]
+        assert abs(dz - p.deriv()(z)) < 1e-11
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_hermite_tensor_exact_on_separable_cubics(d):
+    """Values + first partials, no mixed terms: exact on sum_i p_i(x_i)."""
+    rng = np.random.default_rng(3 + d)
+    xs = [np.sort(np.concatenate([[0.0, 1.0], rng.uniform(0, 1, 6 + i)])) for i in range(d)]
+    polys = [np.polynomial.Polynomial(rng.normal(size=4)) for _ in range(d)]
+    prob = _problem_on(xs)
+    grids = np.meshgrid(*xs, indexing="ij")
+    u = sum(polys[i](grids[i]) for i in range(d))
+    g = np.stack([polys[i].deriv()(grids[i]) for i in range(d)])
+    for _ in range(100):
+        z = rng.uniform(0, 1, d)
+        exact = sum(polys[i](z[i]) for i in range(d))
+        assert abs(oracle.interp(prob, u, g, z) - exact) < 1e-12
+        grad = oracle.interp(prob, u, g, z, grad=True)
+        for i in range(d):
+            assert abs(grad[i] - polys[i].deriv()(z[i])) < 1e-10
+
+
+def test_hermite_partition_and_continuity():
+    """H00 + H01 = 1: constants reproduced with zero slopes; C1 across a face."""
+    x = np.linspace(0, 1, 9)
+    prob = _problem_on([x])
+    rng = np.random.default_rng(5)
+    u = rng.uniform(size=9)
+    g = rng.normal(size=(1, 9))
+    for k in range(1, 8):
+        xl = x[k] - 1e-9
+        xr = x[k] + 1e-9
+        assert abs(oracle.interp(prob, u, g, [xl]) - oracle.interp(prob, u, g, [xr])) < 1e-7
+        gl = oracle.interp(prob, u, g, [xl], grad=True)[0]
+        gr = oracle.interp(prob, u, g, [xr], grad=True)[0]
+        assert abs(gl - g[0, k]) < 1e-6 and abs(gr - g[0, k]) < 1e-6
+    assert abs(oracle.interp(prob, np.full(9, 0.7), np.zeros((1, 9)), [0.33]) - 0.7) < 1e-15
+
+
+def test_pchip_interior_matches_library_on_uniform_axis():
+    """On a uniform axis the library PCHIP slope formula reduces to Eq. (e300)
+    (harmonic mean, zero when the differences differ in sign or vanish)."""
+    rng = np.random.default_rng(6)
+    x = np.linspace(-1, 2, 41)
+    u = np.cumsum(rng.normal(size=41)) * 0.1
+    u[10:14] = u[10]          # flat run: zero differences
+    prob = _problem_on([x])
+    g = oracle.slopes(prob, u)[0]
+    ref = PchipInterpolator(x, u).derivative()(x)
+    np.testing.assert_allclose(g[1:-1], ref[1:-1], rtol=1e-12, atol=1e-14)
+
+
+def test_pchip_end_nodes_follow_paper_rule():
+    """End slopes substitute (delta_1, delta_2) and (delta_{J-1}, delta_{J-2})."""
+    x = np.array([0.0, 0.5, 1.5, 3.0, 3.5])
+    u = np.array([0.0, 1.0, 1.5, 2.5, 2.0])
+    prob = _problem_on([x])
+    g = oracle.slopes(prob, u)[0]
+    d = np.diff(u) / np.diff(x)
+    hm = lambda a, b: 0.0 if a * b <= 0 else 2.0 / (1.0 / a + 1.0 / b)
+    assert abs(g[0] - hm(d[0], d[1])) < 1e-15
+    assert abs(g[-1] - hm(d[-1], d[-2])) < 1e-15
+    assert g[-1] == 0.0 and g[3] == 0.0      # sign change at node 3
+
+
+def test_pchip_affine_exact_and_periodic_constant():
+    x = np.linspace(0, 1, 11)
+    y = np.linspace(-1, 1, 7)
+    prob = _problem_on([x, y])
+    X, Y = np.meshgrid(x, y, indexing="ij")
+    g = oracle.slopes(prob, 2.0 * X - 3.0 * Y + 1.0)
+    np.testing.assert_allclose(g[0], 2.0, rtol=1e-13)
+    np.testing.assert_allclose(g[1], -3.0, rtol=1e-13)
+    # periodic axis: sin(2 pi x) sampled with node n-1 = node 0
+    xp = np.linspace(0, 1, 65)
+    probp = _problem_on([xp], [True])
+    u = np.sin(2 * np.pi * xp)
+    gp = oracle.slopes(probp, u)[0]
+    assert gp[0] == gp[-1]
+    # equal one-sided differences across the seam: slope = sin(2 pi h) / h,
+    # and the mirror node x = 1/2 carries the opposite slope
+    hp = xp[1] - xp[0]
+    assert abs(gp[0] - np.sin(2 * np.pi * hp) / hp) < 1e-12
+    assert abs(gp[0] + gp[32]) < 1e-12
+
+
+def test_pchip_shape_preserving():
+    """Monotone data -> monotone interpolant within the data range (the paper
+    relies on this to keep 0 <= u <= 1, Section 1 and 3.1.2)."""
+    rng = np.random.default_rng(7)
+    x = np.sort(np.concatenate([[0, 1], rng.uniform(0, 1, 30)]))
+    u = np.sort(rng.uniform(size=x.size))
+    prob = _problem_on([x])
+    g = oracle.slopes(prob, u)
+    zz = np.linspace(0, 1, 3001)
+    vals = np.array([oracle.interp(prob, u, g, [z]) for z in zz])
+    assert np.all(np.diff(vals) >= -1e-14)
+    assert vals.min() >= u.min() - 1e-14 and vals.max() <= u.max() + 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Whole step: translation, constants, affine fields, drift conventions
+# ---------------------------------------------------------------------------
+
+
+def test_translation_1d_and_2d():
+    """sigma = 0 and b = (k h)/dt: the scheme shifts chi by k cells per step.
+    Pins the sign of the drift, the axis order and the exit rule."""
+    n0, n1, dt, N = 21, 17, 0.01, 6
+    x = np.linspace(0.0, 2.0, n0)
+    y = np.linspace(0.0, 1.0, n1)
+    h0, h1 = x[1] - x[0], y[1] - y[0]
+    k0, k1 = 1, -2
+    prob = W.Problem(axes=[W.Axis(x), W.Axis(y)], coef_kind="const",
+                     coef=(k0 * h0 / dt, k1 * h1 / dt), D=0.0, region_kind="box",
+                     gh_q=2, dt=dt, n_steps=N)
+    out = oracle.solve(prob, snaps=list(range(N + 1)))
+    I0, I1 = np.meshgrid(np.arange(n0), np.arange(n1), indexing="ij")
+    for n in range(N + 1):
+        m = N - n
+        # the walk is monotone per axis: it has exited iff it starts on a face
+        # or ends on or beyond one
+        start = (I0 == 0) | (I0 == n0 - 1) | (I1 == 0) | (I1 == n1 - 1)
+        hit = start | (I0 + m * k0 >= n0 - 1) | (I0 + m * k0 <= 0) | \
+            (I1 + m * k1 >= n1 - 1) | (I1 + m * k1 <= 0)
+        np.testing.assert_allclose(out[n], hit.astype(float), atol=1e-12, err_msg=f"n={n}")
+    # 1D
+    p1 = W.Problem(axes=[W.Axis(x)], coef_kind="const", coef=(-h0 / dt,), D=0.0,
+                   region_kind="box", gh_q=3, dt=dt, n_steps=N)
+    o1 = oracle.solve(p1, snaps=[0])[0]
+    i0 = np.arange(n0)
+    np.testing.assert_allclose(o1, ((i0 - N <= 0) | (i0 == n0 - 1)).astype(float), atol=1e-12)
+
+
+@pytest.mark.parametrize("which", ["cell", "abc"])
+def test_constant_one_preserved(which):
+    if which == "cell":
+        prob = W.cell2d(nx=41, ny=21, n_steps=3)
+    else:
+        prob = W.abc3d(n=13, n_steps=3, D=2e-3)
+    u = oracle.step(prob, 1, np.ones(prob.shape))
+    np.testing.assert_allclose(u, 1.0, atol=1e-14)
+
+
+def test_affine_field_moves_with_drift_only():
+    """Symmetric GH nodes + exact PCHIP on affine data: one step maps
+    u = alpha + beta.x to alpha + beta.(x + b dt) at nodes whose landing points
+    stay inside the box (Eq. (e31) with E[xi] = 0)."""
+    x = np.linspace(0, 4, 41)
+    y = np.linspace(0, 2, 21)
+    b = (0.7, -0.4)
+    dt = 0.02
+    prob = W.Problem(axes=[W.Axis(x), W.Axis(y)], coef_kind="const", coef=b, D=0.05,
+                     region_kind="box", gh_q=4, dt=dt, n_steps=1)
+    X, Y = np.meshgrid(x, y, indexing="ij")
+    u1 = 0.2 + 0.1 * X - 0.3 * Y
+    u0 = oracle.step(prob, 0, u1)
+    inner = (slice(8, -8), slice(6, -6))
+    expect = 0.2 + 0.1 * (X + b[0] * dt) - 0.3 * (Y + b[1] * dt)
+    np.testing.assert_allclose(u0[inner], expect[inner], atol=1e-14)
+
+
+def _psi_cell(x, y, t, A, eps, om):
+    return A * np.sin(np.pi * (x + eps * np.sin(om * t))) * np.sin(np.pi * y)
+
+
+def test_cellular_drift_is_rotated_stream_gradient_at_t_n():
+    """Affine state => u^n - u^{n+1} = dt * beta . b(t_n, x_j).  b is obtained
+    here by central differences of the stream function psi of the workload,
+    with b = (-dpsi/dy, dpsi/dx) (the paper's sign convention, Section 4.2),
+    evaluated at the left end t_n of the step."""
+    A, eps, om = 1.3, 0.25, 9.0
+    dt, n = 0.01, 7
+    prob = W.cell2d(nx=81, ny=41, A=A, eps=eps, omega=om, D=1e-4, dt=dt,
+                    n_steps=10, radius=0.45)
+    x, y = prob.axes[0].nodes, prob.axes[1].nodes
+    X, Y = np.meshgrid(x, y, indexing="ij")
+    beta = (0.6, -0.9)
+    u1 = beta[0] * X + beta[1] * Y
+    u0 = oracle.step(prob, n, u1)
+    t = n * dt
+    hh = 1e-6
+    bx = -(_psi_cell(X, Y + hh, t, A, eps, om) - _psi_cell(X, Y - hh, t, A, eps, om)) / (2 * hh)
+    by = (_psi_cell(X + hh, Y, t, A, eps, om) - _psi_cell(X - hh, Y, t, A, eps, om)) / (2 * hh)
+    cls = oracle.node_class(prob)
+    # nodes well inside the disc (no landing point exits)
+    r = np.hypot(X - 0.5, Y - 0.5)
+    sel = (cls == 0) & (r < 0.35)
+    got = (u0 - u1)[sel] / dt
+    want = beta[0] * bx[sel] + beta[1] * by[sel]
+    np.testing.assert_allclose(got, want, atol=1e-6)
+    # a one-step shift of the time level would be visible at this omega
+    t1 = (n + 1) * dt
+    bx1 = -(_psi_cell(X, Y + hh, t1, A, eps, om) - _psi_cell(X, Y - hh, t1, A, eps, om)) / (2 * hh)
+    assert np.abs(beta[0] * (bx1 - bx)[sel]).max() > 1e-3
+
+
+def test_abc_drift_is_beltrami_and_modulated():
+    """The ABC field satisfies curl v = v and div v = 0; the modulation
+    multiplies it by 1 + amp sin t."""
+    prob = W.abc3d(n=9, A=1.0, B=0.8, C=0.6, amp=0.1)
+    rng = np.random.default_rng(8)
+    hh = 1e-5
+    for _ in range(20):
+        p = rng.uniform(-3, 3, 3)
+        t = float(rng.uniform(0, 5))
+        f = 1.0 + 0.1 * math.sin(t)
+        v = oracle.drift(prob, t, p)
+        J = np.zeros((3, 3))
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = hh
+            J[:, k] = (oracle.drift(prob, t, p + e) - oracle.drift(prob, t, p - e)) / (2 * hh)
+        curl = np.array([J[2, 1] - J[1, 2], J[0, 2] - J[2, 0], J[1, 0] - J[0, 1]])
+        np.testing.assert_allclose(curl, v, atol=1e-8)
+        assert abs(np.trace(J)) < 1e-8
+        v0 = oracle.drift(prob, 0.0, p)
+        np.testing.assert_allclose(v, f * v0, rtol=1e-13, atol=1e-15)
+
+
+def test_diffusion_scale_from_quadratic():
+    """For u = x^2 on an interior window the expectation adds
+    E[(S a)^2] = S^2/2 with S = sqrt(2D) sqrt(2 dt), i.e. 2 D dt: pins the
+    sqrt(2 dt) factor of Eq. (e31) and sigma = sqrt(2D).  PCHIP slopes are
+    not exact on x^2, so a fine grid and a loose tolerance are used."""
+    x = np.linspace(-1, 1, 4001)
+    D, dt = 0.3, 1e-3
+    prob = W.Problem(axes=[W.Axis(x)], coef_kind="const", coef=(0.0,), D=D,
+                     region_kind="box", gh_q=4, dt=dt, n_steps=1)
+    u1 = x ** 2
+    u0 = oracle.step(prob, 0, u1)
+    mid = slice(1500, 2500)
+    np.testing.assert_allclose((u0 - u1)[mid], 2 * D * dt, rtol=2e-3)
+
+
+def test_periodic_axis_wraps():
+    """Pure translation across a periodic seam: a bump moves around the
+    circle and comes back."""
+    n, dt = 33, 0.01
+    x = np.linspace(0, 1, n)
+    h = x[1] - x[0]
+    z = np.linspace(-1, 1, 9)
+    prob = W.Problem(axes=[W.Axis(x, True), W.Axis(z)], coef_kind="const",
+                     coef=(3 * h / dt, 0.0), D=0.0, region_kind="box", gh_q=2,
+                     dt=dt, n_steps=1)
+    rng = np.random.default_rng(9)
+    u = rng.uniform(size=(n, 9))
+    u[-1] = u[0]
+    u1 = oracle.step(prob, 0, u)
+    inner = slice(1, -1)
+    for i in range(n - 1):
+        np.testing.assert_allclose(u1[i, inner], u[(i + 3) % (n - 1), inner], atol=1e-12)
+    np.testing.assert_allclose(u1[-1], u1[0], atol=0)
+
+
+# ---------------------------------------------------------------------------
+# Whole scheme against the closed form (Section 4.1)
+# ---------------------------------------------------------------------------
+
+
+def test_series_forms_agree():
+    xs = np.linspace(0.05, 1.95, 39)
+    for T in (0.01, 0.1, 0.5, 1.0, 3.0):
+        np.testing.assert_allclose(p_exit_series(T, xs, 2.0), p_exit_images(T, xs, 2.0),
+                                   atol=1e-12)
+    # survey-quoted reference values at the centre of (-1, 1)
+    assert abs(p_exit_series(1.0, 1.0, 2.0) - 0.629222570200) < 1e-11
+
+
+def remark2_grid(L, h, dt, sigma, q):
+    """Uniform interior spacing h; first and last cells of width
+    sigma sqrt(2 dt) max|a| so that every landing point of an interior node
+    stays in the closed domain (Remark 2, with b = 0)."""
+    a, _ = oracle.gh_rule(q)
+    hb = sigma * math.sqrt(2 * dt) * np.abs(a).max()
+    m = max(1, int(round((L - 2 * hb) / h)))
+    inner = np.linspace(hb, L - hb, m + 1)
+    return np.concatenate([[0.0], inner, [L]])
+
+
+def test_bm_first_order_in_dt_on_remark2_grid():
+    """Paper Fig. ex3:f2 setting: X = X0 + W on [0, 10], T = 3, 3-point rule,
+    PCHIP, Assumption 1 enforced: error O(dt)."""
+    L, T, q = 10.0, 3.0, 3
+    errs, dts = [], [0.2, 0.1, 0.05, 0.025]
+    for dt in dts:
+        x = remark2_grid(L, 0.02, dt, 1.0, q)
+        prob = W.Problem(axes=[W.Axis(x)], coef_kind="const", coef=(0.0,), D=0.5,
+                         region_kind="box", gh_q=q, dt=dt, n_steps=int(round(T / dt)))
+        u0 = oracle.solve(prob, snaps=[0])[0]
+        errs.append(np.abs(u0 - p_exit_series(T, x, L)).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 0.8), (errs, rates)
+    assert errs[-1] < 0.01
+
+
+def test_bm1d_workload_vs_series_and_bounds():
+    """bm1d violates Assumption 1 (a landing point reaches 66 cells), so the
+    discrete-monitoring bias is visible; loose gate on u^0, strict bounds."""
+    prob = W.bm1d()
+    snaps = list(range(0, 101, 10))
+    out = oracle.solve(prob, snaps=snaps)
+    x = prob.axes[0].nodes
+    u0 = out[0]
+    ser = p_exit_series(1.0, x + 1.0, 2.0)
+    assert np.abs(u0 - ser).max() < 0.1
+    assert out.min() >= -1e-14 and out.max() <= 1 + 1e-14
+    # horizon monotonicity (autonomous): u^n >= u^{n+1}
+    for a, b in zip(out[:-1], out[1:]):
+        assert np.all(a >= b - 1e-12)
+
+
+def test_bm1d_matches_discrete_chain_monte_carlo():
+    """The scheme computes E over one Euler step per time step with exit checked
+    at step ends; a Monte Carlo run of that chain must agree within sampling
+    error plus the quadrature/interpolation error of the scheme."""
+    prob = W.bm1d()
+    u0 = oracle.solve(prob, snaps=[0])[0]
+    x = prob.axes[0].nodes
+    rng = np.random.default_rng(10)
+    sig_sqdt = math.sqrt(2 * prob.D * prob.dt)
+    for j in (100, 150, 190):
+        n_paths = 400_000
+        pos = np.full(n_paths, x[j])
+        alive = np.ones(n_paths, dtype=bool)
+        for _ in range(prob.n_steps):
+            pos[alive] += sig_sqdt * rng.standard_normal(alive.sum())
+            alive &= (pos > -1.0) & (pos < 1.0)
+        p_mc = 1.0 - alive.mean()
+        se = math.sqrt(max(p_mc * (1 - p_mc), 1e-12) / n_paths)
+        assert abs(u0[j] - p_mc) < 5 * se + 4e-3, (j, u0[j], p_mc, se)
+
+
+def _one_step_error(m, f):
+    """RMS error of one step on smooth data f against the exact Gauss-Hermite
+    expectation of f itself (library rule), at nodes whose landing points stay
+    inside the disc: isolates the interpolation error of Section 3.1.2.  The
+    drift is the cellular flow, taken from central differences of its stream
+    function, so that the in-cell positions of landing points spread."""
+    prob = W.cell2d(nx=32 * m + 1, ny=16 * m + 1, D=2e-3, dt=5e-3, n_steps=4,
+                    radius=0.45, gh_q=4)
+    x, y = prob.axes[0].nodes, prob.axes[1].nodes
+    X, Y = np.meshgrid(x, y, indexing="ij")
+    n = 2
+    u0 = oracle.step(prob, n, f(X, Y))
+    a, w = hermgauss(4)
+    w = w / math.sqrt(math.pi)
+    S = math.sqrt(2 * prob.D) * math.sqrt(2 * prob.dt)
+    A, eps, om = prob.coef
+    t, hh = n * prob.dt, 1e-6
+    bx = -(_psi_cell(X, Y + hh, t, A, eps, om) - _psi_cell(X, Y - hh, t, A, eps, om)) / (2 * hh)
+    by = (_psi_cell(X + hh, Y, t, A, eps, om) - _psi_cell(X - hh, Y, t, A, eps, om)) / (2 * hh)
+    ex = np.zeros_like(X)
+    for i in range(4):
+        for k in range(4):
+            ex += w[i] * w[k] * f(X + bx * prob.dt + S * a[i], Y + by * prob.dt + S * a[k])
+    sel = np.hypot(X - 0.5, Y - 0.5) < 0.35
+    return math.sqrt(np.mean((u0 - ex)[sel] ** 2))
+
+
+@pytest.mark.parametrize("name", ["exp", "separable", "trig"])
+def test_second_order_in_space_one_step(name):
+    """Second order in dx (Section 3.1.4, Eq. (e_err)): the one-step error on
+    smooth data falls at least like h^2.  The tensor interpolant without mixed
+    (twist) terms has an h_x h_y f_xy error with zero cell mean, so the
+    constant oscillates; the gates are the overall order and a bound on
+    err / h^2."""
+    f = {"exp": lambda X, Y: np.exp(0.5 * X + 0.3 * Y),
+         "separable": lambda X, Y: np.exp(0.5 * X) + np.sin(3 * Y),
+         "trig": lambda X, Y: np.sin(3 * X) * np.cos(2 * Y) + 0.5 * X * Y}[name]
+    ms = [1, 2, 4, 8]
+    errs = [_one_step_error(m, f) for m in ms]
+    for m, e in zip(ms[1:], errs[1:]):
+        assert e * m * m <= 2.0 * errs[0], errs
+    assert math.log2(errs[0] / errs[-1]) / 3 >= 1.8, errs
+
+
+def test_stability_large_dt():
+    """Unconditional stability (Section 3.1.4): dt far beyond any CFL limit
+    keeps u bounded in 1D."""
+    prob = W.bm1d(dt=0.5, n_steps=40)
+    out = oracle.solve(prob, snaps=[0, 20, 40])
+    assert np.isfinite(out).all()
+    assert out.min() >= -1e-12 and out.max() <= 1 + 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Matrix form (Eq. (e34)-(e36)) and adjoint
+# ---------------------------------------------------------------------------
+
+
+def test_dense_row_reproduces_step():
+    prob = W.cell2d(nx=33, ny=17, n_steps=4, D=5e-3, radius=0.4)
+    rng = np.random.default_rng(11)
+    u = rng.uniform(size=prob.shape)
+    u0 = oracle.step(prob, 2, u)
+    g = oracle.slopes(prob, u)
+    vec = np.concatenate([u.reshape(1, -1), g.reshape(2, -1)])
+    act = oracle.active_nodes(prob)
+    for j in act[:: max(1, len(act) // 25)]:
+        row, em = oracle.assemble_row(prob, 2, int(j))
+        assert abs(em + np.sum(row * vec) - u0.reshape(-1)[j]) < 1e-13
+
+
+def _fd_grad(prob, k, h, rec, lam):
+    coef = list(prob.coef)
+    D = prob.D
+    vals = []
+    for sgn in (+1, -1):
+        c2, D2 = list(coef), D
+        if k < len(coef):
+            c2[k] = coef[k] + sgn * h * max(1.0, abs(coef[k]))
+        else:
+            D2 = D + sgn * h * D
+        u0 = oracle.solve(prob, snaps=[0], frozen_exits=rec, coef=c2, D=D2)[0]
+        vals.append(float(np.sum(lam * u0)))
+    step = h * (max(1.0, abs(coef[k])) if k < len(coef) else D)
+    return (vals[0] - vals[1]) / (2 * step)
+
+
+@pytest.mark.parametrize("which", ["cell", "const1d", "abc"])
+def test_adjoint_matches_central_differences(which):
+    """Frozen exit classification, central differences with h = 1e-6."""
+    if which == "cell":
+        prob = W.cell2d(nx=49, ny=25, n_steps=12, dt=2e-3, D=2e-3, A=1.1, eps=0.2, omega=5.0)
+    elif which == "const1d":
+        prob = W.Problem(axes=[W.uniform_axis(-1, 1, 41)], coef_kind="const", coef=(0.3,),
+                         D=0.2, region_kind="box", gh_q=5, dt=0.01, n_steps=15)
+    else:
+        prob = W.abc3d(n=11, n_steps=4, dt=0.05, D=3e-3)
+    _, rec = oracle.solve(prob, snaps=[0], record_exits=True)
+    rng = np.random.default_rng(12)
+    lam = rng.uniform(size=prob.shape)
+    grad, _ = oracle.adjoint(prob, lam, frozen_exits=rec)
+    for k in range(len(grad)):
+        fd = _fd_grad(prob, k, 1e-6, rec, lam)
+        scale = max(abs(fd), 1e-8 * np.abs(lam).sum())
+        assert abs(grad[k] - fd) <= 1e-5 * scale + 1e-9, (k, grad[k], fd)

@@ -1,0 +1,208 @@
+"""Seeded synthetic workloads for the backward Feynman-Kac exit-probability scheme.
+
+This module only *describes* problems: grids (node coordinate arrays), drift
+and diffusion parameters, exit regions, quadrature order, time step and step
+count.  It holds none of the scheme's arithmetic, so the CPU reference
+(``oracle/``) and the GPU library (``paper_2104_14561_amd``) can both take
+their inputs from here without sharing any computation.
+
+Problem statement (paper, Section 2, Eq. (e1)-(e2)): an SDE
+dX = b(t,X) dt + sigma(t,X) dW on a box, exit probability P(t,x).  All
+workloads here use an isotropic constant diffusion sigma = sqrt(2 D) I, as in
+dX = sqrt(2D) dW.
+
+Workloads (the paper's flows are analytic, so these stand in for them exactly;
+there is no dataset):
+
+* ``bm1d``        1D Brownian motion, D = 0.5, exit from (-1, 1), 201 nodes,
+                  T = 1, dt = 0.01, 16-node Gauss-Hermite rule (Section 4.1).
+* ``cell2d``      time-periodic cellular flow, stream function
+                  psi = A sin(pi (x + eps sin(omega t))) sin(pi y) on
+                  [0,2]x[0,1], 513x257 nodes, exit region = complement of the
+                  disc of radius 0.3 centred at (0.5, 0.5), 8x8 nodes
+                  (a cellular flow as in Section 4.2, with a disc target).
+* ``cell2d_batch64`` 64 seeded cellular-flow instances on uneven grids.
+* ``cell2d_adj``  ``cell2d`` with dt = 5e-4 and 2000 steps.
+* ``abc3d``       time-modulated ABC flow on a 129^3 grid, periodic in x, y,
+                  exit at |z| >= pi/2, 6x6x6 nodes; ``abc3d_batch8`` draws D.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+COEF_CONST = "const"            # p = (b_0, .., b_{d-1}); constant drift
+COEF_CELLULAR2D = "cellular2d"  # p = (A, eps, omega)
+COEF_ABC3D = "abc3d"            # p = (A, B, C, amp)
+
+REGION_BOX = "box"    # exit when a non-periodic coordinate leaves the open box
+REGION_BALL = "ball"  # exit also when |z - c| >= r
+
+N_DRIFT_PARAMS = {COEF_CONST: None, COEF_CELLULAR2D: 3, COEF_ABC3D: 4}
+
+
+@dataclasses.dataclass
+class Axis:
+    """One axis of the Cartesian mesh S = S^1 x ... x S^d (paper Section 3.1.2).
+
+    ``nodes`` are strictly increasing coordinates.  On a periodic axis the last
+    node is the image of the first one (x[n-1] = x[0] + period) and carries the
+    same value.
+    """
+
+    nodes: np.ndarray
+    periodic: bool = False
+
+    def __post_init__(self):
+        self.nodes = np.ascontiguousarray(self.nodes, dtype=np.float64)
+
+    @property
+    def n(self) -> int:
+        return int(self.nodes.shape[0])
+
+
+@dataclasses.dataclass
+class Problem:
+    """One instance of the exit-probability problem.
+
+    Attributes follow the paper's problem statement: the grid, the drift b
+    (``coef_kind`` + ``coef``), the diffusion D (sigma = sqrt(2D) I), the
+    exit region, the Gauss-Hermite order Q* (``gh_q`` nodes per Brownian
+    dimension), the time step ``dt``, the step count ``n_steps`` and the start
+    time ``t0`` (step n uses coefficients at t0 + n dt).
+    """
+
+    axes: List[Axis]
+    coef_kind: str
+    coef: Tuple[float, ...]
+    D: float
+    region_kind: str = REGION_BOX
+    center: Tuple[float, ...] = (0.0, 0.0, 0.0)
+    radius: float = 0.0
+    gh_q: int = 3
+    dt: float = 1e-2
+    n_steps: int = 1
+    t0: float = 0.0
+    name: str = ""
+
+    @property
+    def d(self) -> int:
+        return len(self.axes)
+
+    @property
+    def shape(self) -> Tuple[int, ...]:
+        return tuple(a.n for a in self.axes)
+
+    @property
+    def n_nodes(self) -> int:
+        return int(np.prod(self.shape))
+
+    def replace(self, **kw) -> "Problem":
+        return dataclasses.replace(self, **kw)
+
+
+def uniform_axis(lo: float, hi: float, n: int, periodic: bool = False) -> Axis:
+    return Axis(np.linspace(lo, hi, n), periodic)
+
+
+# ---------------------------------------------------------------------------
+# Named workloads
+# ---------------------------------------------------------------------------
+
+def bm1d(n: int = 201, dt: float = 0.01, n_steps: int = 100, gh_q: int = 16,
+         D: float = 0.5) -> Problem:
+    """1D Brownian motion dX = sqrt(2D) dW, exit from (-1, 1)."""
+    return Problem(axes=[uniform_axis(-1.0, 1.0, n)], coef_kind=COEF_CONST,
+                   coef=(0.0,), D=D, region_kind=REGION_BOX, gh_q=gh_q,
+                   dt=dt, n_steps=n_steps, name="bm1d")
+
+
+def cell2d(nx: int = 513, ny: int = 257, A: float = 1.0, eps: float = 0.1,
+           omega: float = 2.0 * math.pi, D: float = 1e-3, dt: float = 1e-3,
+           n_steps: int = 1000, gh_q: int = 8, radius: float = 0.3,
+           center=(0.5, 0.5), name: str = "cell2d") -> Problem:
+    """Cellular flow psi = A sin(pi(x + eps sin(omega t))) sin(pi y), disc target."""
+    return Problem(axes=[uniform_axis(0.0, 2.0, nx), uniform_axis(0.0, 1.0, ny)],
+                   coef_kind=COEF_CELLULAR2D, coef=(A, eps, omega), D=D,
+                   region_kind=REGION_BALL, center=tuple(center) + (0.0,),
+                   radius=radius, gh_q=gh_q, dt=dt, n_steps=n_steps, name=name)
+
+
+def cell2d_adj(**kw) -> Problem:
+    kw.setdefault("dt", 5e-4)
+    kw.setdefault("n_steps", 2000)
+    kw.setdefault("name", "cell2d_adj")
+    return cell2d(**kw)
+
+
+BATCH64_SEED = 210414561
+ABC8_SEED = 210414562
+
+
+def cell2d_batch(n_inst: int = 64, seed: int = BATCH64_SEED, n_steps: int = 1000,
+                 dt: float = 1e-3, gh_q: int = 8, max_m: int = 8) -> List[Problem]:
+    """Seeded cellular-flow instances on uneven grids (128m+1) x (64m+1).
+
+    Per instance, in order: m ~ U{1..max_m}, A ~ U[0.5, 1.5], eps ~ U[0, 0.3],
+    omega ~ U[pi, 4 pi], log10 D ~ U[-4, -2].
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_inst):
+        m = int(rng.integers(1, max_m + 1))
+        A = float(rng.uniform(0.5, 1.5))
+        eps = float(rng.uniform(0.0, 0.3))
+        omega = float(rng.uniform(math.pi, 4.0 * math.pi))
+        D = float(10.0 ** rng.uniform(-4.0, -2.0))
+        out.append(cell2d(nx=128 * m + 1, ny=64 * m + 1, A=A, eps=eps, omega=omega,
+                          D=D, dt=dt, n_steps=n_steps, gh_q=gh_q,
+                          name=f"cell2d_batch[{i}]"))
+    return out
+
+
+def abc3d(n: int = 129, D: float = 5e-4, A: float = 1.0, B: float = 0.8,
+          C: float = 0.6, amp: float = 0.1, dt: float = 2e-3, n_steps: int = 500,
+          gh_q: int = 6, name: str = "abc3d") -> Problem:
+    """ABC flow (A sin z + C cos y, B sin x + A cos z, C sin y + B cos x),
+    each amplitude times (1 + amp sin t); periodic in x, y; exit at |z| >= pi/2."""
+    two_pi = 2.0 * math.pi
+    return Problem(axes=[uniform_axis(0.0, two_pi, n, periodic=True),
+                         uniform_axis(0.0, two_pi, n, periodic=True),
+                         uniform_axis(-0.5 * math.pi, 0.5 * math.pi, n)],
+                   coef_kind=COEF_ABC3D, coef=(A, B, C, amp), D=D,
+                   region_kind=REGION_BOX, gh_q=gh_q, dt=dt, n_steps=n_steps,
+                   name=name)
+
+
+def abc3d_batch(n_inst: int = 8, seed: int = ABC8_SEED, **kw) -> List[Problem]:
+    """ABC instances with log10 D ~ U[-4, -3] (seeded)."""
+    rng = np.random.default_rng(seed)
+    Ds = [float(10.0 ** rng.uniform(-4.0, -3.0)) for _ in range(n_inst)]
+    return [abc3d(D=D, name=f"abc3d_batch[{i}]", **kw) for i, D in enumerate(Ds)]
+
+
+def paper2d(n1: int = 129, n2: int = 33, Pe: float = 10.0, eps: float = 0.15,
+            omega: float = 2.0 * math.pi / 10.0) -> dict:
+    """Parameters of the paper's own 2D example (Section 4.2), for reference."""
+    return dict(n1=n1, n2=n2, Pe=Pe, eps=eps, omega=omega, n=2, T=0.05)
+
+
+def random_field(shape: Sequence[int], seed: int, lo: float = 0.0,
+                 hi: float = 1.0) -> np.ndarray:
+    """Seeded uniform random field (test states for single-step checks)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=tuple(shape)).astype(np.float64)
+
+
+def by_name(name: str):
+    table = {
+        "bm1d": lambda: [bm1d()],
+        "cell2d": lambda: [cell2d()],
+        "cell2d_batch64": lambda: cell2d_batch(),
+        "cell2d_adj": lambda: [cell2d_adj()],
+        "abc3d_batch8": lambda: abc3d_batch(),
+    }
+    return table[name]()
