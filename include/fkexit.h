@@ -1,0 +1,218 @@
+/*
+ * fkexit.h -- C ABI of the MI355X (gfx950) library for the backward
+ * Feynman-Kac scheme of the exit-time probability (Yang, Zhang,
+ * del-Castillo-Negrete, Stoyanov: "A Feynman-Kac based numerical method for
+ * the exit time probability of a class of transport problems").
+ *
+ * Problem (paper Section 2, Eq. (e1)-(e2)): an SDE dX = b(t,X) dt + sigma dW
+ * on a Cartesian grid over a box, sigma = sqrt(2 D) I, an exit region, a
+ * tensor Gauss-Hermite rule of Q* nodes per dimension, a time step dt and a
+ * step count N.  Output: the fields u^n, n = N..0, of Scheme 1 (Section 3.1),
+ *   u^N = chi;  u^n_j = sum_q w_q * (z_jq exits ? 1 : I[u^{n+1}](z_jq)),
+ *   z_jq = x_j + b(t_n, x_j) dt + sigma sqrt(2 dt) a_q            (Eq. (e31))
+ * with I the tensor cubic Hermite interpolant whose nodal slopes are the PCHIP
+ * slopes of Eq. (e300) (value and first-derivative basis functions, Eq. (Lag11)),
+ * i.e. u^n = Q Psi^n F^n u^{n+1} of Eq. (e36) plus the exit mass.  For an
+ * autonomous problem u^n = P(T - t_n, x); in general u^n_j is the probability
+ * of exiting in (t_n, T] from x_j at t_n.
+ *
+ * Conventions shared by every call:
+ *  - All calls return fk_status; nothing is thrown across the ABI.  On error
+ *    fk_last_error() (thread-local) holds a message and outputs are undefined.
+ *  - "device" pointers are HIP device memory owned by the caller; "host"
+ *    pointers are host memory owned by the caller.  The library never
+ *    allocates device memory: every device buffer it uses lives in the caller's
+ *    workspace (fk_plan_set_workspace) or in the caller's outputs.
+ *  - stream is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *    asynchronously; outputs are valid after the stream has synchronised.
+ *  - Field layout: one field is the concatenation of the instances of a plan,
+ *    instance i at node offset off[i] (fk_plan_layout), each instance in
+ *    C order over its grid (axis d-1 fastest).  Element type is double for
+ *    FK_PREC_F64 and float for FK_PREC_F32.
+ *  - A plan is not thread-safe; distinct plans are.
+ */
+#ifndef FKEXIT_H
+#define FKEXIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FK_ABI_VERSION 1
+#define FK_MAX_DIM 3
+#define FK_MAX_THETA 8
+
+typedef enum {
+    FK_OK = 0,
+    FK_ERR_ARG = -1,          /* invalid argument */
+    FK_ERR_UNSUPPORTED = -2,  /* valid request outside what this build implements */
+    FK_ERR_WORKSPACE = -3,    /* workspace missing or too small */
+    FK_ERR_HIP = -4,          /* HIP runtime error */
+    FK_ERR_NONFINITE = -5,    /* non-finite parameter, state or result */
+    FK_ERR_STATE = -6         /* call out of order */
+} fk_status;
+
+/* Drift b(t, x); theta = (coef[0..np-1], D) are the differentiable parameters.
+ *  FK_COEF_CONST       b = (coef[0], .., coef[d-1]);                 np = d
+ *  FK_COEF_CELLULAR2D  stream function psi = A sin(pi (x + eps sin(omega t))) sin(pi y),
+ *                      b = (-dpsi/dy, dpsi/dx), coef = (A, eps, omega); np = 3
+ *                      (cellular flow of Section 4.2, the paper's sign convention)
+ *  FK_COEF_ABC3D       b = f(t) (A sin z + C cos y, B sin x + A cos z, C sin y + B cos x),
+ *                      f(t) = 1 + amp sin t, coef = (A, B, C, amp); np = 4 */
+enum { FK_COEF_CONST = 0, FK_COEF_CELLULAR2D = 1, FK_COEF_ABC3D = 2 };
+
+/* Exit region (paper Section 2: D is an open box; the benchmark spec's targets add
+ * a ball).  FK_REGION_BOX: a point exits when a coordinate on a non-periodic
+ * axis is <= the first or >= the last node.  FK_REGION_BALL: it also exits
+ * when |z - center|^2 >= radius^2 (evaluated as sum over axes of
+ * (z_i - c_i)*(z_i - c_i), axis 0 first, no fused multiply-add).  Nodes that
+ * lie in the exit region hold u = 1 for every n. */
+enum { FK_REGION_BOX = 0, FK_REGION_BALL = 1 };
+
+/* FK_PREC_F64: everything in FP64.
+ * FK_PREC_F32: landing points, exit tests, cells and in-cell positions in FP64
+ * (classification needs it); Hermite weights, gathers, accumulation and the
+ * stored fields in FP32. */
+enum { FK_PREC_F64 = 0, FK_PREC_F32 = 1 };
+
+/* FK_FORM_FUSED: matrix-free step (landing, weights and contraction in one
+ * kernel).  FK_FORM_ELL: the step operator A_n = Q Psi^n (Eq. (e36)) is
+ * assembled each step into ELL storage and then applied as a sparse
+ * matrix-vector product, the paper's own GPU formulation (Section 3.2.1). */
+enum { FK_FORM_FUSED = 0, FK_FORM_ELL = 1 };
+
+typedef struct {
+    int n;                /* number of nodes, >= 4 */
+    const double *nodes;  /* host: n strictly increasing coordinates (copied) */
+    int periodic;         /* nonzero: nodes[n-1] is the image of nodes[0] */
+} fk_axis;
+
+typedef struct {
+    int d;                 /* 1..3 */
+    fk_axis ax[FK_MAX_DIM];
+    int coef_kind;         /* FK_COEF_* */
+    double coef[7];        /* drift parameters, see FK_COEF_* */
+    double D;              /* diffusion coefficient, sigma = sqrt(2 D) I, D >= 0 */
+    int region_kind;       /* FK_REGION_* */
+    double center[FK_MAX_DIM];
+    double radius;
+    int gh_q;              /* Q*, Gauss-Hermite nodes per Brownian dimension */
+    double dt;             /* > 0 */
+    int n_steps;           /* N >= 1 */
+    double t0;             /* step n evaluates coefficients at t0 + n dt */
+} fk_problem;
+
+typedef struct {
+    int precision;   /* FK_PREC_* */
+    int form;        /* FK_FORM_* */
+    int use_graph;   /* nonzero: capture the N-step loop once and replay it */
+    int ckpt_every;  /* adjoint checkpoint interval K (0 = no adjoint storage) */
+    int block;       /* threads per workgroup, 0 = library default */
+    int reserved[3];
+} fk_options;
+
+typedef struct {
+    int n_inst;
+    int d;
+    int gh_q;
+    int n_quad;             /* Q = Q*^d */
+    int n_steps;
+    int n_theta;            /* theta per instance (drift params + D) */
+    int64_t n_nodes;        /* nodes of all instances */
+    int64_t n_active;       /* active nodes of all instances */
+    int64_t ell_width;      /* ELL row width (FK_FORM_ELL), else 0 */
+    size_t workspace_bytes;
+} fk_plan_info;
+
+typedef struct fk_plan fk_plan;
+
+/* Message of the last error on this thread ("" if none). */
+const char *fk_last_error(void);
+
+/* FK_ABI_VERSION of the loaded library. */
+int fk_version(void);
+
+/* Gauss-Hermite rule for the normalised Gaussian weight pi^{-1/2} e^{-xi^2}
+ * (paper Eq. (expec)-(quad)): q nodes ascending and weights summing to 1,
+ * symmetric about 0.  host outputs of length q; 1 <= q <= 64. */
+fk_status fk_gh_rule(int q, double *nodes, double *weights);
+
+/* Validates n_inst >= 1 problems and builds a plan (host work only).  All
+ * instances must share d, gh_q, dt, n_steps, t0, coef_kind and region_kind;
+ * grids and parameters may differ (batched, uneven grids).  Host arrays are
+ * copied.  opt may be NULL (defaults: F64, fused, no graph, no adjoint). */
+fk_status fk_plan_create(const fk_problem *probs, int n_inst, const fk_options *opt,
+                         fk_plan **out);
+
+void fk_plan_destroy(fk_plan *p);
+
+fk_status fk_plan_get_info(const fk_plan *p, fk_plan_info *info);
+
+/* host: node_offset[n_inst + 1] and active_count[n_inst]. */
+fk_status fk_plan_layout(const fk_plan *p, int64_t *node_offset, int64_t *active_count);
+
+/* Attaches caller-owned device memory of at least workspace_bytes bytes
+ * (256-byte aligned) and uploads the plan's tables into it; synchronises
+ * stream before returning.  The memory must stay valid until the plan is
+ * destroyed or another workspace is set. */
+fk_status fk_plan_set_workspace(fk_plan *p, void *dev_ptr, size_t bytes, void *stream);
+
+/* Backward pass from u^N = chi.  u_out (device) receives n_snap fields,
+ * u_out[s] = u^{snap_steps[s]} (0 <= snap_steps[s] <= N, host array).  A
+ * non-finite value in a produced field is reported by fk_check_flags. */
+fk_status fk_forward(fk_plan *p, const int *snap_steps, int n_snap, void *u_out,
+                     void *stream);
+
+/* Backward pass resumed from a caller state u_start = u^{start_step}
+ * (device, one field); snapshots with snap_steps[s] <= start_step. */
+fk_status fk_forward_from(fk_plan *p, const void *u_start, int start_step,
+                          const int *snap_steps, int n_snap, void *u_out, void *stream);
+
+/* One step u^{n+1} -> u^n from an arbitrary state (device fields).  Exit
+ * nodes of the result are 1, periodic images copy their originals. */
+fk_status fk_step(fk_plan *p, int n, const void *u_next, void *u_out, void *stream);
+
+/* Landing cells of step n for instance inst (device outputs):
+ * cells[Ja][Q][d] int32 (-1 where the landing point exits) and
+ * exit_flags[Ja][Q] uint8, active nodes in increasing linear index. */
+fk_status fk_export_cells(fk_plan *p, int inst, int n, int *cells,
+                          unsigned char *exit_flags, void *stream);
+
+/* Assembled step operator of step n (FK_FORM_ELL plans): for every active
+ * node (all instances, packed order) a row of ell_width (column, value) pairs,
+ * column = (d + 1) * node + field (field 0: u, field 1 + a: slope along a,
+ * node = packed node index), padding has value 0; exit_mass[row] = sum of
+ * w_q over exiting landing points.  Layout: cols[k * n_active + row]
+ * (column-major ELL), vals likewise, element type of the plan precision. */
+fk_status fk_export_ell(fk_plan *p, int n, int *cols, void *vals, void *exit_mass,
+                        void *stream);
+
+/* Reads and clears the device status flags (synchronises stream).
+ * *flags bit 0: a non-finite value was produced since the last check. */
+fk_status fk_check_flags(fk_plan *p, void *stream, int *flags);
+
+/* Adjoint of the whole pass with the exit classification held fixed.
+ * lam0 (device, one field) = dJ/du^0.  Outputs: grad (device, double,
+ * n_inst * FK_MAX_THETA, overwritten; entry [i * FK_MAX_THETA + k] is dJ/dtheta_k
+ * of instance i for k < n_theta, theta = (coef[0..np-1], D)) and, if lamN is
+ * not NULL, dJ/du^N (device, one field; zero on exit nodes).
+ * u is checkpointed every ckpt_every steps (fk_options) and recomputed. */
+fk_status fk_adjoint(fk_plan *p, const void *lam0, double *grad, void *lamN,
+                     void *stream);
+
+/* Measurement hook: runs one backward pass from chi without a graph on
+ * stream, with HIP events around every kernel launch, and returns the mean
+ * duration in milliseconds per launch of each pass kind in ms[4] (host):
+ * [0] slope pass, [1] fused step pass, [2] ELL assembly, [3] ELL product
+ * (0 for kinds the plan's form does not launch); counts[4] (host) receives the
+ * number of launches timed.  Synchronises stream. */
+fk_status fk_profile_pass(fk_plan *p, double *ms, int *counts, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FKEXIT_H */

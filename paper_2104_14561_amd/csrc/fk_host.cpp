@@ -1,0 +1,1033 @@
+// fk_host.cpp -- host runtime of the C ABI declared in include/fkexit.h:
+// validation, the library's own Gauss-Hermite rule, plan tables, workspace
+// carving, the backward step loop (optionally captured once in a HIP graph and
+// replayed), export hooks and the checkpointed adjoint schedule.
+#include "fkexit.h"
+#include "fk_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+// Node classification repeats the kernels' exit comparisons; no contraction.
+#pragma clang fp contract(off)
+
+namespace {
+
+thread_local std::string g_err;
+
+fk_status fail(fk_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define FK_HIP(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(FK_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
+    } while (0)
+
+constexpr int kBlock = 256;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int group_of(int qs)
+{
+    int g = 1;
+    while (g < qs) g <<= 1;
+    return g;
+}
+
+// ---------------------------------------------------------------------------
+// Gauss-Hermite rule: nodes are the zeros of the degree-q Hermite polynomial,
+// found as the eigenvalues of the symmetric tridiagonal Jacobi matrix
+// (zero diagonal, off-diagonal sqrt(k/2)) by Sturm-sequence bisection in long
+// double, then polished by Newton's method on the orthonormal recurrence
+//   p_{-1} = 0, p_0 = pi^{-1/4}, p_{k+1} = x sqrt(2/(k+1)) p_k - sqrt(k/(k+1)) p_{k-1},
+//   p_q'(x) = sqrt(2 q) p_{q-1}(x).
+// Weights are the Christoffel numbers 1 / sum_{k<q} p_k(x)^2 divided by
+// sqrt(pi), so they sum to one (density pi^{-1/2} e^{-xi^2}).
+// ---------------------------------------------------------------------------
+using ld = long double;
+
+int sturm_count(int q, ld x)
+{
+    // number of eigenvalues of the Jacobi matrix below x
+    int cnt = 0;
+    ld d = -x;                       // leading principal minors ratio
+    if (d < 0) cnt++;
+    for (int k = 1; k < q; ++k) {
+        ld b2 = (ld)k / 2.0L;
+        if (d == 0) d = 1e-300L;
+        d = -x - b2 / d;
+        if (d < 0) cnt++;
+    }
+    return cnt;
+}
+
+void hermite_orthonormal(int q, ld x, ld *pq, ld *pq1, ld *sumsq)
+{
+    ld pm1 = 0.0L, p = powl(acosl(-1.0L), -0.25L);
+    ld s = p * p;
+    for (int k = 0; k < q - 1; ++k) {
+        ld pn = x * sqrtl(2.0L / (k + 1)) * p - sqrtl((ld)k / (k + 1)) * pm1;
+        pm1 = p;
+        p = pn;
+        s += p * p;
+    }
+    // p = p_{q-1}, pm1 = p_{q-2}; one more step for p_q
+    ld pqv = x * sqrtl(2.0L / q) * p - sqrtl((ld)(q - 1) / q) * pm1;
+    *pq = pqv;
+    *pq1 = p;
+    *sumsq = s;
+}
+
+fk_status gh_rule_impl(int q, double *nodes, double *weights)
+{
+    if (q < 1 || q > 64) return fail(FK_ERR_ARG, "gh_q must be in [1, 64], got %d", q);
+    if (!nodes || !weights) return fail(FK_ERR_ARG, "null output");
+    std::vector<ld> x(q), w(q);
+    const ld bound = 2.0L * sqrtl((ld)q / 2.0L) + 1.0L;
+    for (int i = 0; i < q; ++i) {
+        ld lo = -bound, hi = bound;
+        for (int it = 0; it < 200 && hi - lo > 0; ++it) {
+            ld mid = 0.5L * (lo + hi);
+            if (mid == lo || mid == hi) break;
+            if (sturm_count(q, mid) > i) hi = mid; else lo = mid;
+        }
+        ld r = 0.5L * (lo + hi);
+        for (int it = 0; it < 3; ++it) {
+            ld pq, pq1, s;
+            hermite_orthonormal(q, r, &pq, &pq1, &s);
+            ld dp = sqrtl(2.0L * q) * pq1;
+            if (dp != 0) r -= pq / dp;
+        }
+        ld pq, pq1, s;
+        hermite_orthonormal(q, r, &pq, &pq1, &s);
+        x[i] = r;
+        w[i] = 1.0L / s;
+    }
+    const ld sqpi = sqrtl(acosl(-1.0L));
+    for (int i = 0; i < q; ++i) {
+        ld a = 0.5L * (x[i] - x[q - 1 - i]);
+        ld ww = 0.5L * (w[i] + w[q - 1 - i]) / sqpi;
+        nodes[i] = (double)a;
+        weights[i] = (double)ww;
+    }
+    if (q % 2 == 1) nodes[q / 2] = 0.0;
+    return FK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+struct Region {
+    size_t off = 0, bytes = 0;
+};
+
+}  // namespace
+
+struct fk_plan {
+    std::vector<fk_problem> probs;
+    fk_options opt{};
+    int n_inst = 0, d = 0, qs = 0, Q = 0, N = 0, n_theta = 0, G = 1;
+    double dt = 0, t0 = 0;
+    bool f32 = false;
+    // host tables
+    std::vector<fk::DevInst> inst;
+    std::vector<double> coords;
+    std::vector<int> active;
+    std::vector<unsigned char> cls;
+    std::vector<double> gh_a, gh_w;
+    std::vector<float> gh_wf;
+    std::vector<double> tfac;
+    std::vector<fk::WorkItem> slope_work, node_work, act_work, row_work;
+    int n_table_work = 0;
+    std::vector<int64_t> node_off, act_count;
+    long long n_nodes = 0, n_active = 0;
+    int ell_box[3] = {1, 1, 1};
+    int ell_width = 0;
+    // workspace
+    std::map<std::string, Region> reg;
+    size_t ws_bytes = 0;
+    unsigned char *ws = nullptr;
+    fk::PlanDev dev{};
+    // graph cache
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::string gkey;
+    int n_ckpt = 0;
+
+    void *at(const char *name) const { return ws + reg.at(name).off; }
+};
+
+namespace {
+
+size_t elt(const fk_plan *p) { return p->f32 ? 4 : 8; }
+int rec_stride(int d) { return d == 1 ? 2 : 4; }
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+fk_status validate(const fk_problem &pr, int i)
+{
+    if (pr.d < 1 || pr.d > 3) return fail(FK_ERR_ARG, "instance %d: d must be 1..3", i);
+    for (int a = 0; a < pr.d; ++a) {
+        const fk_axis &ax = pr.ax[a];
+        if (ax.n < 4) return fail(FK_ERR_ARG, "instance %d axis %d: n must be >= 4", i, a);
+        if (!ax.nodes) return fail(FK_ERR_ARG, "instance %d axis %d: null nodes", i, a);
+        for (int k = 0; k < ax.n; ++k)
+            if (!is_finite(ax.nodes[k]))
+                return fail(FK_ERR_NONFINITE, "instance %d axis %d: non-finite node", i, a);
+        for (int k = 1; k < ax.n; ++k)
+            if (!(ax.nodes[k] > ax.nodes[k - 1]))
+                return fail(FK_ERR_ARG, "instance %d axis %d: nodes not strictly increasing", i, a);
+    }
+    long long J = 1;
+    for (int a = 0; a < pr.d; ++a) J *= pr.ax[a].n;
+    if (J > (1LL << 29)) return fail(FK_ERR_UNSUPPORTED, "instance %d: more than 2^29 nodes", i);
+    if (pr.coef_kind < 0 || pr.coef_kind > 2) return fail(FK_ERR_ARG, "instance %d: coef_kind", i);
+    if (pr.coef_kind == FK_COEF_CELLULAR2D && pr.d != 2)
+        return fail(FK_ERR_ARG, "instance %d: cellular flow needs d = 2", i);
+    if (pr.coef_kind == FK_COEF_ABC3D && pr.d != 3)
+        return fail(FK_ERR_ARG, "instance %d: ABC flow needs d = 3", i);
+    for (int k = 0; k < 7; ++k)
+        if (!is_finite(pr.coef[k])) return fail(FK_ERR_NONFINITE, "instance %d: non-finite coef", i);
+    if (!is_finite(pr.D) || !is_finite(pr.dt) || !is_finite(pr.t0))
+        return fail(FK_ERR_NONFINITE, "instance %d: non-finite D, dt or t0", i);
+    if (pr.D < 0) return fail(FK_ERR_ARG, "instance %d: D must be >= 0", i);
+    if (!(pr.dt > 0)) return fail(FK_ERR_ARG, "instance %d: dt must be > 0", i);
+    if (pr.n_steps < 1) return fail(FK_ERR_ARG, "instance %d: n_steps must be >= 1", i);
+    if (pr.gh_q < 1 || pr.gh_q > 64) return fail(FK_ERR_ARG, "instance %d: gh_q in [1, 64]", i);
+    if (pr.region_kind != FK_REGION_BOX && pr.region_kind != FK_REGION_BALL)
+        return fail(FK_ERR_ARG, "instance %d: region_kind", i);
+    if (pr.region_kind == FK_REGION_BALL) {
+        if (!(pr.radius > 0) || !is_finite(pr.radius))
+            return fail(FK_ERR_ARG, "instance %d: ball radius must be > 0", i);
+        for (int a = 0; a < pr.d; ++a) {
+            if (pr.ax[a].periodic) return fail(FK_ERR_UNSUPPORTED, "instance %d: ball with periodic axis", i);
+            const double lo = pr.ax[a].nodes[0], hi = pr.ax[a].nodes[pr.ax[a].n - 1];
+            if (!(pr.center[a] - pr.radius >= lo && pr.center[a] + pr.radius <= hi))
+                return fail(FK_ERR_ARG, "instance %d: ball not inside the grid box", i);
+        }
+    }
+    return FK_OK;
+}
+
+bool axis_uniform(const fk_axis &ax)
+{
+    const double lo = ax.nodes[0], hi = ax.nodes[ax.n - 1];
+    const double h = (hi - lo) / (ax.n - 1);
+    for (int k = 0; k < ax.n; ++k)
+        if (std::fabs(ax.nodes[k] - (lo + k * h)) > 1e-9 * h) return false;
+    return true;
+}
+
+// x_k == k * step + lo exactly for k < n-1 and x_{n-1} == hi, with the same
+// operations as the kernels' coordinate formula (no contraction).
+bool axis_affine(const fk_axis &ax, double *step_out)
+{
+    const double lo = ax.nodes[0], hi = ax.nodes[ax.n - 1];
+    const double step = (hi - lo) / (double)(ax.n - 1);
+    *step_out = step;
+    for (int k = 0; k < ax.n - 1; ++k) {
+        const double xk = (double)k * step + lo;
+        if (xk != ax.nodes[k]) return false;
+    }
+    return true;
+}
+
+// Largest |b_a| the drift can take (bounds the reach of landing points).
+double drift_bound(const fk_problem &pr, int a)
+{
+    const double *c = pr.coef;
+    if (pr.coef_kind == FK_COEF_CONST) return std::fabs(c[a]);
+    if (pr.coef_kind == FK_COEF_CELLULAR2D) return std::fabs(c[0]) * M_PI;
+    const double f = 1.0 + std::fabs(c[3]);
+    if (a == 0) return (std::fabs(c[0]) + std::fabs(c[2])) * f;
+    if (a == 1) return (std::fabs(c[1]) + std::fabs(c[0])) * f;
+    return (std::fabs(c[2]) + std::fabs(c[1])) * f;
+}
+
+// Exit test of a point, the same comparisons as the kernels.
+bool exit_point(const fk_problem &pr, const double *z)
+{
+    for (int a = 0; a < pr.d; ++a) {
+        if (pr.ax[a].periodic) continue;
+        if (z[a] <= pr.ax[a].nodes[0] || z[a] >= pr.ax[a].nodes[pr.ax[a].n - 1]) return true;
+    }
+    if (pr.region_kind == FK_REGION_BALL) {
+        double s = 0.0;
+        for (int a = 0; a < pr.d; ++a) {
+            const double t = z[a] - pr.center[a];
+            const double t2 = t * t;
+            s = s + t2;
+        }
+        if (s >= pr.radius * pr.radius) return true;
+    }
+    return false;
+}
+
+void add_region(fk_plan *p, const char *name, size_t bytes)
+{
+    Region r;
+    r.off = p->ws_bytes;
+    r.bytes = bytes;
+    p->reg[name] = r;
+    p->ws_bytes = align_up(p->ws_bytes + std::max<size_t>(bytes, 1));
+}
+
+void build_work(std::vector<fk::WorkItem> &out, int inst, int count, int chunk, int first = 0,
+                int kind = 0)
+{
+    for (int f = 0; f < count; f += chunk) {
+        fk::WorkItem w;
+        w.inst = inst;
+        w.first = first + f;
+        w.count = std::min(chunk, count - f);
+        w.kind = kind;
+        out.push_back(w);
+    }
+}
+
+int grid_for(size_t n_work)
+{
+    // persistent grid: enough workgroups for the work list, at most 8 per CU,
+    // a multiple of the 8 XCDs
+    size_t g = std::min<size_t>(n_work, 256 * 8);
+    if (g >= 8) g = (g + 7) / 8 * 8;
+    return (int)std::max<size_t>(g, 1);
+}
+
+fk_status build_plan(fk_plan *p)
+{
+    const fk_problem &p0 = p->probs[0];
+    p->d = p0.d;
+    p->qs = p0.gh_q;
+    p->N = p0.n_steps;
+    p->dt = p0.dt;
+    p->t0 = p0.t0;
+    p->Q = 1;
+    for (int a = 0; a < p->d; ++a) p->Q *= p->qs;
+    p->G = std::min(64, group_of(p->Q));
+    p->n_theta = (p0.coef_kind == FK_COEF_CONST) ? p->d + 1 : (p0.coef_kind == FK_COEF_CELLULAR2D ? 4 : 5);
+    if ((long long)p->Q > 256) return fail(FK_ERR_UNSUPPORTED, "Q = gh_q^d above 256");
+
+    p->gh_a.assign(p->qs, 0.0);
+    std::vector<double> w1(p->qs);
+    fk_status st = gh_rule_impl(p->qs, p->gh_a.data(), w1.data());
+    if (st != FK_OK) return st;
+    p->gh_w.assign(p->Q, 0.0);
+    p->gh_wf.assign(p->Q, 0.0f);
+    for (int q = 0; q < p->Q; ++q) {
+        int qi[3], r = q;
+        for (int a = p->d - 1; a >= 0; --a) { qi[a] = r % p->qs; r /= p->qs; }
+        double w = w1[qi[0]];
+        for (int a = 1; a < p->d; ++a) w = w * w1[qi[a]];
+        p->gh_w[q] = w;
+        p->gh_wf[q] = (float)w;
+    }
+    double amax = 0.0;
+    for (double a : p->gh_a) amax = std::max(amax, std::fabs(a));
+
+    const int npb = kBlock / p->G;
+    std::vector<fk::WorkItem> tables, runs;
+    p->node_off.assign(p->n_inst + 1, 0);
+    p->act_count.assign(p->n_inst, 0);
+    long long coord_total = 0;
+    int box[3] = {1, 1, 1};
+    for (int i = 0; i < p->n_inst; ++i) {
+        const fk_problem &pr = p->probs[i];
+        fk::DevInst I;
+        std::memset(&I, 0, sizeof(I));
+        I.d = pr.d;
+        long long J = 1;
+        for (int a = 0; a < pr.d; ++a) J *= pr.ax[a].n;
+        long long stride = 1;
+        for (int a = pr.d - 1; a >= 0; --a) {
+            I.stride[a] = stride;
+            stride *= pr.ax[a].n;
+        }
+        for (int a = 0; a < 3; ++a) {
+            if (a < pr.d) {
+                const fk_axis &ax = pr.ax[a];
+                I.n[a] = ax.n;
+                I.periodic[a] = ax.periodic ? 1 : 0;
+                I.uniform[a] = axis_uniform(ax) ? 1 : 0;
+                double step = 0.0;
+                I.affine[a] = axis_affine(ax, &step) ? 1 : 0;
+                I.step[a] = step;
+                I.coord_off[a] = coord_total;
+                I.lo[a] = ax.nodes[0];
+                I.hi[a] = ax.nodes[ax.n - 1];
+                I.period[a] = ax.nodes[ax.n - 1] - ax.nodes[0];
+                I.inv_h[a] = I.affine[a] ? 1.0 / step
+                                         : (ax.n - 1) / (ax.nodes[ax.n - 1] - ax.nodes[0]);
+                for (int k = 0; k < ax.n; ++k) p->coords.push_back(ax.nodes[k]);
+                coord_total += ax.n;
+            } else {
+                I.n[a] = 1;
+            }
+        }
+        I.coef_kind = pr.coef_kind;
+        I.region_kind = pr.region_kind;
+        for (int k = 0; k < 7; ++k) I.coef[k] = pr.coef[k];
+        I.D = pr.D;
+        for (int a = 0; a < 3; ++a) I.center[a] = pr.center[a];
+        I.r2 = pr.radius * pr.radius;
+        const double sq = std::sqrt(2.0 * pr.dt);
+        I.S = std::sqrt(2.0 * pr.D) * sq;
+        I.dSdD = pr.D > 0 ? I.S / (2.0 * pr.D) : 0.0;
+        I.node_off = p->n_nodes;
+        I.act_off = p->n_active;
+
+        // node classes: 0 active, 1 exit, 2 image of active, 3 image of exit
+        std::vector<unsigned char> c(J);
+        int idx[3];
+        double x[3];
+        for (long long j = 0; j < J; ++j) {
+            long long r = j;
+            for (int a = pr.d - 1; a >= 0; --a) { idx[a] = (int)(r % pr.ax[a].n); r /= pr.ax[a].n; }
+            bool image = false;
+            for (int a = 0; a < pr.d; ++a)
+                if (pr.ax[a].periodic && idx[a] == pr.ax[a].n - 1) { image = true; idx[a] = 0; }
+            for (int a = 0; a < pr.d; ++a) x[a] = pr.ax[a].nodes[idx[a]];
+            const bool ex = exit_point(pr, x);
+            c[j] = (unsigned char)((image ? 2 : 0) | (ex ? 1 : 0));
+        }
+        int na = 0;
+        int amin[3] = {1 << 30, 1 << 30, 1 << 30}, amax_i[3] = {-1, -1, -1};
+        for (long long j = 0; j < J; ++j)
+            if (c[j] == 0) {
+                p->active.push_back((int)j);
+                na++;
+                long long r = j;
+                for (int a = pr.d - 1; a >= 0; --a) {
+                    const int ia = (int)(r % pr.ax[a].n);
+                    r /= pr.ax[a].n;
+                    amin[a] = std::min(amin[a], ia);
+                    amax_i[a] = std::max(amax_i[a], ia);
+                }
+            }
+        // trig tables of the drift arguments, one entry per axis coordinate
+        if (pr.coef_kind != FK_COEF_CONST)
+            for (int a = 0; a < pr.d; ++a)
+                build_work(tables, i, pr.ax[a].n, kBlock, 0, 1 + a);
+        // slope records are needed only where landing cells of active nodes can
+        // reach: the active bounding box widened by the reach plus the corner
+        int blo[3] = {0, 0, 0}, bhi[3] = {0, 0, 0};
+        for (int a = 0; a < pr.d; ++a) {
+            double hmin = 1e300;
+            for (int k = 1; k < pr.ax[a].n; ++k)
+                hmin = std::min(hmin, pr.ax[a].nodes[k] - pr.ax[a].nodes[k - 1]);
+            const double reach = drift_bound(pr, a) * pr.dt + I.S * amax;
+            const double cells = std::ceil(reach / hmin) + 2.0;
+            const int dil = cells > 1e9 ? (1 << 30) : (int)cells;
+            if (pr.ax[a].periodic || na == 0) {
+                blo[a] = 0;
+                bhi[a] = pr.ax[a].n - 1;
+            } else {
+                blo[a] = std::max(0, amin[a] - dil);
+                bhi[a] = (int)std::min<long long>(pr.ax[a].n - 1, (long long)amax_i[a] + dil);
+            }
+        }
+        if (na > 0) {
+            const int dl = pr.d - 1;
+            long long rows = 1;
+            for (int a = 0; a < dl; ++a) rows *= (bhi[a] - blo[a] + 1);
+            for (long long r = 0; r < rows; ++r) {
+                long long rr = r, base = 0;
+                for (int a = dl - 1; a >= 0; --a) {
+                    const int len = bhi[a] - blo[a] + 1;
+                    const int ia = blo[a] + (int)(rr % len);
+                    rr /= len;
+                    base += (long long)ia * I.stride[a];
+                }
+                build_work(runs, i, bhi[dl] - blo[dl] + 1, kBlock, (int)(base + blo[dl]), 0);
+            }
+        }
+        p->cls.insert(p->cls.end(), c.begin(), c.end());
+        I.n_act = na;
+        p->inst.push_back(I);
+        p->node_off[i] = p->n_nodes;
+        p->act_count[i] = na;
+        build_work(p->node_work, i, (int)J, kBlock);
+        build_work(p->act_work, i, na, npb);
+        build_work(p->row_work, i, na, kBlock);
+        p->n_nodes += J;
+        p->n_active += na;
+
+        // ELL row box: the landing points of one node spread over 2 S max|a|
+        for (int a = 0; a < pr.d; ++a) {
+            double hmin = 1e300;
+            for (int k = 1; k < pr.ax[a].n; ++k)
+                hmin = std::min(hmin, pr.ax[a].nodes[k] - pr.ax[a].nodes[k - 1]);
+            int L = (int)std::floor(2.0 * I.S * amax / hmin) + 3;
+            L = std::min(L, pr.ax[a].n);
+            box[a] = std::max(box[a], L);
+        }
+    }
+    p->node_off[p->n_inst] = p->n_nodes;
+    p->slope_work = tables;
+    p->slope_work.insert(p->slope_work.end(), runs.begin(), runs.end());
+    p->n_table_work = (int)tables.size();
+
+    // per-(step, instance) time factors
+    p->tfac.assign((size_t)p->N * p->n_inst * fk::kTimeFactors, 0.0);
+    for (int n = 0; n < p->N; ++n) {
+        const double t = p->t0 + (double)n * p->dt;
+        for (int i = 0; i < p->n_inst; ++i) {
+            const fk_problem &pr = p->probs[i];
+            double *tf = &p->tfac[((size_t)n * p->n_inst + i) * fk::kTimeFactors];
+            if (pr.coef_kind == FK_COEF_CELLULAR2D) {
+                tf[0] = pr.coef[1] * std::sin(pr.coef[2] * t);
+                tf[1] = std::sin(pr.coef[2] * t);
+                tf[2] = std::cos(pr.coef[2] * t);
+                tf[3] = t;
+            } else if (pr.coef_kind == FK_COEF_ABC3D) {
+                tf[0] = 1.0 + pr.coef[3] * std::sin(t);
+                tf[1] = std::sin(t);
+                tf[3] = t;
+            } else {
+                tf[3] = t;
+            }
+        }
+    }
+
+    if (p->opt.form == FK_FORM_ELL) {
+        for (int a = 0; a < p->d; ++a)
+            for (int i = 0; i < p->n_inst; ++i)
+                if (p->probs[i].ax[a].periodic)
+                    return fail(FK_ERR_UNSUPPORTED, "ELL form needs non-periodic axes");
+        long long W = p->d + 1;
+        for (int a = 0; a < p->d; ++a) { p->ell_box[a] = box[a]; W *= box[a]; }
+        if (W * (long long)(kBlock / p->G) * (p->f32 ? 4 : 8) > 64 * 1024)
+            return fail(FK_ERR_UNSUPPORTED, "ELL row box too large for LDS (%lld entries)", W);
+        p->ell_width = (int)W;
+    }
+
+    // workspace layout
+    p->ws_bytes = 0;
+    add_region(p, "inst", sizeof(fk::DevInst) * p->inst.size());
+    add_region(p, "coords", sizeof(double) * p->coords.size());
+    add_region(p, "active", sizeof(int) * std::max<size_t>(p->active.size(), 1));
+    add_region(p, "cls", p->cls.size());
+    add_region(p, "gh_a", sizeof(double) * p->gh_a.size());
+    add_region(p, "gh_w", sizeof(double) * p->gh_w.size());
+    add_region(p, "gh_wf", sizeof(float) * p->gh_wf.size());
+    add_region(p, "tfac", sizeof(double) * p->tfac.size());
+    add_region(p, "trig", sizeof(double) * 2 * std::max<size_t>(p->coords.size(), 1));
+    add_region(p, "slope_work", sizeof(fk::WorkItem) * std::max<size_t>(p->slope_work.size(), 1));
+    add_region(p, "node_work", sizeof(fk::WorkItem) * std::max<size_t>(p->node_work.size(), 1));
+    add_region(p, "act_work", sizeof(fk::WorkItem) * std::max<size_t>(p->act_work.size(), 1));
+    add_region(p, "row_work", sizeof(fk::WorkItem) * std::max<size_t>(p->row_work.size(), 1));
+    add_region(p, "flags", 64);
+    const size_t fb = elt(p) * (size_t)p->n_nodes;
+    add_region(p, "uA", fb);
+    add_region(p, "uB", fb);
+    add_region(p, "packed", fb * rec_stride(p->d));
+    if (p->opt.form == FK_FORM_ELL) {
+        add_region(p, "ell_cols", sizeof(int) * (size_t)p->n_active * p->ell_width);
+        add_region(p, "ell_vals", elt(p) * (size_t)p->n_active * p->ell_width);
+        add_region(p, "ell_em", elt(p) * (size_t)std::max<long long>(p->n_active, 1));
+    }
+    if (p->opt.ckpt_every > 0) {
+        const int K = p->opt.ckpt_every;
+        p->n_ckpt = (p->N - 1) / K + 2;
+        add_region(p, "lamA", fb);
+        add_region(p, "lamB", fb);
+        add_region(p, "mu", fb * rec_stride(p->d));
+        add_region(p, "grad", sizeof(double) * fk::kThetaSlots * p->n_inst);
+        add_region(p, "ckpt", fb * p->n_ckpt);
+        add_region(p, "seg", fb * std::min(K, p->N));
+    }
+    return FK_OK;
+}
+
+void fill_dev(fk_plan *p)
+{
+    fk::PlanDev &D = p->dev;
+    std::memset(&D, 0, sizeof(D));
+    D.inst = (const fk::DevInst *)p->at("inst");
+    D.coords = (const double *)p->at("coords");
+    D.active = (const int *)p->at("active");
+    D.chi = (const unsigned char *)p->at("cls");
+    D.gh_a = (const double *)p->at("gh_a");
+    D.gh_w = (const double *)p->at("gh_w");
+    D.gh_wf = (const float *)p->at("gh_wf");
+    D.tfac = (const double *)p->at("tfac");
+    D.trig = (double2 *)p->at("trig");
+    D.slope_work = (const fk::WorkItem *)p->at("slope_work");
+    D.node_work = (const fk::WorkItem *)p->at("node_work");
+    D.act_work = (const fk::WorkItem *)p->at("act_work");
+    D.row_work = (const fk::WorkItem *)p->at("row_work");
+    D.flags = (int *)p->at("flags");
+    D.n_inst = p->n_inst;
+    D.n_slope_work = (int)p->slope_work.size();
+    D.n_table_work = p->n_table_work;
+    D.n_node_work = (int)p->node_work.size();
+    D.n_act_work = (int)p->act_work.size();
+    D.n_row_work = (int)p->row_work.size();
+    D.d = p->d;
+    D.qs = p->qs;
+    D.n_quad = p->Q;
+    D.n_steps = p->N;
+    D.block = kBlock;
+    D.group = p->G;
+    D.slope_grid = grid_for(p->slope_work.size());
+    D.node_grid = grid_for(p->node_work.size());
+    D.act_grid = grid_for(p->act_work.size());
+    D.row_grid = grid_for(p->row_work.size());
+    D.dt = p->dt;
+    D.t0 = p->t0;
+    D.n_nodes = p->n_nodes;
+    D.n_active = p->n_active;
+    D.ell_width = p->ell_width;
+    for (int a = 0; a < 3; ++a) D.ell_box[a] = p->ell_box[a];
+    D.ell_grid = D.act_grid;
+}
+
+fk_status need_ws(const fk_plan *p)
+{
+    if (!p) return fail(FK_ERR_ARG, "null plan");
+    if (!p->ws) return fail(FK_ERR_STATE, "no workspace set (fk_plan_set_workspace)");
+    return FK_OK;
+}
+
+#define FK_TRY(expr)                         \
+    do {                                     \
+        fk_status s_ = (expr);               \
+        if (s_ != FK_OK) return s_;          \
+    } while (0)
+
+#define FK_LAUNCH(expr)                                                               \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(FK_ERR_HIP, "launch failed: %s", hipGetErrorString(e_));     \
+    } while (0)
+
+// One step u_next -> u_out (u_out must hold 1 on exit nodes already).
+fk_status enqueue_step(fk_plan *p, int n, const void *u_next, void *u_out, hipStream_t s)
+{
+    void *packed = p->at("packed");
+    FK_LAUNCH(fk::launch_slopes(p->dev, p->f32, n, u_next, packed, s));
+    if (p->opt.form == FK_FORM_ELL) {
+        int *cols = (int *)p->at("ell_cols");
+        void *vals = p->at("ell_vals"), *em = p->at("ell_em");
+        FK_LAUNCH(fk::launch_assemble_ell(p->dev, p->f32, n, cols, vals, em, s));
+        FK_LAUNCH(fk::launch_ell_apply(p->dev, p->f32, cols, vals, em, packed, u_out, s));
+    } else {
+        FK_LAUNCH(fk::launch_step_fused(p->dev, p->f32, n, packed, u_out, s));
+    }
+    return FK_OK;
+}
+
+// Backward loop from u_start (a field at step `start`) down to step 0,
+// copying snapshots.  ckpt: optional checkpoint store (adjoint).
+fk_status enqueue_pass(fk_plan *p, const void *u_start, int start, const int *snaps, int n_snap,
+                       void *u_out, hipStream_t s, bool store_ckpt)
+{
+    const size_t fb = elt(p) * (size_t)p->n_nodes;
+    void *ua = p->at("uA"), *ub = p->at("uB");
+    FK_LAUNCH(fk::launch_clear_flags(p->dev, s));
+    // both buffers hold 1 on exit nodes (and chi elsewhere)
+    FK_LAUNCH(fk::launch_init_field(p->dev, p->f32, ub, s));
+    if (u_start) {
+        FK_HIP(hipMemcpyAsync(ua, u_start, fb, hipMemcpyDeviceToDevice, s));
+    } else {
+        FK_LAUNCH(fk::launch_init_field(p->dev, p->f32, ua, s));
+    }
+    auto snap_copy = [&](int n, const void *u) -> fk_status {
+        for (int k = 0; k < n_snap; ++k)
+            if (snaps[k] == n)
+                FK_HIP(hipMemcpyAsync((unsigned char *)u_out + (size_t)k * fb, u, fb,
+                                      hipMemcpyDeviceToDevice, s));
+        return FK_OK;
+    };
+    auto ckpt_copy = [&](int n, const void *u) -> fk_status {
+        if (!store_ckpt) return FK_OK;
+        const int K = p->opt.ckpt_every;
+        int slot = -1;
+        if (n == p->N) slot = p->n_ckpt - 1;
+        else if (n % K == 0) slot = n / K;
+        if (slot >= 0)
+            FK_HIP(hipMemcpyAsync((unsigned char *)p->at("ckpt") + (size_t)slot * fb, u, fb,
+                                  hipMemcpyDeviceToDevice, s));
+        return FK_OK;
+    };
+    FK_TRY(snap_copy(start, ua));
+    FK_TRY(ckpt_copy(start, ua));
+    void *cur = ua, *nxt = ub;
+    for (int n = start - 1; n >= 0; --n) {
+        FK_TRY(enqueue_step(p, n, cur, nxt, s));
+        std::swap(cur, nxt);
+        FK_TRY(snap_copy(n, cur));
+        FK_TRY(ckpt_copy(n, cur));
+    }
+    return FK_OK;
+}
+
+fk_status run_pass(fk_plan *p, const void *u_start, int start, const int *snaps, int n_snap,
+                   void *u_out, hipStream_t s)
+{
+    if (!p->opt.use_graph) return enqueue_pass(p, u_start, start, snaps, n_snap, u_out, s, false);
+    char key[256];
+    snprintf(key, sizeof(key), "%p|%d|%p|", u_start, start, u_out);
+    std::string k = key;
+    for (int i = 0; i < n_snap; ++i) k += std::to_string(snaps[i]) + ",";
+    if (!p->gexec || k != p->gkey) {
+        if (p->gexec) {
+            (void)hipGraphExecDestroy(p->gexec);
+            p->gexec = nullptr;
+        }
+        if (!p->cap_stream) FK_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        FK_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+        fk_status st = enqueue_pass(p, u_start, start, snaps, n_snap, u_out, p->cap_stream, false);
+        hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
+        if (st != FK_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return fail(FK_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(FK_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
+        p->gkey = k;
+    }
+    FK_HIP(hipGraphLaunch(p->gexec, s));
+    return FK_OK;
+}
+
+fk_status check_snaps(const fk_plan *p, const int *snaps, int n_snap, int start, const void *u_out)
+{
+    if (n_snap < 0) return fail(FK_ERR_ARG, "n_snap < 0");
+    if (n_snap > 0 && (!snaps || !u_out)) return fail(FK_ERR_ARG, "null snapshot list or output");
+    for (int k = 0; k < n_snap; ++k)
+        if (snaps[k] < 0 || snaps[k] > start)
+            return fail(FK_ERR_ARG, "snapshot step %d outside [0, %d]", snaps[k], start);
+    (void)p;
+    return FK_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *fk_last_error(void) { return g_err.c_str(); }
+
+int fk_version(void) { return FK_ABI_VERSION; }
+
+fk_status fk_gh_rule(int q, double *nodes, double *weights)
+{
+    return gh_rule_impl(q, nodes, weights);
+}
+
+fk_status fk_plan_create(const fk_problem *probs, int n_inst, const fk_options *opt, fk_plan **out)
+{
+    g_err.clear();
+    if (!out) return fail(FK_ERR_ARG, "null output plan pointer");
+    *out = nullptr;
+    if (!probs || n_inst < 1) return fail(FK_ERR_ARG, "need n_inst >= 1 problems");
+    fk_options o{};
+    if (opt) o = *opt;
+    if (o.precision != FK_PREC_F64 && o.precision != FK_PREC_F32)
+        return fail(FK_ERR_ARG, "precision must be FK_PREC_F64 or FK_PREC_F32");
+    if (o.form != FK_FORM_FUSED && o.form != FK_FORM_ELL)
+        return fail(FK_ERR_ARG, "form must be FK_FORM_FUSED or FK_FORM_ELL");
+    if (o.ckpt_every < 0) return fail(FK_ERR_ARG, "ckpt_every must be >= 0");
+    if (o.block != 0 && o.block != kBlock) return fail(FK_ERR_UNSUPPORTED, "block must be 0 or 256");
+    for (int i = 0; i < n_inst; ++i) FK_TRY(validate(probs[i], i));
+    const fk_problem &a = probs[0];
+    for (int i = 1; i < n_inst; ++i) {
+        const fk_problem &b = probs[i];
+        if (b.d != a.d || b.gh_q != a.gh_q || b.dt != a.dt || b.n_steps != a.n_steps ||
+            b.t0 != a.t0 || b.coef_kind != a.coef_kind || b.region_kind != a.region_kind)
+            return fail(FK_ERR_ARG, "instance %d: d, gh_q, dt, n_steps, t0, coef_kind and "
+                        "region_kind must match instance 0", i);
+    }
+    if (o.ckpt_every > 0)
+        for (int i = 0; i < n_inst; ++i)
+            if (!(probs[i].D > 0)) return fail(FK_ERR_ARG, "adjoint needs D > 0 (instance %d)", i);
+    fk_plan *p = new (std::nothrow) fk_plan();
+    if (!p) return fail(FK_ERR_ARG, "out of host memory");
+    p->opt = o;
+    p->f32 = o.precision == FK_PREC_F32;
+    p->n_inst = n_inst;
+    p->probs.assign(probs, probs + n_inst);
+    for (auto &pr : p->probs)
+        for (int ax = 0; ax < 3; ++ax) pr.ax[ax].nodes = nullptr;   // copied into coords
+    // build from the caller's arrays (still valid during this call)
+    std::vector<fk_problem> tmp(probs, probs + n_inst);
+    std::swap(p->probs, tmp);
+    fk_status st = build_plan(p);
+    std::swap(p->probs, tmp);
+    if (st != FK_OK) {
+        delete p;
+        return st;
+    }
+    *out = p;
+    return FK_OK;
+}
+
+void fk_plan_destroy(fk_plan *p)
+{
+    if (!p) return;
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    delete p;
+}
+
+fk_status fk_plan_get_info(const fk_plan *p, fk_plan_info *info)
+{
+    if (!p || !info) return fail(FK_ERR_ARG, "null argument");
+    info->n_inst = p->n_inst;
+    info->d = p->d;
+    info->gh_q = p->qs;
+    info->n_quad = p->Q;
+    info->n_steps = p->N;
+    info->n_theta = p->n_theta;
+    info->n_nodes = p->n_nodes;
+    info->n_active = p->n_active;
+    info->ell_width = p->ell_width;
+    info->workspace_bytes = p->ws_bytes;
+    return FK_OK;
+}
+
+fk_status fk_plan_layout(const fk_plan *p, int64_t *node_offset, int64_t *active_count)
+{
+    if (!p) return fail(FK_ERR_ARG, "null plan");
+    if (node_offset)
+        for (int i = 0; i <= p->n_inst; ++i) node_offset[i] = p->node_off[i];
+    if (active_count)
+        for (int i = 0; i < p->n_inst; ++i) active_count[i] = p->act_count[i];
+    return FK_OK;
+}
+
+fk_status fk_plan_set_workspace(fk_plan *p, void *dev_ptr, size_t bytes, void *stream)
+{
+    if (!p) return fail(FK_ERR_ARG, "null plan");
+    if (!dev_ptr) return fail(FK_ERR_ARG, "null workspace");
+    if (((uintptr_t)dev_ptr) % kAlign) return fail(FK_ERR_ARG, "workspace must be 256-byte aligned");
+    if (bytes < p->ws_bytes)
+        return fail(FK_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", bytes, p->ws_bytes);
+    hipStream_t s = (hipStream_t)stream;
+    if (p->gexec) {
+        (void)hipGraphExecDestroy(p->gexec);
+        p->gexec = nullptr;
+        p->gkey.clear();
+    }
+    p->ws = (unsigned char *)dev_ptr;
+    fill_dev(p);
+    auto up = [&](const char *name, const void *src, size_t n) -> fk_status {
+        if (n) FK_HIP(hipMemcpyAsync(p->at(name), src, n, hipMemcpyHostToDevice, s));
+        return FK_OK;
+    };
+    FK_TRY(up("inst", p->inst.data(), sizeof(fk::DevInst) * p->inst.size()));
+    FK_TRY(up("coords", p->coords.data(), sizeof(double) * p->coords.size()));
+    FK_TRY(up("active", p->active.data(), sizeof(int) * p->active.size()));
+    FK_TRY(up("cls", p->cls.data(), p->cls.size()));
+    FK_TRY(up("gh_a", p->gh_a.data(), sizeof(double) * p->gh_a.size()));
+    FK_TRY(up("gh_w", p->gh_w.data(), sizeof(double) * p->gh_w.size()));
+    FK_TRY(up("gh_wf", p->gh_wf.data(), sizeof(float) * p->gh_wf.size()));
+    FK_TRY(up("tfac", p->tfac.data(), sizeof(double) * p->tfac.size()));
+    FK_TRY(up("slope_work", p->slope_work.data(), sizeof(fk::WorkItem) * p->slope_work.size()));
+    FK_TRY(up("node_work", p->node_work.data(), sizeof(fk::WorkItem) * p->node_work.size()));
+    FK_TRY(up("act_work", p->act_work.data(), sizeof(fk::WorkItem) * p->act_work.size()));
+    FK_TRY(up("row_work", p->row_work.data(), sizeof(fk::WorkItem) * p->row_work.size()));
+    FK_LAUNCH(fk::launch_clear_flags(p->dev, s));
+    FK_HIP(hipStreamSynchronize(s));
+    return FK_OK;
+}
+
+fk_status fk_forward(fk_plan *p, const int *snap_steps, int n_snap, void *u_out, void *stream)
+{
+    FK_TRY(need_ws(p));
+    FK_TRY(check_snaps(p, snap_steps, n_snap, p->N, u_out));
+    return run_pass(p, nullptr, p->N, snap_steps, n_snap, u_out, (hipStream_t)stream);
+}
+
+fk_status fk_forward_from(fk_plan *p, const void *u_start, int start_step, const int *snap_steps,
+                          int n_snap, void *u_out, void *stream)
+{
+    FK_TRY(need_ws(p));
+    if (!u_start) return fail(FK_ERR_ARG, "null start state");
+    if (start_step < 0 || start_step > p->N) return fail(FK_ERR_ARG, "start_step outside [0, N]");
+    FK_TRY(check_snaps(p, snap_steps, n_snap, start_step, u_out));
+    return run_pass(p, u_start, start_step, snap_steps, n_snap, u_out, (hipStream_t)stream);
+}
+
+fk_status fk_step(fk_plan *p, int n, const void *u_next, void *u_out, void *stream)
+{
+    FK_TRY(need_ws(p));
+    if (!u_next || !u_out) return fail(FK_ERR_ARG, "null field");
+    if (n < 0 || n >= p->N) return fail(FK_ERR_ARG, "step %d outside [0, N-1]", n);
+    hipStream_t s = (hipStream_t)stream;
+    FK_LAUNCH(fk::launch_init_field(p->dev, p->f32, u_out, s));
+    return enqueue_step(p, n, u_next, u_out, s);
+}
+
+fk_status fk_export_cells(fk_plan *p, int inst, int n, int *cells, unsigned char *exit_flags,
+                          void *stream)
+{
+    FK_TRY(need_ws(p));
+    if (inst < 0 || inst >= p->n_inst) return fail(FK_ERR_ARG, "instance out of range");
+    if (n < 0 || n >= p->N) return fail(FK_ERR_ARG, "step outside [0, N-1]");
+    if (!cells || !exit_flags) return fail(FK_ERR_ARG, "null output");
+    FK_LAUNCH(fk::launch_tables(p->dev, n, (hipStream_t)stream));
+    FK_LAUNCH(fk::launch_export_cells(p->dev, inst, n, cells, exit_flags, (hipStream_t)stream));
+    return FK_OK;
+}
+
+fk_status fk_export_ell(fk_plan *p, int n, int *cols, void *vals, void *exit_mass, void *stream)
+{
+    FK_TRY(need_ws(p));
+    if (p->opt.form != FK_FORM_ELL) return fail(FK_ERR_STATE, "plan was not created with FK_FORM_ELL");
+    if (n < 0 || n >= p->N) return fail(FK_ERR_ARG, "step outside [0, N-1]");
+    if (!cols || !vals || !exit_mass) return fail(FK_ERR_ARG, "null output");
+    hipStream_t s = (hipStream_t)stream;
+    int *icols = (int *)p->at("ell_cols");
+    void *ivals = p->at("ell_vals"), *iem = p->at("ell_em");
+    FK_LAUNCH(fk::launch_tables(p->dev, n, s));
+    FK_LAUNCH(fk::launch_assemble_ell(p->dev, p->f32, n, icols, ivals, iem, s));
+    FK_LAUNCH(fk::launch_export_ell(p->dev, p->f32, icols, cols, s));
+    const size_t nv = (size_t)p->n_active * p->ell_width;
+    FK_HIP(hipMemcpyAsync(vals, ivals, nv * elt(p), hipMemcpyDeviceToDevice, s));
+    FK_HIP(hipMemcpyAsync(exit_mass, iem, (size_t)p->n_active * elt(p), hipMemcpyDeviceToDevice, s));
+    return FK_OK;
+}
+
+fk_status fk_check_flags(fk_plan *p, void *stream, int *flags)
+{
+    FK_TRY(need_ws(p));
+    if (!flags) return fail(FK_ERR_ARG, "null flags");
+    hipStream_t s = (hipStream_t)stream;
+    int h = 0;
+    FK_HIP(hipMemcpyAsync(&h, p->at("flags"), sizeof(int), hipMemcpyDeviceToHost, s));
+    FK_HIP(hipStreamSynchronize(s));
+    FK_LAUNCH(fk::launch_clear_flags(p->dev, s));
+    *flags = h;
+    if (h & 1) return fail(FK_ERR_NONFINITE, "a non-finite value was produced");
+    if (h & 2) return fail(FK_ERR_UNSUPPORTED, "a landing point fell outside the ELL row box");
+    return FK_OK;
+}
+
+fk_status fk_adjoint(fk_plan *p, const void *lam0, double *grad, void *lamN, void *stream)
+{
+    FK_TRY(need_ws(p));
+    if (p->opt.ckpt_every <= 0) return fail(FK_ERR_STATE, "plan created without ckpt_every > 0");
+    if (!lam0 || !grad) return fail(FK_ERR_ARG, "null lam0 or grad");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t fb = elt(p) * (size_t)p->n_nodes;
+    const int K = p->opt.ckpt_every;
+    // 1. forward pass storing checkpoints
+    FK_TRY(enqueue_pass(p, nullptr, p->N, nullptr, 0, nullptr, s, true));
+    // 2. reverse sweep, segment by segment from step 0 upward
+    void *la = p->at("lamA"), *lb = p->at("lamB"), *mu = p->at("mu");
+    double *g = (double *)p->at("grad");
+    unsigned char *ck = (unsigned char *)p->at("ckpt");
+    unsigned char *seg = (unsigned char *)p->at("seg");
+    void *packed = p->at("packed");
+    FK_LAUNCH(fk::launch_zero(g, sizeof(double) * fk::kThetaSlots * p->n_inst, s));
+    FK_LAUNCH(fk::launch_adjoint_init(p->dev, p->f32, lam0, la, s));
+    const int nseg = (p->N - 1) / K + 1;
+    for (int sg = 0; sg < nseg; ++sg) {
+        const int n0 = sg * K, n1 = std::min(n0 + K, p->N);
+        const int top_slot = (n1 == p->N) ? p->n_ckpt - 1 : n1 / K;
+        // seg[j] = u^{n0 + 1 + j}, j = 0 .. n1 - n0 - 1
+        FK_HIP(hipMemcpyAsync(seg + (size_t)(n1 - n0 - 1) * fb, ck + (size_t)top_slot * fb, fb,
+                              hipMemcpyDeviceToDevice, s));
+        for (int m = n1 - 1; m >= n0 + 1; --m) {
+            void *dst = seg + (size_t)(m - n0 - 1) * fb;
+            FK_LAUNCH(fk::launch_init_field(p->dev, p->f32, dst, s));
+            FK_TRY(enqueue_step(p, m, seg + (size_t)(m - n0) * fb, dst, s));
+        }
+        for (int n = n0; n < n1; ++n) {
+            const void *v = seg + (size_t)(n - n0) * fb;   // u^{n+1}
+            FK_LAUNCH(fk::launch_slopes(p->dev, p->f32, n, v, packed, s));
+            FK_LAUNCH(fk::launch_zero(mu, fb * rec_stride(p->d), s));
+            FK_LAUNCH(fk::launch_adjoint_step(p->dev, p->f32, n, packed, la, mu, g, s));
+            FK_LAUNCH(fk::launch_adjoint_slopes_T(p->dev, p->f32, v, mu, lb, s));
+            std::swap(la, lb);
+        }
+    }
+    FK_HIP(hipMemcpyAsync(grad, g, sizeof(double) * fk::kThetaSlots * p->n_inst,
+                          hipMemcpyDeviceToDevice, s));
+    if (lamN) FK_HIP(hipMemcpyAsync(lamN, la, fb, hipMemcpyDeviceToDevice, s));
+    return FK_OK;
+}
+
+fk_status fk_profile_pass(fk_plan *p, double *ms, int *counts, void *stream)
+{
+    FK_TRY(need_ws(p));
+    if (!ms || !counts) return fail(FK_ERR_ARG, "null output");
+    hipStream_t s = (hipStream_t)stream;
+    const int nk = 4;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kind;
+    auto rec = [&](int k) -> fk_status {
+        hipEvent_t e;
+        FK_HIP(hipEventCreate(&e));
+        FK_HIP(hipEventRecord(e, s));
+        ev.push_back(e);
+        kind.push_back(k);
+        return FK_OK;
+    };
+    void *ua = p->at("uA"), *ub = p->at("uB"), *packed = p->at("packed");
+    FK_LAUNCH(fk::launch_init_field(p->dev, p->f32, ua, s));
+    FK_LAUNCH(fk::launch_init_field(p->dev, p->f32, ub, s));
+    void *cur = ua, *nxt = ub;
+    for (int n = p->N - 1; n >= 0; --n) {
+        FK_TRY(rec(-1));
+        FK_LAUNCH(fk::launch_slopes(p->dev, p->f32, n, cur, packed, s));
+        FK_TRY(rec(0));
+        if (p->opt.form == FK_FORM_ELL) {
+            int *cols = (int *)p->at("ell_cols");
+            void *vals = p->at("ell_vals"), *em = p->at("ell_em");
+            FK_LAUNCH(fk::launch_assemble_ell(p->dev, p->f32, n, cols, vals, em, s));
+            FK_TRY(rec(2));
+            FK_LAUNCH(fk::launch_ell_apply(p->dev, p->f32, cols, vals, em, packed, nxt, s));
+            FK_TRY(rec(3));
+        } else {
+            FK_LAUNCH(fk::launch_step_fused(p->dev, p->f32, n, packed, nxt, s));
+            FK_TRY(rec(1));
+        }
+        std::swap(cur, nxt);
+    }
+    FK_HIP(hipStreamSynchronize(s));
+    double tot[nk] = {0, 0, 0, 0};
+    int cnt[nk] = {0, 0, 0, 0};
+    for (size_t i = 1; i < ev.size(); ++i) {
+        if (kind[i] < 0) continue;
+        float t = 0.f;
+        FK_HIP(hipEventElapsedTime(&t, ev[i - 1], ev[i]));
+        tot[kind[i]] += t;
+        cnt[kind[i]] += 1;
+    }
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (int k = 0; k < nk; ++k) {
+        ms[k] = cnt[k] ? tot[k] / cnt[k] : 0.0;
+        counts[k] = cnt[k];
+    }
+    return FK_OK;
+}
+
+}  // extern "C"

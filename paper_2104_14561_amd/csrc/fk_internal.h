@@ -1,0 +1,118 @@
+// fk_internal.h -- device-side plan records and kernel launchers shared by the
+// host runtime (fk_host.cpp) and the gfx950 kernels (fk_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace fk {
+
+constexpr int kMaxDim = 3;
+constexpr int kTimeFactors = 4;   // per (step, instance) time table entries
+constexpr int kThetaSlots = 8;    // gradient entries per instance (FK_MAX_THETA)
+
+// Per-instance record read by every kernel (one per instance of a plan).
+struct DevInst {
+    int d;
+    int n[kMaxDim];
+    int periodic[kMaxDim];
+    int uniform[kMaxDim];          // nearly equal spacing: guess the cell arithmetically
+    int affine[kMaxDim];           // x_k == k * step + lo exactly (k < n-1), x_{n-1} == hi
+    int coef_kind;
+    int region_kind;
+    int n_act;
+    int pad0;
+    long long stride[kMaxDim];     // node strides inside the instance
+    long long node_off;            // offset of the instance in a packed field
+    long long coord_off[kMaxDim];  // offsets of the axes in the coordinate array
+    long long act_off;             // offset in the packed active list
+    double lo[kMaxDim], hi[kMaxDim], inv_h[kMaxDim], period[kMaxDim], step[kMaxDim];
+    double coef[7];
+    double D;
+    double center[kMaxDim];
+    double r2;
+    double S;       // sqrt(2 D) * sqrt(2 dt)
+    double dSdD;    // S / (2 D)  (adjoint)
+};
+
+// A contiguous chunk of one instance's nodes (slope pass) or active nodes
+// (step pass) handled by one workgroup.  kind 0: nodes first .. first+count-1;
+// kind 1 + a: entries of the trig table of axis a.
+struct WorkItem {
+    int inst;
+    int first;
+    int count;
+    int kind;
+};
+
+// Pointers into the workspace that every launch needs.
+struct PlanDev {
+    const DevInst *inst;
+    const double *coords;       // packed node coordinates of all axes
+    const int *active;          // node index inside its instance, per active node
+    const unsigned char *chi;   // terminal values (0/1) per packed node
+    const double *gh_a;         // 1D GH nodes (Q*)
+    const double *gh_w;         // tensor weights (Q), double
+    const float *gh_wf;         // tensor weights (Q), float
+    const double *tfac;         // [n_steps][n_inst][kTimeFactors]
+    double2 *trig;              // per-axis (sin, cos) of the drift arguments at t_n
+    const WorkItem *slope_work; // trig table items, then node runs near active nodes
+    const WorkItem *node_work;  // all nodes (adjoint passes)
+    const WorkItem *act_work;   // step pass work list (block / G active nodes each)
+    const WorkItem *row_work;   // row-per-thread work list (block active nodes each)
+    int *flags;                 // bit 0: non-finite value produced
+    int n_inst;
+    int n_slope_work;
+    int n_table_work;
+    int n_node_work;
+    int n_act_work;
+    int n_row_work;
+    int d;
+    int qs;                     // Q*
+    int n_quad;                 // Q
+    int n_steps;
+    int block;                  // threads per workgroup
+    int group;                  // lanes per active node in the step passes
+    int slope_grid;             // workgroups of the slope pass
+    int node_grid;              // workgroups of all-node passes
+    int act_grid;               // workgroups of the step pass
+    int row_grid;               // workgroups of row-per-thread passes
+    double dt;
+    double t0;
+    long long n_nodes;
+    long long n_active;
+    // ELL form
+    int ell_width;
+    int ell_box[kMaxDim];
+    int ell_grid;
+};
+
+// Kernel launchers (fk_kernels.hip).  T is double or float; all return the
+// HIP error of the launch.
+hipError_t launch_init_field(const PlanDev &P, bool f32, void *u, hipStream_t s);
+hipError_t launch_slopes(const PlanDev &P, bool f32, int n, const void *u, void *packed,
+                         hipStream_t s);
+hipError_t launch_tables(const PlanDev &P, int n, hipStream_t s);
+hipError_t launch_step_fused(const PlanDev &P, bool f32, int n, const void *packed,
+                             void *u_out, hipStream_t s);
+hipError_t launch_assemble_ell(const PlanDev &P, bool f32, int n, int *cols, void *vals,
+                               void *exit_mass, hipStream_t s);
+hipError_t launch_ell_apply(const PlanDev &P, bool f32, const int *cols, const void *vals,
+                            const void *exit_mass, const void *packed, void *u_out,
+                            hipStream_t s);
+hipError_t launch_export_ell(const PlanDev &P, bool f32, const int *cols_in, int *cols_out,
+                             hipStream_t s);
+hipError_t launch_export_cells(const PlanDev &P, int inst, int n, int *cells,
+                               unsigned char *exit_flags, hipStream_t s);
+hipError_t launch_clear_flags(const PlanDev &P, hipStream_t s);
+
+// Adjoint launchers.
+hipError_t launch_adjoint_step(const PlanDev &P, bool f32, int n, const void *packed,
+                               const void *lam, void *mu, double *grad, hipStream_t s);
+hipError_t launch_adjoint_slopes_T(const PlanDev &P, bool f32, const void *u,
+                                   const void *mu, void *lam_next, hipStream_t s);
+hipError_t launch_adjoint_init(const PlanDev &P, bool f32, const void *lam0, void *lam,
+                               hipStream_t s);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+
+}  // namespace fk

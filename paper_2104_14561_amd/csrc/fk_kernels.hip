@@ -1,0 +1,1205 @@
+// fk_kernels.hip -- gfx950 kernels of the backward Feynman-Kac step.
+//
+// One backward step u^{n+1} -> u^n (paper Section 3.1, Scheme 1; matrix form
+// u^n = Q Psi^n F^n u^{n+1}, Eq. (e36)) is two passes:
+//   1. slope pass (F^n): per node near the active region, the PCHIP slope
+//      along every axis (Eq. (e300) and the end-node rule after it), packed
+//      with the value into one record (u, g_0, .., g_{d-1}) so that the step
+//      pass gathers a whole cell corner with one vector load.  The same launch
+//      tabulates sin/cos of the per-axis arguments of the drift at t_n.
+//   2. step pass (Q Psi^n): per active node, the Euler landing points through
+//      the tensor Gauss-Hermite nodes (Eq. (e31)), exit test, cell location,
+//      tensor cubic Hermite weights (Section 3.1.2) and the weighted sum over
+//      quadrature points (Eq. (quad)).
+//
+// Lane layout of the step pass: a group of G lanes (G = Q rounded up to a
+// power of two, at most one wave) serves one active node; lane l takes the
+// tensor Gauss-Hermite points q = l, l + G, ...  The sum over the group is a
+// fixed shuffle tree, so FP64 results are reproducible run to run.  The sum
+// is accumulated as offsets from the node's own value u^{n+1}_j
+// (u^n_j = u^{n+1}_j + sum_q w_q (v_q - u^{n+1}_j), v_q = 1 for an exit), which
+// is the same number in exact arithmetic (sum_q w_q = 1) but keeps the
+// rounding of weights and basis in FP32 proportional to the local variation
+// of u instead of u itself.
+//
+// Landing points, exit tests and cells are FP64 in both precisions; the
+// evaluation order of the landing point is sq = sqrt(2 dt), S = sqrt(2D) sq,
+// c = x + b dt, z = c + S a, with every product rounded (no contraction), so
+// that cells agree bit for bit with any implementation that follows the same
+// order.
+#include "fk_internal.h"
+
+#include <cmath>
+
+namespace fk {
+namespace {
+
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------------------
+// Packed node record (u, slopes): 2 entries for d = 1, 4 for d = 2, 3.
+// ---------------------------------------------------------------------------
+template <typename T, int PS> struct RecT;
+template <> struct RecT<double, 2> { using type = double2; };
+template <> struct RecT<double, 4> { using type = double4; };
+template <> struct RecT<float, 2> { using type = float2; };
+template <> struct RecT<float, 4> { using type = float4; };
+
+template <int D> struct RecStride { static constexpr int value = (D == 1) ? 2 : 4; };
+
+// ---------------------------------------------------------------------------
+// Work distribution: a persistent loop over work items.  Workgroups are
+// dispatched round-robin over the 8 XCDs (workgroup b runs on XCD b % 8);
+// each XCD takes a contiguous chunk of the work list so that neighbouring
+// tiles -- whose stencils overlap -- share one L2.
+// ---------------------------------------------------------------------------
+struct WorkRange {
+    int begin, end, step;
+};
+
+__device__ inline WorkRange work_range(int first, int n_work)
+{
+    const int nx = 8;
+    const int g = gridDim.x;
+    WorkRange r;
+    if (g < nx || (g % nx) != 0) {
+        r.begin = first + blockIdx.x;
+        r.end = first + n_work;
+        r.step = g;
+        return r;
+    }
+    const int xcd = blockIdx.x % nx, local = blockIdx.x / nx, per = g / nx;
+    const int chunk = (n_work + nx - 1) / nx;
+    r.begin = first + xcd * chunk + local;
+    r.end = first + min(n_work, (xcd + 1) * chunk);
+    r.step = per;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Axis geometry.  An affine axis (host-verified: x_k = k * step + lo exactly
+// for k < n-1, x_{n-1} = hi) needs no coordinate loads.
+// ---------------------------------------------------------------------------
+__device__ inline double coord(const DevInst &I, const double *coords, int a, int k)
+{
+#pragma clang fp contract(off)
+    if (I.affine[a]) return (k == I.n[a] - 1) ? I.hi[a] : (double)k * I.step[a] + I.lo[a];
+    return coords[I.coord_off[a] + k];
+}
+
+// Cell of z: max{k : x_k <= z}, clamped to [0, n-2].  On a uniform axis the
+// arithmetic guess floor((z - lo) / h) is within one cell of the answer (the
+// spacing deviates from h by far less than a cell), so one conditional step up
+// and one down against the node coordinates give it exactly; other axes use
+// binary search over the stored coordinates.
+__device__ inline int locate(const DevInst &I, const double *coords, int a, double z)
+{
+    const int n = I.n[a];
+    int k;
+    if (I.uniform[a]) {
+        const double f = floor((z - I.lo[a]) * I.inv_h[a]);
+        k = (f >= 0.0) ? ((f <= (double)(n - 2)) ? (int)f : n - 2) : 0;
+        if (k < n - 2 && coord(I, coords, a, k + 1) <= z) ++k;
+        if (k > 0 && coord(I, coords, a, k) > z) --k;
+    } else {
+        const double *x = coords + I.coord_off[a];
+        int l = 0, h = n - 1;
+        if (z >= x[n - 1]) {
+            l = n - 2;
+        } else if (z >= x[0]) {
+            while (h - l > 1) {
+                const int m = (l + h) >> 1;
+                if (x[m] <= z) l = m; else h = m;
+            }
+        }
+        k = l;
+    }
+    return k;
+}
+
+// One axis of a landing point: coordinate, exit flag, cell and position.
+struct AxisEval {
+    double s;      // position inside the cell
+    double h;      // cell width
+    double dz2;    // (z - centre)^2 for the ball test
+    int k;         // cell
+    bool ex;       // z left the box on this (non-periodic) axis
+};
+
+__device__ inline AxisEval eval_axis(const DevInst &I, const double *coords, int a, double c,
+                                     double ga)
+{
+#pragma clang fp contract(off)
+    double z = c + I.S * ga;
+    if (I.periodic[a]) {
+        if (z >= I.hi[a]) z = z - I.period[a];
+        else if (z < I.lo[a]) z = z + I.period[a];
+    }
+    AxisEval e;
+    e.ex = !I.periodic[a] && (z <= I.lo[a] || z >= I.hi[a]);
+    const double t = z - I.center[a];
+    e.dz2 = t * t;
+    const int k = locate(I, coords, a, z);
+    const double xk = coord(I, coords, a, k);
+    if (I.affine[a]) {
+        e.h = I.step[a];
+        e.s = (z - xk) * I.inv_h[a];
+    } else {
+        e.h = coord(I, coords, a, k + 1) - xk;
+        e.s = (z - xk) / e.h;
+    }
+    e.k = k;
+    return e;
+}
+
+__device__ inline bool ball_exit(const double *dz2, int d, double r2)
+{
+#pragma clang fp contract(off)
+    double s = dz2[0];
+    for (int a = 1; a < d; ++a) s = s + dz2[a];
+    return s >= r2;
+}
+
+// ---------------------------------------------------------------------------
+// Coefficients (FP64).  tf = per-(step, instance) time factors tabulated at
+// plan creation: cellular (eps sin(omega t), sin(omega t), cos(omega t), t);
+// ABC (1 + amp sin t, sin t, 0, t).  trig = per-axis (sin, cos) table of the
+// drift's argument at each node coordinate for the current step:
+// cellular axis 0: pi (x + eps sin(omega t)); cellular axis 1: pi y;
+// ABC: the coordinate itself.
+// ---------------------------------------------------------------------------
+__device__ inline double trig_arg(const DevInst &I, const double *tf, int a, double x)
+{
+#pragma clang fp contract(off)
+    if (I.coef_kind == 1) return (a == 0) ? M_PI * (x + tf[0]) : M_PI * x;
+    return x;
+}
+
+__device__ inline void drift(const DevInst &I, const double *tf, const double2 *trig,
+                             const int *idx, double *b)
+{
+#pragma clang fp contract(off)
+    if (I.coef_kind == 0) {
+        for (int a = 0; a < I.d; ++a) b[a] = I.coef[a];
+    } else if (I.coef_kind == 1) {
+        const double2 t0 = trig[I.coord_off[0] + idx[0]];
+        const double2 t1 = trig[I.coord_off[1] + idx[1]];
+        const double sa = t0.x, ca = t0.y, sy = t1.x, cy = t1.y;
+        const double Api = I.coef[0] * M_PI;
+        b[0] = -(Api * sa * cy);
+        b[1] = Api * ca * sy;
+    } else {
+        const double2 tx = trig[I.coord_off[0] + idx[0]];
+        const double2 ty = trig[I.coord_off[1] + idx[1]];
+        const double2 tz = trig[I.coord_off[2] + idx[2]];
+        const double f = tf[0];
+        const double Af = I.coef[0] * f, Bf = I.coef[1] * f, Cf = I.coef[2] * f;
+        b[0] = Af * tz.x + Cf * ty.y;
+        b[1] = Bf * tx.x + Af * tz.y;
+        b[2] = Cf * ty.x + Bf * tx.y;
+    }
+}
+
+// d b_a / d theta_k for the drift parameters (theta_k, k < np); db[k*3 + a].
+__device__ inline int drift_dtheta(const DevInst &I, const double *tf, const double2 *trig,
+                                   const int *idx, double *db)
+{
+    for (int k = 0; k < 12; ++k) db[k] = 0.0;
+    if (I.coef_kind == 0) {
+        for (int a = 0; a < I.d; ++a) db[a * 3 + a] = 1.0;
+        return I.d;
+    } else if (I.coef_kind == 1) {
+        const double A = I.coef[0], eps = I.coef[1];
+        const double swt = tf[1], cwt = tf[2], t = tf[3];
+        const double2 t0 = trig[I.coord_off[0] + idx[0]];
+        const double2 t1 = trig[I.coord_off[1] + idx[1]];
+        const double sphi = t0.x, cphi = t0.y, sy = t1.x, cy = t1.y;
+        const double db0 = -A * M_PI * cphi * cy;   // d b0 / d phi
+        const double db1 = -A * M_PI * sphi * sy;   // d b1 / d phi
+        const double dpe = M_PI * swt;              // d phi / d eps
+        const double dpo = M_PI * eps * t * cwt;    // d phi / d omega
+        db[0] = -M_PI * sphi * cy;  db[1] = M_PI * cphi * sy;
+        db[3] = db0 * dpe;          db[4] = db1 * dpe;
+        db[6] = db0 * dpo;          db[7] = db1 * dpo;
+        return 3;
+    } else {
+        const double A = I.coef[0], B = I.coef[1], C = I.coef[2];
+        const double f = tf[0], st = tf[1];
+        const double2 tx = trig[I.coord_off[0] + idx[0]];
+        const double2 ty = trig[I.coord_off[1] + idx[1]];
+        const double2 tz = trig[I.coord_off[2] + idx[2]];
+        const double sx = tx.x, cx = tx.y, sy = ty.x, cy = ty.y, sz = tz.x, cz = tz.y;
+        db[0] = f * sz;  db[1] = f * cz;                      // A
+        db[4] = f * sx;  db[5] = f * cx;                      // B
+        db[6] = f * cy;  db[8] = f * sy;                      // C
+        db[9] = st * (A * sz + C * cy);                        // amp
+        db[10] = st * (B * sx + A * cz);
+        db[11] = st * (C * sy + B * cx);
+        return 4;
+    }
+}
+
+template <int D>
+__device__ inline void split_node(const DevInst &I, int node, int *idx)
+{
+    if (D == 1) {
+        idx[0] = node;
+    } else if (D == 2) {
+        idx[0] = node / I.n[1];
+        idx[1] = node - idx[0] * I.n[1];
+    } else {
+        const int plane = I.n[1] * I.n[2];
+        idx[0] = node / plane;
+        const int rem = node - idx[0] * plane;
+        idx[1] = rem / I.n[2];
+        idx[2] = rem - idx[1] * I.n[2];
+    }
+}
+
+// Landing-point centre c = x + b(t_n, x) dt of a node.
+template <int D>
+__device__ inline void node_centre(const DevInst &I, const double *coords, const double *tf,
+                                   const double2 *trig, const int *idx, double dt, double *c)
+{
+#pragma clang fp contract(off)
+    double b[3];
+    drift(I, tf, trig, idx, b);
+    for (int a = 0; a < D; ++a) c[a] = coord(I, coords, a, idx[a]) + b[a] * dt;
+}
+
+// ---------------------------------------------------------------------------
+// Cubic Hermite basis on [0, 1] (Section 3.1.2): value basis v0 = H00,
+// v1 = H01 and slope basis times the cell width d0 = h H10, d1 = h H11, and
+// the derivatives of both with respect to z.
+// ---------------------------------------------------------------------------
+template <typename T> struct Basis {
+    T v0, v1, d0, d1;
+};
+
+template <typename T>
+__device__ inline Basis<T> hermite(double s_d, double h_d)
+{
+    const T s = (T)s_d, h = (T)h_d;
+    const T om = T(1) - s;
+    Basis<T> B;
+    B.v0 = (T(1) + T(2) * s) * om * om;
+    B.v1 = s * s * (T(3) - T(2) * s);
+    B.d0 = h * s * om * om;
+    B.d1 = h * s * s * (s - T(1));
+    return B;
+}
+
+template <typename T>
+__device__ inline Basis<T> hermite_dz(double s_d, double h_d)
+{
+    const T s = (T)s_d, h = (T)h_d;
+    Basis<T> B;
+    B.v0 = (T(6) * s * s - T(6) * s) / h;
+    B.v1 = (T(6) * s - T(6) * s * s) / h;
+    B.d0 = T(1) - T(4) * s + T(3) * s * s;
+    B.d1 = T(3) * s * s - T(2) * s;
+    return B;
+}
+
+template <int G, typename T>
+__device__ inline T group_sum(T v)
+{
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename T>
+__device__ inline void flag_nonfinite(int *flags, T v)
+{
+    if (!isfinite((double)v)) atomicOr(flags, 1);
+}
+
+// Write a node's value and its periodic images.
+template <int D, typename T>
+__device__ inline void store_node(const DevInst &I, const int *idx, long long node, T v,
+                                  T *u_out)
+{
+    u_out[I.node_off + node] = v;
+    int pm = 0;
+    for (int a = 0; a < D; ++a)
+        if (I.periodic[a] && idx[a] == 0) pm |= 1 << a;
+    if (pm) {
+        for (int sub = pm; sub; sub = (sub - 1) & pm) {
+            long long o = node;
+            for (int a = 0; a < D; ++a)
+                if (sub & (1 << a)) o += (long long)(I.n[a] - 1) * I.stride[a];
+            u_out[I.node_off + o] = v;
+        }
+    }
+}
+
+// Hermite value of the corner records p at one landing point; the value
+// entries enter as offsets (p.x - uref).
+template <typename T, int D, typename R>
+__device__ inline T hermite_value(const R *p, const Basis<T> *B, T uref)
+{
+    if constexpr (D == 1) {
+        return (p[0].x - uref) * B[0].v0 + (p[1].x - uref) * B[0].v1 + p[0].y * B[0].d0 +
+               p[1].y * B[0].d1;
+    } else if constexpr (D == 2) {
+        // corners p[a*2 + b]: a along axis 0, b along axis 1
+        const Basis<T> &X = B[0], &Y = B[1];
+        const T A0 = (p[0].x - uref) * X.v0 + (p[2].x - uref) * X.v1 + p[0].y * X.d0 + p[2].y * X.d1;
+        const T A1 = (p[1].x - uref) * X.v0 + (p[3].x - uref) * X.v1 + p[1].y * X.d0 + p[3].y * X.d1;
+        const T C0 = p[0].z * X.v0 + p[2].z * X.v1;
+        const T C1 = p[1].z * X.v0 + p[3].z * X.v1;
+        return Y.v0 * A0 + Y.v1 * A1 + Y.d0 * C0 + Y.d1 * C1;
+    } else {
+        // corners p[(a*2 + b)*2 + c]
+        const Basis<T> &X = B[0], &Y = B[1], &Z = B[2];
+        T acc = T(0);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const T Zv = c ? Z.v1 : Z.v0, Zd = c ? Z.d1 : Z.d0;
+            T sv = T(0), sd = T(0);
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const T Yv = b ? Y.v1 : Y.v0, Yd = b ? Y.d1 : Y.d0;
+                const R &p0 = p[(0 * 2 + b) * 2 + c], &p1 = p[(1 * 2 + b) * 2 + c];
+                const T xu = (p0.x - uref) * X.v0 + (p1.x - uref) * X.v1 + p0.y * X.d0 + p1.y * X.d1;
+                const T xg1 = p0.z * X.v0 + p1.z * X.v1;
+                const T xg2 = p0.w * X.v0 + p1.w * X.v1;
+                sv += Yv * xu + Yd * xg1;
+                sd += Yv * xg2;
+            }
+            acc += Zv * sv + Zd * sd;
+        }
+        return acc;
+    }
+}
+
+// Gradient of the Hermite value with respect to z (adjoint); Bz = hermite_dz.
+template <typename T, int D, typename R>
+__device__ inline void hermite_grad(const R *p, const Basis<T> *B, const Basis<T> *Bz, T *g)
+{
+    Basis<T> BB[3];
+    for (int m = 0; m < D; ++m) {
+        for (int a = 0; a < D; ++a) BB[a] = (a == m) ? Bz[a] : B[a];
+        g[m] = hermite_value<T, D, R>(p, BB, T(0));
+    }
+}
+
+// Gather the 2^D corner records of a cell.
+template <int D, typename R>
+__device__ inline void gather_corners(const R *rec, const DevInst &I, const int *k, R *p)
+{
+    long long base = I.node_off;
+    for (int a = 0; a < D; ++a) base += (long long)k[a] * I.stride[a];
+    if constexpr (D == 1) {
+        p[0] = rec[base];
+        p[1] = rec[base + 1];
+    } else if constexpr (D == 2) {
+        const long long s0 = I.stride[0];
+        p[0] = rec[base];
+        p[1] = rec[base + 1];
+        p[2] = rec[base + s0];
+        p[3] = rec[base + s0 + 1];
+    } else {
+        const long long s0 = I.stride[0], s1 = I.stride[1];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                p[(a * 2 + b) * 2 + 0] = rec[base + a * s0 + b * s1];
+                p[(a * 2 + b) * 2 + 1] = rec[base + a * s0 + b * s1 + 1];
+            }
+    }
+}
+
+// Landing point with the GH coordinates aq[] of the point already known.
+template <int D>
+__device__ inline bool landing_point_a(const DevInst &I, const double *coords, const double *c,
+                                       const double *aq, int *k, double *s, double *h)
+{
+    bool ex = false;
+    double dz2[3];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const AxisEval e = eval_axis(I, coords, a, c[a], aq[a]);
+        ex = ex || e.ex;
+        dz2[a] = e.dz2;
+        k[a] = e.k;
+        s[a] = e.s;
+        h[a] = e.h;
+    }
+    if (I.region_kind == 1) ex = ex || ball_exit(dz2, D, I.r2);
+    return ex;
+}
+
+// Evaluates landing point q of a node: exit flag, cells and per-axis data.
+template <int D>
+__device__ inline bool landing_point(const DevInst &I, const double *coords, const double *ga,
+                                     int qs, const double *c, int q, int *k, double *s, double *h)
+{
+    double aq[3];
+    for (int a = D - 1; a >= 0; --a) {
+        aq[a] = ga[q % qs];
+        q /= qs;
+    }
+    bool ex = false;
+    double dz2[3];
+    for (int a = 0; a < D; ++a) {
+        const AxisEval e = eval_axis(I, coords, a, c[a], aq[a]);
+        ex = ex || e.ex;
+        dz2[a] = e.dz2;
+        k[a] = e.k;
+        s[a] = e.s;
+        h[a] = e.h;
+    }
+    if (I.region_kind == 1) ex = ex || ball_exit(dz2, D, I.r2);
+    return ex;
+}
+
+template <typename T> __device__ inline const T *weights(const PlanDev &P);
+template <> __device__ inline const double *weights<double>(const PlanDev &P) { return P.gh_w; }
+template <> __device__ inline const float *weights<float>(const PlanDev &P) { return P.gh_wf; }
+
+__device__ inline const double *time_factors(const PlanDev &P, int n, int inst)
+{
+    return P.tfac + ((long long)n * P.n_inst + inst) * kTimeFactors;
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_init_field(const unsigned char *cls, long long n,
+                                                       T *u)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        u[i] = (T)(cls[i] & 1);
+}
+
+// Slope pass for step n over work items [first, first + count): table items
+// (kind 1 + a) fill the (sin, cos) table of axis a; node items (kind 0) write
+// record[node] = (u, g_0, .., g_{d-1}).
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_slopes(PlanDev P, int n, int first, int count,
+                                                   const T *__restrict__ u,
+                                                   T *__restrict__ packed)
+{
+    constexpr int PS = RecStride<D>::value;
+    using R = typename RecT<T, PS>::type;
+    R *rec = reinterpret_cast<R *>(packed);
+    const WorkRange wr = work_range(first, count);
+    for (int w = wr.begin; w < wr.end; w += wr.step) {
+        const WorkItem it = P.slope_work[w];
+        if ((int)threadIdx.x >= it.count) continue;
+        const DevInst &I = P.inst[it.inst];
+        if (it.kind > 0) {
+            const int a = it.kind - 1;
+            const int i = it.first + threadIdx.x;
+            const double arg = trig_arg(I, time_factors(P, n, it.inst), a,
+                                        P.coords[I.coord_off[a] + i]);
+            P.trig[I.coord_off[a] + i] = make_double2(sin(arg), cos(arg));
+            continue;
+        }
+        const int node = it.first + threadIdx.x;
+        int idx[3];
+        split_node<D>(I, node, idx);
+        const T *ui = u + I.node_off;
+        T out[4] = {ui[node], T(0), T(0), T(0)};
+        for (int a = 0; a < D; ++a) {
+            const int na = I.n[a];
+            const int i = idx[a];
+            int il, ic, ir;
+            if (I.periodic[a]) {
+                ic = (i == na - 1) ? 0 : i;
+                il = (ic == 0) ? na - 2 : ic - 1;
+                ir = ic + 1;
+            } else if (i == 0) {
+                il = 0; ic = 1; ir = 2;
+            } else if (i == na - 1) {
+                il = na - 3; ic = na - 2; ir = na - 1;
+            } else {
+                il = i - 1; ic = i; ir = i + 1;
+            }
+            double hl, hr;
+            if (I.affine[a]) {
+                hl = I.step[a];
+                hr = I.step[a];
+            } else {
+                const double *x = P.coords + I.coord_off[a];
+                hl = (ic == 0) ? x[na - 1] - x[na - 2] : x[ic] - x[il];
+                hr = x[ir] - x[ic];
+            }
+            const long long base = node - (long long)i * I.stride[a];
+            const T ul = ui[base + (long long)il * I.stride[a]];
+            const T uc = ui[base + (long long)ic * I.stride[a]];
+            const T ur = ui[base + (long long)ir * I.stride[a]];
+            const T dl = (uc - ul) / (T)hl;
+            const T dr = (ur - uc) / (T)hr;
+            out[1 + a] = (dl * dr > T(0)) ? T(2) * dl * dr / (dl + dr) : T(0);
+        }
+        R r;
+        if constexpr (PS == 2) {
+            r.x = out[0]; r.y = out[1];
+        } else {
+            r.x = out[0]; r.y = out[1]; r.z = out[2]; r.w = out[3];
+        }
+        rec[I.node_off + node] = r;
+    }
+}
+
+// Fused step pass (matrix-free form of Eq. (e36)).  The read-only tables
+// come in as separate restrict-qualified arguments so that per-instance and
+// per-work-item fields are fetched with scalar loads; each lane's quadrature
+// points (at most NQ per lane) are decoded once per launch.
+template <typename T, int D, int G, int NQ>
+__global__ void __launch_bounds__(kBlock) k_step_fused(
+    const PlanDev P, int n, const DevInst *__restrict__ insts,
+    const WorkItem *__restrict__ work, const int *__restrict__ active,
+    const double2 *__restrict__ trig, const double *__restrict__ coords,
+    const T *__restrict__ packed, T *__restrict__ u_out)
+{
+    constexpr int PS = RecStride<D>::value;
+    using R = typename RecT<T, PS>::type;
+    const R *rec = reinterpret_cast<const R *>(packed);
+    const int lane = threadIdx.x % G;
+    int slot = threadIdx.x / G;
+    if (G == 64) slot = __builtin_amdgcn_readfirstlane(slot);
+    // this lane's quadrature points q = lane + i G
+    double aq[NQ][3];
+    T wq[NQ];
+    bool has[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        int q = lane + i * G;
+        has[i] = q < P.n_quad;
+        if (!has[i]) q = 0;
+        wq[i] = has[i] ? weights<T>(P)[q] : T(0);
+        for (int a = D - 1; a >= 0; --a) {
+            aq[i][a] = P.gh_a[q % P.qs];
+            q /= P.qs;
+        }
+    }
+    const WorkRange wr = work_range(0, P.n_act_work);
+    for (int w = wr.begin; w < wr.end; w += wr.step) {
+        const WorkItem it = work[w];
+        const bool valid = slot < it.count;
+        const DevInst &I = insts[it.inst];
+        T acc = T(0), uref = T(0);
+        int idx[3] = {0, 0, 0};
+        int node = 0;
+        if (valid) {
+            node = active[I.act_off + it.first + slot];
+            split_node<D>(I, node, idx);
+            uref = rec[I.node_off + node].x;
+            double c[3];
+            node_centre<D>(I, coords, time_factors(P, n, it.inst), trig, idx, P.dt, c);
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) {
+                if (!has[i]) continue;
+                int k[3];
+                double s[3], h[3];
+                const bool ex = landing_point_a<D>(I, coords, c, aq[i], k, s, h);
+                if (ex) {
+                    acc += wq[i] * (T(1) - uref);
+                } else {
+                    Basis<T> B[3];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) B[a] = hermite<T>(s[a], h[a]);
+                    R p[1 << D];
+                    gather_corners<D, R>(rec, I, k, p);
+                    acc += wq[i] * hermite_value<T, D, R>(p, B, uref);
+                }
+            }
+        }
+        acc = group_sum<G>(acc);
+        if (valid && lane == 0) {
+            const T v = uref + acc;
+            flag_nonfinite(P.flags, v);
+            store_node<D, T>(I, idx, node, v, u_out);
+        }
+    }
+}
+
+// Landing cells and exit flags of one instance (index parity checks).
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_export_cells(PlanDev P, int inst, int n,
+                                                         int *cells, unsigned char *exitf)
+{
+    const DevInst &I = P.inst[inst];
+    const long long total = (long long)I.n_act * P.n_quad;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+         t += (long long)gridDim.x * blockDim.x) {
+        const int r = (int)(t / P.n_quad);
+        const int q = (int)(t - (long long)r * P.n_quad);
+        const int node = P.active[I.act_off + r];
+        int idx[3];
+        split_node<D>(I, node, idx);
+        double c[3];
+        node_centre<D>(I, P.coords, time_factors(P, n, inst), P.trig, idx, P.dt, c);
+        int k[3];
+        double s[3], h[3];
+        const bool ex = landing_point<D>(I, P.coords, P.gh_a, P.qs, c, q, k, s, h);
+        exitf[t] = ex ? 1 : 0;
+        for (int a = 0; a < D; ++a) cells[t * D + a] = ex ? -1 : k[a];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Assembled form (the paper's GPU formulation, Section 3.2.1): A_n stored in
+// ELL, each row the dense box of nodes covered by its landing points times
+// (d+1) fields.  The lane group of a row builds it in LDS with shared atomics,
+// then writes it column-major (coalesced for the row-per-thread product).
+// The stored row is the plain operator (u^n_j = exit_mass + A_j [u; g]); the
+// product evaluates it in the same offset form as the fused pass.
+// ---------------------------------------------------------------------------
+template <typename T, int D, int G>
+__global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n, int *__restrict__ cols,
+                                                         T *__restrict__ vals,
+                                                         T *__restrict__ exit_mass)
+{
+    constexpr int PS = RecStride<D>::value;
+    extern __shared__ unsigned char smem_raw[];
+    T *box = reinterpret_cast<T *>(smem_raw);
+    const int W = P.ell_width;
+    const T *Wq = weights<T>(P);
+    const int lane = threadIdx.x % G;
+    const int slot = threadIdx.x / G;
+    const WorkRange wr = work_range(0, P.n_act_work);
+    for (int w = wr.begin; w < wr.end; w += wr.step) {
+        const WorkItem it = P.act_work[w];
+        const bool valid = slot < it.count;
+        const DevInst &I = P.inst[it.inst];
+        T *mybox = box + (long long)slot * W;
+        for (int k = lane; k < W; k += G) mybox[k] = T(0);
+        __syncthreads();
+        int idx[3] = {0, 0, 0};
+        int origin[3] = {0, 0, 0};
+        T em = T(0);
+        long long row = 0;
+        if (valid) {
+            const int node = P.active[I.act_off + it.first + slot];
+            row = I.act_off + it.first + slot;
+            split_node<D>(I, node, idx);
+            double c[3];
+            node_centre<D>(I, P.coords, time_factors(P, n, it.inst), P.trig, idx, P.dt, c);
+            // box origin: cell of the smallest landing coordinate per axis
+            for (int a = 0; a < D; ++a)
+                origin[a] = eval_axis(I, P.coords, a, c[a], P.gh_a[0]).k;
+            for (int q = lane; q < P.n_quad; q += G) {
+                int k[3];
+                double s[3], h[3];
+                const bool ex = landing_point<D>(I, P.coords, P.gh_a, P.qs, c, q, k, s, h);
+                const T wq = Wq[q];
+                if (ex) {
+                    em += wq;
+                    continue;
+                }
+                Basis<T> B[3];
+                for (int a = 0; a < D; ++a) B[a] = hermite<T>(s[a], h[a]);
+                for (int cb = 0; cb < (1 << D); ++cb) {
+                    int off = 0;
+                    bool in = true;
+                    T wv = wq;
+                    for (int a = 0; a < D; ++a) {
+                        const int bit = (cb >> (D - 1 - a)) & 1;
+                        const int l = k[a] + bit - origin[a];
+                        in = in && l >= 0 && l < P.ell_box[a];
+                        off = off * P.ell_box[a] + l;
+                        wv *= bit ? B[a].v1 : B[a].v0;
+                    }
+                    if (!in) {
+                        atomicOr(P.flags, 2);
+                        continue;
+                    }
+                    atomicAdd(&mybox[off * (D + 1)], wv);
+                    for (int a = 0; a < D; ++a) {
+                        T ws = wq;
+                        for (int i = 0; i < D; ++i) {
+                            const int bit = (cb >> (D - 1 - i)) & 1;
+                            if (i == a) ws *= bit ? B[i].d1 : B[i].d0;
+                            else ws *= bit ? B[i].v1 : B[i].v0;
+                        }
+                        atomicAdd(&mybox[off * (D + 1) + 1 + a], ws);
+                    }
+                }
+            }
+        }
+        em = group_sum<G>(em);
+        __syncthreads();
+        if (valid) {
+            const long long na = P.n_active;
+            for (int k = lane; k < W; k += G) {
+                const int f = k % (D + 1);
+                int l = k / (D + 1);
+                long long nd = I.node_off;
+                for (int a = D - 1; a >= 0; --a) {
+                    const int la = l % P.ell_box[a];
+                    l /= P.ell_box[a];
+                    int ia = origin[a] + la;
+                    if (ia > I.n[a] - 1) ia = I.n[a] - 1;   // padding stays in range
+                    nd += (long long)ia * I.stride[a];
+                }
+                cols[k * na + row] = (int)(nd * PS + f);
+                vals[k * na + row] = mybox[k];
+            }
+            if (lane == 0) exit_mass[row] = em;
+        }
+        __syncthreads();
+    }
+}
+
+// Row-per-thread ELL product
+//   u^n[row] = uref + exit_mass[row] (1 - uref) + sum_k val (x[col] - uref [value cols])
+// i.e. exit_mass + A [u; g] written in offset form about uref = u^{n+1}[row].
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_ell_apply(PlanDev P, const int *__restrict__ cols,
+                                                      const T *__restrict__ vals,
+                                                      const T *__restrict__ exit_mass,
+                                                      const T *__restrict__ packed,
+                                                      T *__restrict__ u_out)
+{
+    constexpr int PS = RecStride<D>::value;
+    const long long na = P.n_active;
+    const int W = P.ell_width;
+    const WorkRange wr = work_range(0, P.n_row_work);
+    for (int w = wr.begin; w < wr.end; w += wr.step) {
+        const WorkItem it = P.row_work[w];
+        if ((int)threadIdx.x >= it.count) continue;
+        const DevInst &I = P.inst[it.inst];
+        const long long row = I.act_off + it.first + threadIdx.x;
+        const int node = P.active[row];
+        const T uref = packed[(I.node_off + node) * PS];
+        T acc = exit_mass[row] * (T(1) - uref);
+        for (int k = 0; k < W; ++k) {
+            const int col = cols[k * na + row];
+            const T x = packed[col];
+            acc += vals[k * na + row] * ((col % PS) == 0 ? x - uref : x);
+        }
+        int idx[3];
+        split_node<D>(I, node, idx);
+        const T v = uref + acc;
+        flag_nonfinite(P.flags, v);
+        store_node<D, T>(I, idx, node, v, u_out);
+    }
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_export_ell_cols(PlanDev P, const int *cols_in,
+                                                            int *cols_out)
+{
+    constexpr int PS = RecStride<D>::value;
+    const long long total = P.n_active * (long long)P.ell_width;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
+         t += (long long)gridDim.x * blockDim.x) {
+        const int c = cols_in[t];
+        cols_out[t] = (c / PS) * (D + 1) + (c % PS);
+    }
+}
+
+__global__ void k_clear_flags(int *flags) { flags[0] = 0; }
+
+__global__ void __launch_bounds__(kBlock) k_zero(unsigned int *p, long long n)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint (exit classification held fixed).  Step n: given lam^n on active
+// nodes, scatter mu = A_n^T lam^n into per-node records (mu_u, mu_g...), and
+// accumulate dJ/dtheta += lam^n_j sum_q w_q grad_z I(z_jq) . dz_jq/dtheta.
+// ---------------------------------------------------------------------------
+template <typename T, int D, int G>
+__global__ void __launch_bounds__(kBlock) k_adjoint_step(PlanDev P, int n,
+                                                         const T *__restrict__ packed,
+                                                         const T *__restrict__ lam,
+                                                         T *__restrict__ mu,
+                                                         double *__restrict__ grad)
+{
+    constexpr int PS = RecStride<D>::value;
+    using R = typename RecT<T, PS>::type;
+    const R *rec = reinterpret_cast<const R *>(packed);
+    const T *W = weights<T>(P);
+    const int lane = threadIdx.x % G;
+    const int slot = threadIdx.x / G;
+    __shared__ double red[kBlock / 64][kThetaSlots];
+    const WorkRange wr = work_range(0, P.n_act_work);
+    for (int w = wr.begin; w < wr.end; w += wr.step) {
+        const WorkItem it = P.act_work[w];
+        const bool valid = slot < it.count;
+        const DevInst &I = P.inst[it.inst];
+        double gth[kThetaSlots];
+        for (int k = 0; k < kThetaSlots; ++k) gth[k] = 0.0;
+        if (valid) {
+            const int node = P.active[I.act_off + it.first + slot];
+            int idx[3];
+            split_node<D>(I, node, idx);
+            const T L = lam[I.node_off + node];
+            if (L != T(0)) {
+                const double *tf = time_factors(P, n, it.inst);
+                double c[3];
+                node_centre<D>(I, P.coords, tf, P.trig, idx, P.dt, c);
+                // per axis: sum_q w_q dI/dz_a and sum_q w_q a_{q_a} dI/dz_a
+                T Gz[3] = {T(0), T(0), T(0)}, Hz[3] = {T(0), T(0), T(0)};
+                for (int q = lane; q < P.n_quad; q += G) {
+                    int k[3];
+                    double s[3], h[3];
+                    if (landing_point<D>(I, P.coords, P.gh_a, P.qs, c, q, k, s, h)) continue;
+                    const T wq = W[q];
+                    const T Lw = L * wq;
+                    Basis<T> B[3], Bz[3];
+                    for (int a = 0; a < D; ++a) {
+                        B[a] = hermite<T>(s[a], h[a]);
+                        Bz[a] = hermite_dz<T>(s[a], h[a]);
+                    }
+                    R p[1 << D];
+                    gather_corners<D, R>(rec, I, k, p);
+                    T gz[3];
+                    hermite_grad<T, D, R>(p, B, Bz, gz);
+                    int qr = q, qi[3];
+                    for (int a = D - 1; a >= 0; --a) { qi[a] = qr % P.qs; qr /= P.qs; }
+                    for (int a = 0; a < D; ++a) {
+                        Gz[a] += wq * gz[a];
+                        Hz[a] += wq * (T)P.gh_a[qi[a]] * gz[a];
+                    }
+                    // scatter the transposed row into mu
+                    long long base = I.node_off;
+                    for (int a = 0; a < D; ++a) base += (long long)k[a] * I.stride[a];
+                    for (int cb = 0; cb < (1 << D); ++cb) {
+                        long long o = base;
+                        T wv = Lw;
+                        for (int a = 0; a < D; ++a) {
+                            const int bit = (cb >> (D - 1 - a)) & 1;
+                            o += bit * I.stride[a];
+                            wv *= bit ? B[a].v1 : B[a].v0;
+                        }
+                        atomicAdd(&mu[o * PS], wv);
+                        for (int a = 0; a < D; ++a) {
+                            T ws = Lw;
+                            for (int i = 0; i < D; ++i) {
+                                const int bit = (cb >> (D - 1 - i)) & 1;
+                                if (i == a) ws *= bit ? B[i].d1 : B[i].d0;
+                                else ws *= bit ? B[i].v1 : B[i].v0;
+                            }
+                            atomicAdd(&mu[o * PS + 1 + a], ws);
+                        }
+                    }
+                }
+                double db[12];
+                const int nt = drift_dtheta(I, tf, P.trig, idx, db);
+                for (int kk = 0; kk < nt; ++kk) {
+                    double sdot = 0.0;
+                    for (int a = 0; a < D; ++a) sdot += (double)Gz[a] * db[kk * 3 + a];
+                    gth[kk] = (double)L * P.dt * sdot;
+                }
+                double sd = 0.0;
+                for (int a = 0; a < D; ++a) sd += (double)Hz[a];
+                gth[nt] = (double)L * sd * I.dSdD;
+            }
+        }
+        // block reduction of the parameter gradient, one atomic per entry
+        const int wave = threadIdx.x / 64, wl = threadIdx.x % 64;
+        for (int kk = 0; kk < kThetaSlots; ++kk) {
+            double v = gth[kk];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (wl == 0) red[wave][kk] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < kThetaSlots) {
+            double v = 0.0;
+            for (int wv = 0; wv < kBlock / 64; ++wv) v += red[wv][threadIdx.x];
+            if (v != 0.0) atomicAdd(&grad[it.inst * kThetaSlots + threadIdx.x], v);
+        }
+        __syncthreads();
+    }
+}
+
+// lam^{n+1} += J_F(u)^T mu_g (scatter over each node's slope stencil);
+// lam_next must hold mu_u on entry.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_adjoint_slopes_T(PlanDev P, const T *__restrict__ u,
+                                                             const T *__restrict__ mu,
+                                                             T *__restrict__ lam_next)
+{
+    constexpr int PS = RecStride<D>::value;
+    const WorkRange wr = work_range(0, P.n_node_work);
+    for (int w = wr.begin; w < wr.end; w += wr.step) {
+        const WorkItem it = P.node_work[w];
+        if ((int)threadIdx.x >= it.count) continue;
+        const DevInst &I = P.inst[it.inst];
+        const int node = it.first + threadIdx.x;
+        int idx[3];
+        split_node<D>(I, node, idx);
+        const T *ui = u + I.node_off;
+        T *li = lam_next + I.node_off;
+        for (int a = 0; a < D; ++a) {
+            const T m = mu[(I.node_off + node) * PS + 1 + a];
+            if (m == T(0)) continue;
+            const int na = I.n[a];
+            const double *x = P.coords + I.coord_off[a];
+            const int i = idx[a];
+            int il, ic, ir;
+            double hl, hr;
+            if (I.periodic[a]) {
+                ic = (i == na - 1) ? 0 : i;
+                il = (ic == 0) ? na - 2 : ic - 1;
+                ir = ic + 1;
+                hl = (ic == 0) ? x[na - 1] - x[na - 2] : x[ic] - x[ic - 1];
+                hr = x[ic + 1] - x[ic];
+            } else if (i == 0) {
+                il = 0; ic = 1; ir = 2;
+                hl = x[1] - x[0]; hr = x[2] - x[1];
+            } else if (i == na - 1) {
+                il = na - 3; ic = na - 2; ir = na - 1;
+                hl = x[na - 2] - x[na - 3]; hr = x[na - 1] - x[na - 2];
+            } else {
+                il = i - 1; ic = i; ir = i + 1;
+                hl = x[i] - x[i - 1]; hr = x[i + 1] - x[i];
+            }
+            const long long base = node - (long long)i * I.stride[a];
+            const long long nl = base + (long long)il * I.stride[a];
+            const long long nc = base + (long long)ic * I.stride[a];
+            const long long nr = base + (long long)ir * I.stride[a];
+            const T dl = (ui[nc] - ui[nl]) / (T)hl;
+            const T dr = (ui[nr] - ui[nc]) / (T)hr;
+            if (!(dl * dr > T(0))) continue;
+            const T den = (dl + dr) * (dl + dr);
+            const T gdl = T(2) * dr * dr / den;
+            const T gdr = T(2) * dl * dl / den;
+            atomicAdd(&li[nl], m * (-gdl / (T)hl));
+            atomicAdd(&li[nc], m * (gdl / (T)hl - gdr / (T)hr));
+            atomicAdd(&li[nr], m * (gdr / (T)hr));
+        }
+    }
+}
+
+// lam <- mu_u (field 0 of the records).
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_mu_value(PlanDev P, const T *__restrict__ mu,
+                                                     T *__restrict__ lam)
+{
+    constexpr int PS = RecStride<D>::value;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < P.n_nodes;
+         i += (long long)gridDim.x * blockDim.x)
+        lam[i] = mu[i * PS];
+}
+
+// Exit nodes carry no sensitivity; a periodic image passes its cotangent to
+// the node it copies.  cls: 0 active, 1 exit, 2 image of an active node,
+// 3 image of an exit node.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_fold_images(PlanDev P, T *__restrict__ lam)
+{
+    const WorkRange wr = work_range(0, P.n_node_work);
+    for (int w = wr.begin; w < wr.end; w += wr.step) {
+        const WorkItem it = P.node_work[w];
+        if ((int)threadIdx.x >= it.count) continue;
+        const DevInst &I = P.inst[it.inst];
+        const int node = it.first + threadIdx.x;
+        const long long g = I.node_off + node;
+        const unsigned char c = P.chi[g];
+        if (c == 0) continue;
+        if (c == 2) {
+            int idx[3];
+            split_node<D>(I, node, idx);
+            long long rep = node;
+            for (int a = 0; a < D; ++a)
+                if (I.periodic[a] && idx[a] == I.n[a] - 1)
+                    rep -= (long long)(I.n[a] - 1) * I.stride[a];
+            atomicAdd(&lam[I.node_off + rep], lam[g]);
+        }
+        lam[g] = T(0);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+#define FK_DISPATCH_G(G_, ...)                                   \
+    switch (G_) {                                                \
+    case 1: { constexpr int G = 1; __VA_ARGS__; } break;         \
+    case 2: { constexpr int G = 2; __VA_ARGS__; } break;         \
+    case 4: { constexpr int G = 4; __VA_ARGS__; } break;         \
+    case 8: { constexpr int G = 8; __VA_ARGS__; } break;         \
+    case 16: { constexpr int G = 16; __VA_ARGS__; } break;       \
+    case 32: { constexpr int G = 32; __VA_ARGS__; } break;       \
+    case 64: { constexpr int G = 64; __VA_ARGS__; } break;       \
+    default: return hipErrorInvalidValue;                        \
+    }
+
+#define FK_DISPATCH_D(D_, ...)                                   \
+    switch (D_) {                                                \
+    case 1: { constexpr int D = 1; __VA_ARGS__; } break;         \
+    case 2: { constexpr int D = 2; __VA_ARGS__; } break;         \
+    case 3: { constexpr int D = 3; __VA_ARGS__; } break;         \
+    default: return hipErrorInvalidValue;                        \
+    }
+
+static int flat_grid(long long n)
+{
+    long long g = (n + kBlock - 1) / kBlock;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+hipError_t launch_init_field(const PlanDev &P, bool f32, void *u, hipStream_t s)
+{
+    if (f32)
+        k_init_field<float><<<flat_grid(P.n_nodes), kBlock, 0, s>>>(P.chi, P.n_nodes, (float *)u);
+    else
+        k_init_field<double><<<flat_grid(P.n_nodes), kBlock, 0, s>>>(P.chi, P.n_nodes, (double *)u);
+    return hipGetLastError();
+}
+
+hipError_t launch_slopes(const PlanDev &P, bool f32, int n, const void *u, void *packed,
+                         hipStream_t s)
+{
+    FK_DISPATCH_D(P.d,
+        if (f32) k_slopes<float, D><<<P.slope_grid, kBlock, 0, s>>>(P, n, 0, P.n_slope_work, (const float *)u, (float *)packed);
+        else k_slopes<double, D><<<P.slope_grid, kBlock, 0, s>>>(P, n, 0, P.n_slope_work, (const double *)u, (double *)packed));
+    return hipGetLastError();
+}
+
+hipError_t launch_tables(const PlanDev &P, int n, hipStream_t s)
+{
+    if (P.n_table_work == 0) return hipSuccess;
+    const int g = P.n_table_work >= 8 ? (P.n_table_work + 7) / 8 * 8 : P.n_table_work;
+    FK_DISPATCH_D(P.d,
+        k_slopes<double, D><<<g, kBlock, 0, s>>>(P, n, 0, P.n_table_work, nullptr, nullptr));
+    return hipGetLastError();
+}
+
+template <typename T, int D, int G, int NQ>
+static void step_fused_launch(const PlanDev &P, int n, const void *packed, void *u_out,
+                              hipStream_t s)
+{
+    k_step_fused<T, D, G, NQ><<<P.act_grid, kBlock, 0, s>>>(
+        P, n, P.inst, P.act_work, P.active, P.trig, P.coords, (const T *)packed, (T *)u_out);
+}
+
+template <typename T, int D>
+static hipError_t step_fused_dispatch(const PlanDev &P, int n, const void *packed, void *u_out,
+                                      hipStream_t s)
+{
+    const int nq = (P.n_quad + P.group - 1) / P.group;
+    switch (P.group) {
+    case 1: step_fused_launch<T, D, 1, 1>(P, n, packed, u_out, s); break;
+    case 2: step_fused_launch<T, D, 2, 1>(P, n, packed, u_out, s); break;
+    case 4: step_fused_launch<T, D, 4, 1>(P, n, packed, u_out, s); break;
+    case 8: step_fused_launch<T, D, 8, 1>(P, n, packed, u_out, s); break;
+    case 16: step_fused_launch<T, D, 16, 1>(P, n, packed, u_out, s); break;
+    case 32: step_fused_launch<T, D, 32, 1>(P, n, packed, u_out, s); break;
+    case 64:
+        if (nq <= 1) step_fused_launch<T, D, 64, 1>(P, n, packed, u_out, s);
+        else if (nq <= 2) step_fused_launch<T, D, 64, 2>(P, n, packed, u_out, s);
+        else if (nq <= 4) step_fused_launch<T, D, 64, 4>(P, n, packed, u_out, s);
+        else return hipErrorInvalidValue;
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step_fused(const PlanDev &P, bool f32, int n, const void *packed, void *u_out,
+                             hipStream_t s)
+{
+    FK_DISPATCH_D(P.d,
+        return f32 ? step_fused_dispatch<float, D>(P, n, packed, u_out, s)
+                   : step_fused_dispatch<double, D>(P, n, packed, u_out, s));
+    return hipSuccess;
+}
+
+hipError_t launch_assemble_ell(const PlanDev &P, bool f32, int n, int *cols, void *vals,
+                               void *exit_mass, hipStream_t s)
+{
+    const size_t lds = (size_t)(kBlock / P.group) * P.ell_width * (f32 ? 4 : 8);
+    FK_DISPATCH_D(P.d, FK_DISPATCH_G(P.group,
+        if (f32) k_assemble_ell<float, D, G><<<P.act_grid, kBlock, lds, s>>>(P, n, cols, (float *)vals, (float *)exit_mass);
+        else k_assemble_ell<double, D, G><<<P.act_grid, kBlock, lds, s>>>(P, n, cols, (double *)vals, (double *)exit_mass)));
+    return hipGetLastError();
+}
+
+hipError_t launch_ell_apply(const PlanDev &P, bool f32, const int *cols, const void *vals,
+                            const void *exit_mass, const void *packed, void *u_out, hipStream_t s)
+{
+    FK_DISPATCH_D(P.d,
+        if (f32) k_ell_apply<float, D><<<P.row_grid, kBlock, 0, s>>>(P, cols, (const float *)vals, (const float *)exit_mass, (const float *)packed, (float *)u_out);
+        else k_ell_apply<double, D><<<P.row_grid, kBlock, 0, s>>>(P, cols, (const double *)vals, (const double *)exit_mass, (const double *)packed, (double *)u_out));
+    return hipGetLastError();
+}
+
+hipError_t launch_export_ell(const PlanDev &P, bool f32, const int *cols_in, int *cols_out,
+                             hipStream_t s)
+{
+    (void)f32;
+    FK_DISPATCH_D(P.d,
+        k_export_ell_cols<D><<<flat_grid(P.n_active * (long long)P.ell_width), kBlock, 0, s>>>(P, cols_in, cols_out));
+    return hipGetLastError();
+}
+
+hipError_t launch_export_cells(const PlanDev &P, int inst, int n, int *cells,
+                               unsigned char *exit_flags, hipStream_t s)
+{
+    FK_DISPATCH_D(P.d,
+        k_export_cells<D><<<4096, kBlock, 0, s>>>(P, inst, n, cells, exit_flags));
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_flags(const PlanDev &P, hipStream_t s)
+{
+    k_clear_flags<<<1, 1, 0, s>>>(P.flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s)
+{
+    const long long n = (long long)(bytes / 4);
+    k_zero<<<flat_grid(n), kBlock, 0, s>>>((unsigned int *)p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step(const PlanDev &P, bool f32, int n, const void *packed,
+                               const void *lam, void *mu, double *grad, hipStream_t s)
+{
+    FK_DISPATCH_D(P.d, FK_DISPATCH_G(P.group,
+        if (f32) k_adjoint_step<float, D, G><<<P.act_grid, kBlock, 0, s>>>(P, n, (const float *)packed, (const float *)lam, (float *)mu, grad);
+        else k_adjoint_step<double, D, G><<<P.act_grid, kBlock, 0, s>>>(P, n, (const double *)packed, (const double *)lam, (double *)mu, grad)));
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_slopes_T(const PlanDev &P, bool f32, const void *u, const void *mu,
+                                   void *lam_next, hipStream_t s)
+{
+    FK_DISPATCH_D(P.d,
+        if (f32) {
+            k_mu_value<float, D><<<flat_grid(P.n_nodes), kBlock, 0, s>>>(P, (const float *)mu, (float *)lam_next);
+            k_adjoint_slopes_T<float, D><<<P.node_grid, kBlock, 0, s>>>(P, (const float *)u, (const float *)mu, (float *)lam_next);
+            k_fold_images<float, D><<<P.node_grid, kBlock, 0, s>>>(P, (float *)lam_next);
+        } else {
+            k_mu_value<double, D><<<flat_grid(P.n_nodes), kBlock, 0, s>>>(P, (const double *)mu, (double *)lam_next);
+            k_adjoint_slopes_T<double, D><<<P.node_grid, kBlock, 0, s>>>(P, (const double *)u, (const double *)mu, (double *)lam_next);
+            k_fold_images<double, D><<<P.node_grid, kBlock, 0, s>>>(P, (double *)lam_next);
+        });
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_init(const PlanDev &P, bool f32, const void *lam0, void *lam,
+                               hipStream_t s)
+{
+    hipError_t e = hipMemcpyAsync(lam, lam0, (size_t)P.n_nodes * (f32 ? 4 : 8),
+                                  hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    FK_DISPATCH_D(P.d,
+        if (f32) k_fold_images<float, D><<<P.node_grid, kBlock, 0, s>>>(P, (float *)lam);
+        else k_fold_images<double, D><<<P.node_grid, kBlock, 0, s>>>(P, (double *)lam));
+    return hipGetLastError();
+}
+
+}  // namespace fk
