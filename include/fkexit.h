@@ -111,7 +111,14 @@ typedef struct {
     int use_graph;   /* nonzero: capture the N-step loop once and replay it */
     int ckpt_every;  /* adjoint checkpoint interval K (0 = no adjoint storage) */
     int block;       /* threads per workgroup, 0 = library default */
-    int reserved[3];
+    int step_kernel; /* fused step layout: 0 = auto; 1 = one thread per node;
+                        2 = a lane group per node over the tensor points (any gh_q);
+                        3 = Q* lanes per node over the outermost axis.  1 and 3
+                        exist for d=1: gh_q 2..8,10,12,16; d=2: 2..8; d=3: 2..6
+                        (FK_ERR_UNSUPPORTED otherwise).  auto picks 1 for plans
+                        with many active nodes, 3 for small ones, 2 when 1/3
+                        are not compiled for gh_q */
+    int reserved[2];
 } fk_options;
 
 typedef struct {

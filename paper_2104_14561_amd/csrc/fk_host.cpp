@@ -153,10 +153,10 @@ struct fk_plan {
     std::vector<double> coords;
     std::vector<int> active;
     std::vector<unsigned char> cls;
-    std::vector<double> gh_a, gh_w;
-    std::vector<float> gh_wf;
+    std::vector<double> gh_a, gh_w, gh_w1;
+    std::vector<float> gh_wf, gh_w1f;
     std::vector<double> tfac;
-    std::vector<fk::WorkItem> slope_work, node_work, act_work, row_work;
+    std::vector<fk::WorkItem> slope_work, node_work, act_work, row_work, split_work;
     int n_table_work = 0;
     std::vector<int64_t> node_off, act_count;
     long long n_nodes = 0, n_active = 0;
@@ -323,7 +323,10 @@ fk_status build_plan(fk_plan *p)
     p->t0 = p0.t0;
     p->Q = 1;
     for (int a = 0; a < p->d; ++a) p->Q *= p->qs;
-    p->G = std::min(64, group_of(p->Q));
+    // lanes per active node: the tensor points spread over at most one wave, and
+    // at least d Q* lanes for the per-axis staging of the step pass
+    p->G = std::max(4, std::min(64, group_of(p->Q)));
+    if (p->d * p->qs > p->G) return fail(FK_ERR_UNSUPPORTED, "d * gh_q above the lane group");
     p->n_theta = (p0.coef_kind == FK_COEF_CONST) ? p->d + 1 : (p0.coef_kind == FK_COEF_CELLULAR2D ? 4 : 5);
     if ((long long)p->Q > 256) return fail(FK_ERR_UNSUPPORTED, "Q = gh_q^d above 256");
 
@@ -331,6 +334,8 @@ fk_status build_plan(fk_plan *p)
     std::vector<double> w1(p->qs);
     fk_status st = gh_rule_impl(p->qs, p->gh_a.data(), w1.data());
     if (st != FK_OK) return st;
+    p->gh_w1 = w1;
+    p->gh_w1f.assign(w1.begin(), w1.end());
     p->gh_w.assign(p->Q, 0.0);
     p->gh_wf.assign(p->Q, 0.0f);
     for (int q = 0; q < p->Q; ++q) {
@@ -468,6 +473,7 @@ fk_status build_plan(fk_plan *p)
         build_work(p->node_work, i, (int)J, kBlock);
         build_work(p->act_work, i, na, npb);
         build_work(p->row_work, i, na, kBlock);
+        build_work(p->split_work, i, na, kBlock / std::max(2, group_of(p->qs)));
         p->n_nodes += J;
         p->n_active += na;
 
@@ -529,12 +535,15 @@ fk_status build_plan(fk_plan *p)
     add_region(p, "gh_a", sizeof(double) * p->gh_a.size());
     add_region(p, "gh_w", sizeof(double) * p->gh_w.size());
     add_region(p, "gh_wf", sizeof(float) * p->gh_wf.size());
+    add_region(p, "gh_w1", sizeof(double) * p->gh_w1.size());
+    add_region(p, "gh_w1f", sizeof(float) * p->gh_w1f.size());
     add_region(p, "tfac", sizeof(double) * p->tfac.size());
     add_region(p, "trig", sizeof(double) * 2 * std::max<size_t>(p->coords.size(), 1));
     add_region(p, "slope_work", sizeof(fk::WorkItem) * std::max<size_t>(p->slope_work.size(), 1));
     add_region(p, "node_work", sizeof(fk::WorkItem) * std::max<size_t>(p->node_work.size(), 1));
     add_region(p, "act_work", sizeof(fk::WorkItem) * std::max<size_t>(p->act_work.size(), 1));
     add_region(p, "row_work", sizeof(fk::WorkItem) * std::max<size_t>(p->row_work.size(), 1));
+    add_region(p, "split_work", sizeof(fk::WorkItem) * std::max<size_t>(p->split_work.size(), 1));
     add_region(p, "flags", 64);
     const size_t fb = elt(p) * (size_t)p->n_nodes;
     add_region(p, "uA", fb);
@@ -569,12 +578,17 @@ void fill_dev(fk_plan *p)
     D.gh_a = (const double *)p->at("gh_a");
     D.gh_w = (const double *)p->at("gh_w");
     D.gh_wf = (const float *)p->at("gh_wf");
+    D.gh_w1 = (const double *)p->at("gh_w1");
+    D.gh_w1f = (const float *)p->at("gh_w1f");
     D.tfac = (const double *)p->at("tfac");
     D.trig = (double2 *)p->at("trig");
     D.slope_work = (const fk::WorkItem *)p->at("slope_work");
     D.node_work = (const fk::WorkItem *)p->at("node_work");
     D.act_work = (const fk::WorkItem *)p->at("act_work");
     D.row_work = (const fk::WorkItem *)p->at("row_work");
+    D.split_work = (const fk::WorkItem *)p->at("split_work");
+    D.n_split_work = (int)p->split_work.size();
+    D.split_grid = grid_for(p->split_work.size());
     D.flags = (int *)p->at("flags");
     D.n_inst = p->n_inst;
     D.n_slope_work = (int)p->slope_work.size();
@@ -588,6 +602,16 @@ void fill_dev(fk_plan *p)
     D.n_steps = p->N;
     D.block = kBlock;
     D.group = p->G;
+    D.all_affine = 1;
+    for (const fk::DevInst &I : p->inst)
+        for (int a = 0; a < p->d; ++a)
+            if (!I.affine[a]) D.all_affine = 0;
+    // auto: one thread per node once there are enough nodes to fill the chip
+    // (about 2 waves per SIMD), else split each node over Q* lanes
+    if (p->opt.step_kernel == 2) D.step_kind = 1;
+    else if (p->opt.step_kernel == 3) D.step_kind = 2;
+    else if (p->opt.step_kernel == 1) D.step_kind = 0;
+    else D.step_kind = (p->n_active >= 256LL * 4 * 64 * 2) ? 0 : 2;
     D.slope_grid = grid_for(p->slope_work.size());
     D.node_grid = grid_for(p->node_work.size());
     D.act_grid = grid_for(p->act_work.size());
@@ -755,6 +779,10 @@ fk_status fk_plan_create(const fk_problem *probs, int n_inst, const fk_options *
         return fail(FK_ERR_ARG, "form must be FK_FORM_FUSED or FK_FORM_ELL");
     if (o.ckpt_every < 0) return fail(FK_ERR_ARG, "ckpt_every must be >= 0");
     if (o.block != 0 && o.block != kBlock) return fail(FK_ERR_UNSUPPORTED, "block must be 0 or 256");
+    if (o.step_kernel < 0 || o.step_kernel > 3) return fail(FK_ERR_ARG, "step_kernel must be 0..3");
+    if ((o.step_kernel == 1 || o.step_kernel == 3) && !fk::step_node_compiled(probs[0].d, probs[0].gh_q))
+        return fail(FK_ERR_UNSUPPORTED, "no thread-per-node kernel compiled for d=%d, gh_q=%d",
+                    probs[0].d, probs[0].gh_q);
     for (int i = 0; i < n_inst; ++i) FK_TRY(validate(probs[i], i));
     const fk_problem &a = probs[0];
     for (int i = 1; i < n_inst; ++i) {
@@ -848,11 +876,14 @@ fk_status fk_plan_set_workspace(fk_plan *p, void *dev_ptr, size_t bytes, void *s
     FK_TRY(up("gh_a", p->gh_a.data(), sizeof(double) * p->gh_a.size()));
     FK_TRY(up("gh_w", p->gh_w.data(), sizeof(double) * p->gh_w.size()));
     FK_TRY(up("gh_wf", p->gh_wf.data(), sizeof(float) * p->gh_wf.size()));
+    FK_TRY(up("gh_w1", p->gh_w1.data(), sizeof(double) * p->gh_w1.size()));
+    FK_TRY(up("gh_w1f", p->gh_w1f.data(), sizeof(float) * p->gh_w1f.size()));
     FK_TRY(up("tfac", p->tfac.data(), sizeof(double) * p->tfac.size()));
     FK_TRY(up("slope_work", p->slope_work.data(), sizeof(fk::WorkItem) * p->slope_work.size()));
     FK_TRY(up("node_work", p->node_work.data(), sizeof(fk::WorkItem) * p->node_work.size()));
     FK_TRY(up("act_work", p->act_work.data(), sizeof(fk::WorkItem) * p->act_work.size()));
     FK_TRY(up("row_work", p->row_work.data(), sizeof(fk::WorkItem) * p->row_work.size()));
+    FK_TRY(up("split_work", p->split_work.data(), sizeof(fk::WorkItem) * p->split_work.size()));
     FK_LAUNCH(fk::launch_clear_flags(p->dev, s));
     FK_HIP(hipStreamSynchronize(s));
     return FK_OK;

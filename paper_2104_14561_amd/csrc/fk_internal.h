@@ -54,6 +54,8 @@ struct PlanDev {
     const double *gh_a;         // 1D GH nodes (Q*)
     const double *gh_w;         // tensor weights (Q), double
     const float *gh_wf;         // tensor weights (Q), float
+    const double *gh_w1;        // 1D weights (Q*), double
+    const float *gh_w1f;        // 1D weights (Q*), float
     const double *tfac;         // [n_steps][n_inst][kTimeFactors]
     double2 *trig;              // per-axis (sin, cos) of the drift arguments at t_n
     const WorkItem *slope_work; // trig table items, then node runs near active nodes
@@ -73,6 +75,11 @@ struct PlanDev {
     int n_steps;
     int block;                  // threads per workgroup
     int group;                  // lanes per active node in the step passes
+    int step_kind;              // 0: thread per node, 1: lane group, 2: split node
+    int all_affine;             // every axis of every instance is affine
+    const WorkItem *split_work; // chunks of block / pow2(Q*) active nodes
+    int n_split_work;
+    int split_grid;
     int slope_grid;             // workgroups of the slope pass
     int node_grid;              // workgroups of all-node passes
     int act_grid;               // workgroups of the step pass
@@ -95,6 +102,7 @@ hipError_t launch_slopes(const PlanDev &P, bool f32, int n, const void *u, void 
 hipError_t launch_tables(const PlanDev &P, int n, hipStream_t s);
 hipError_t launch_step_fused(const PlanDev &P, bool f32, int n, const void *packed,
                              void *u_out, hipStream_t s);
+bool step_node_compiled(int d, int qs);
 hipError_t launch_assemble_ell(const PlanDev &P, bool f32, int n, int *cols, void *vals,
                                void *exit_mass, hipStream_t s);
 hipError_t launch_ell_apply(const PlanDev &P, bool f32, const int *cols, const void *vals,

@@ -152,6 +152,54 @@ __device__ inline AxisEval eval_axis(const DevInst &I, const double *coords, int
     return e;
 }
 
+// Axis evaluation for an affine axis (x_k = k * step + lo exactly, x_{n-1} =
+// hi): the floor guess and the exact one-step fix-ups without loads or loops.
+__device__ inline AxisEval eval_axis_affine(const DevInst &I, int a, double c, double ga)
+{
+#pragma clang fp contract(off)
+    double z = c + I.S * ga;
+    const double lo = I.lo[a], hi = I.hi[a];
+    if (I.periodic[a]) {
+        if (z >= hi) z = z - I.period[a];
+        else if (z < lo) z = z + I.period[a];
+    }
+    AxisEval e;
+    e.ex = !I.periodic[a] && (z <= lo || z >= hi);
+    const double t = z - I.center[a];
+    e.dz2 = t * t;
+    const int n = I.n[a];
+    const double step = I.step[a];
+    const double f = floor((z - lo) * I.inv_h[a]);
+    int k = (f >= 0.0) ? ((f <= (double)(n - 2)) ? (int)f : n - 2) : 0;
+    const double xk1 = (k + 1 == n - 1) ? hi : (double)(k + 1) * step + lo;
+    if (k < n - 2 && xk1 <= z) ++k;
+    double xk = (double)k * step + lo;
+    if (k > 0 && xk > z) {
+        --k;
+        xk = (double)k * step + lo;
+    }
+    e.k = k;
+    e.h = step;
+    e.s = (z - xk) * I.inv_h[a];
+    return e;
+}
+
+template <bool AFF>
+__device__ inline AxisEval eval_axis_t(const DevInst &I, const double *coords, int a, double c,
+                                       double ga)
+{
+    if constexpr (AFF) return eval_axis_affine(I, a, c, ga);
+    else return eval_axis(I, coords, a, c, ga);
+}
+
+__device__ inline bool ball_exit2(double a, double b, double r2)
+{
+#pragma clang fp contract(off)
+    double s = a;
+    s = s + b;
+    return s >= r2;
+}
+
 __device__ inline bool ball_exit(const double *dz2, int d, double r2)
 {
 #pragma clang fp contract(off)
@@ -460,6 +508,10 @@ template <typename T> __device__ inline const T *weights(const PlanDev &P);
 template <> __device__ inline const double *weights<double>(const PlanDev &P) { return P.gh_w; }
 template <> __device__ inline const float *weights<float>(const PlanDev &P) { return P.gh_wf; }
 
+template <typename T> __device__ inline const T *weights1(const PlanDev &P);
+template <> __device__ inline const double *weights1<double>(const PlanDev &P) { return P.gh_w1; }
+template <> __device__ inline const float *weights1<float>(const PlanDev &P) { return P.gh_w1f; }
+
 __device__ inline const double *time_factors(const PlanDev &P, int n, int inst)
 {
     return P.tfac + ((long long)n * P.n_inst + inst) * kTimeFactors;
@@ -549,10 +601,42 @@ __global__ void __launch_bounds__(kBlock) k_slopes(PlanDev P, int n, int first, 
     }
 }
 
-// Fused step pass (matrix-free form of Eq. (e36)).  The read-only tables
-// come in as separate restrict-qualified arguments so that per-instance and
-// per-work-item fields are fetched with scalar loads; each lane's quadrature
-// points (at most NQ per lane) are decoded once per launch.
+// Per-axis data of one landing coordinate, shared through LDS by the lanes of
+// a node's group.  The tensor rule makes every per-axis quantity depend only on
+// (axis, 1D Gauss-Hermite index), so a node needs d Q* of these, not d Q.
+template <typename T> struct AxisRec {
+    int k;        // cell
+    int ex;       // left the box on this axis
+    double dz2;   // (z - centre)^2
+    T v0, v1, d0, d1;
+};
+
+// Fills the node's axis records: lane l < d Q* evaluates axis l / Q* at GH
+// index l % Q*.
+template <typename T, int D>
+__device__ inline void stage_axes(const DevInst &I, const double *coords, const double *gh_a,
+                                  int qs, const double *c, int lane, AxisRec<T> *tab)
+{
+    if (lane < D * qs) {
+        const int a = lane / qs, qa = lane - a * qs;
+        const double ca = (D == 1 || a == 0) ? c[0] : (a == 1 ? c[1] : c[2]);
+        const AxisEval e = eval_axis(I, coords, a, ca, gh_a[qa]);
+        const Basis<T> B = hermite<T>(e.s, e.h);
+        AxisRec<T> r;
+        r.k = e.k;
+        r.ex = e.ex ? 1 : 0;
+        r.dz2 = e.dz2;
+        r.v0 = B.v0; r.v1 = B.v1; r.d0 = B.d0; r.d1 = B.d1;
+        tab[lane] = r;
+    }
+}
+
+// Fused step pass (matrix-free form of Eq. (e36)).  A group of G lanes serves
+// one active node: its d Q* axis evaluations are staged in LDS, then lane l
+// assembles the tensor points q = l, l + G, ... (at most NQ), gathers the cell
+// corners' records and contracts them with the tensor Hermite weights.  The
+// read-only tables come in as restrict-qualified arguments so that
+// per-instance fields are fetched with scalar loads.
 template <typename T, int D, int G, int NQ>
 __global__ void __launch_bounds__(kBlock) k_step_fused(
     const PlanDev P, int n, const DevInst *__restrict__ insts,
@@ -562,12 +646,16 @@ __global__ void __launch_bounds__(kBlock) k_step_fused(
 {
     constexpr int PS = RecStride<D>::value;
     using R = typename RecT<T, PS>::type;
+    constexpr int NPB = kBlock / G;
+    __shared__ AxisRec<T> tabs[NPB][G];
     const R *rec = reinterpret_cast<const R *>(packed);
     const int lane = threadIdx.x % G;
     int slot = threadIdx.x / G;
     if (G == 64) slot = __builtin_amdgcn_readfirstlane(slot);
-    // this lane's quadrature points q = lane + i G
-    double aq[NQ][3];
+    AxisRec<T> *tab = tabs[slot];
+    const int qs = P.qs;
+    // this lane's tensor points q = lane + i G: per-axis GH indices and weight
+    int qa[NQ][3];
     T wq[NQ];
     bool has[NQ];
 #pragma unroll
@@ -577,8 +665,8 @@ __global__ void __launch_bounds__(kBlock) k_step_fused(
         if (!has[i]) q = 0;
         wq[i] = has[i] ? weights<T>(P)[q] : T(0);
         for (int a = D - 1; a >= 0; --a) {
-            aq[i][a] = P.gh_a[q % P.qs];
-            q /= P.qs;
+            qa[i][a] = a * qs + q % qs;
+            q /= qs;
         }
     }
     const WorkRange wr = work_range(0, P.n_act_work);
@@ -595,18 +683,35 @@ __global__ void __launch_bounds__(kBlock) k_step_fused(
             uref = rec[I.node_off + node].x;
             double c[3];
             node_centre<D>(I, coords, time_factors(P, n, it.inst), trig, idx, P.dt, c);
+            stage_axes<T, D>(I, coords, P.gh_a, qs, c, lane, tab);
+        }
+        __syncthreads();
+        if (valid) {
+            const bool ball = I.region_kind == 1;
 #pragma unroll
             for (int i = 0; i < NQ; ++i) {
                 if (!has[i]) continue;
-                int k[3];
-                double s[3], h[3];
-                const bool ex = landing_point_a<D>(I, coords, c, aq[i], k, s, h);
+                AxisRec<T> ar[3];
+                bool ex = false;
+                double dz2[3];
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    ar[a] = tab[qa[i][a]];
+                    ex = ex || ar[a].ex;
+                    dz2[a] = ar[a].dz2;
+                }
+                if (ball) ex = ex || ball_exit(dz2, D, I.r2);
                 if (ex) {
                     acc += wq[i] * (T(1) - uref);
                 } else {
                     Basis<T> B[3];
+                    int k[3];
 #pragma unroll
-                    for (int a = 0; a < D; ++a) B[a] = hermite<T>(s[a], h[a]);
+                    for (int a = 0; a < D; ++a) {
+                        k[a] = ar[a].k;
+                        B[a].v0 = ar[a].v0; B[a].v1 = ar[a].v1;
+                        B[a].d0 = ar[a].d0; B[a].d1 = ar[a].d1;
+                    }
                     R p[1 << D];
                     gather_corners<D, R>(rec, I, k, p);
                     acc += wq[i] * hermite_value<T, D, R>(p, B, uref);
@@ -619,6 +724,171 @@ __global__ void __launch_bounds__(kBlock) k_step_fused(
             flag_nonfinite(P.flags, v);
             store_node<D, T>(I, idx, node, v, u_out);
         }
+        __syncthreads();
+    }
+}
+
+// Thread-per-node fused step (the main path).  Lane = active node; the
+// innermost axis' QS landing coordinates (cell, Hermite basis, exit flag and
+// ball distance) are evaluated once per node and kept in registers, the outer
+// axes are looped.  Consecutive lanes are consecutive nodes along the fastest
+// axis, so one gather instruction of a wave reads neighbouring records.  The
+// exit mass is summed over exiting points only (zero when none exits), so the
+// rounding of FP32 weights never biases nodes far from the exit region.
+//
+// G > 1 (small plans): G lanes share a node, lane l taking the outermost
+// axis' indices l, l + G, ...; the lane sums are combined by a shuffle tree.
+template <typename T, int D, int QS, int G, bool AFF>
+__global__ void __launch_bounds__(kBlock) k_step_node(
+    const PlanDev P, int n, int n_work, const DevInst *__restrict__ insts,
+    const WorkItem *__restrict__ work, const int *__restrict__ active,
+    const double2 *__restrict__ trig, const double *__restrict__ coords,
+    const T *__restrict__ packed, T *__restrict__ u_out)
+{
+    constexpr int PS = RecStride<D>::value;
+    using R = typename RecT<T, PS>::type;
+    const R *rec = reinterpret_cast<const R *>(packed);
+    const double *ga = P.gh_a;
+    const T *w1 = weights1<T>(P);
+    T wsum = T(0);
+#pragma unroll
+    for (int q = 0; q < QS; ++q) wsum += w1[q];
+    const int lane = (G > 1) ? (int)(threadIdx.x % G) : 0;
+    const int slot = (G > 1) ? (int)(threadIdx.x / G) : (int)threadIdx.x;
+    const WorkRange wr = work_range(0, n_work);
+    for (int w = wr.begin; w < wr.end; w += wr.step) {
+        const WorkItem it = work[w];
+        if (G == 1 && slot >= it.count) continue;
+        const bool valid = slot < it.count;
+        const DevInst &I = insts[it.inst];
+        const int node = valid ? active[I.act_off + it.first + slot] : active[I.act_off + it.first];
+        int idx[3];
+        split_node<D>(I, node, idx);
+        const T uref = rec[I.node_off + node].x;
+        double c[3];
+        node_centre<D>(I, coords, time_factors(P, n, it.inst), trig, idx, P.dt, c);
+        const bool ball = I.region_kind == 1;
+        const double r2 = I.r2;
+        // innermost axis, hoisted
+        constexpr int AI = D - 1;
+        int kin[QS];
+        T bin[QS][4];
+        bool exin[QS];
+        double din[QS];
+#pragma unroll
+        for (int q = 0; q < QS; ++q) {
+            const AxisEval e = eval_axis_t<AFF>(I, coords, AI, c[AI], ga[q]);
+            const Basis<T> B = hermite<T>(e.s, e.h);
+            kin[q] = e.k;
+            bin[q][0] = B.v0; bin[q][1] = B.v1; bin[q][2] = B.d0; bin[q][3] = B.d1;
+            exin[q] = e.ex;
+            din[q] = e.dz2;
+        }
+        T acc = T(0), emass = T(0);
+        if constexpr (D == 1) {
+#pragma unroll
+            for (int q = 0; q < QS; ++q) {
+                if (G > 1 && (q % G) != lane) continue;
+                const bool ex = exin[q] || (ball && din[q] >= r2);
+                if (ex) {
+                    emass += w1[q];
+                    continue;
+                }
+                const long long base = I.node_off + kin[q];
+                const R p0 = rec[base], p1 = rec[base + 1];
+                const T v = (p0.x - uref) * bin[q][0] + (p1.x - uref) * bin[q][1] +
+                            p0.y * bin[q][2] + p1.y * bin[q][3];
+                acc += w1[q] * v;
+            }
+        } else if constexpr (D == 2) {
+            for (int q0 = lane; q0 < QS; q0 += G) {
+                const AxisEval e0 = eval_axis_t<AFF>(I, coords, 0, c[0], ga[q0]);
+                const T w0 = w1[q0];
+                if (e0.ex) {
+                    emass += w0 * wsum;
+                    continue;
+                }
+                const Basis<T> X = hermite<T>(e0.s, e0.h);
+                const long long row = I.node_off + (long long)e0.k * I.stride[0];
+                const long long s0 = I.stride[0];
+                T part = T(0), pex = T(0);
+#pragma unroll
+                for (int q1 = 0; q1 < QS; ++q1) {
+                    bool ex = exin[q1];
+                    if (ball) ex = ex || ball_exit2(e0.dz2, din[q1], r2);
+                    if (ex) {
+                        pex += w1[q1];
+                        continue;
+                    }
+                    const long long b = row + kin[q1];
+                    const R p00 = rec[b], p01 = rec[b + 1], p10 = rec[b + s0], p11 = rec[b + s0 + 1];
+                    const T A0 = (p00.x - uref) * X.v0 + (p10.x - uref) * X.v1 + p00.y * X.d0 + p10.y * X.d1;
+                    const T A1 = (p01.x - uref) * X.v0 + (p11.x - uref) * X.v1 + p01.y * X.d0 + p11.y * X.d1;
+                    const T C0 = p00.z * X.v0 + p10.z * X.v1;
+                    const T C1 = p01.z * X.v0 + p11.z * X.v1;
+                    part += w1[q1] * (bin[q1][0] * A0 + bin[q1][1] * A1 + bin[q1][2] * C0 + bin[q1][3] * C1);
+                }
+                acc += w0 * part;
+                emass += w0 * pex;
+            }
+        } else {
+            for (int q0 = lane; q0 < QS; q0 += G) {
+                const AxisEval e0 = eval_axis_t<AFF>(I, coords, 0, c[0], ga[q0]);
+                const T w0 = w1[q0];
+                if (e0.ex) {
+                    emass += w0 * wsum * wsum;
+                    continue;
+                }
+                const Basis<T> X = hermite<T>(e0.s, e0.h);
+                for (int q1 = 0; q1 < QS; ++q1) {
+                    const AxisEval e1 = eval_axis_t<AFF>(I, coords, 1, c[1], ga[q1]);
+                    const T w01 = w0 * w1[q1];
+                    if (e1.ex) {
+                        emass += w01 * wsum;
+                        continue;
+                    }
+                    const Basis<T> Y = hermite<T>(e1.s, e1.h);
+                    const long long base = I.node_off + (long long)e0.k * I.stride[0] +
+                                           (long long)e1.k * I.stride[1];
+                    const long long s0 = I.stride[0], s1 = I.stride[1];
+                    T part = T(0), pex = T(0);
+#pragma unroll
+                    for (int q2 = 0; q2 < QS; ++q2) {
+                        bool ex = exin[q2];
+                        if (ball) {
+                            const double dz[3] = {e0.dz2, e1.dz2, din[q2]};
+                            ex = ex || ball_exit(dz, 3, r2);
+                        }
+                        if (ex) {
+                            pex += w1[q2];
+                            continue;
+                        }
+                        const long long b = base + kin[q2];
+                        R p[8];
+#pragma unroll
+                        for (int a = 0; a < 2; ++a)
+#pragma unroll
+                            for (int bb = 0; bb < 2; ++bb) {
+                                p[(a * 2 + bb) * 2 + 0] = rec[b + a * s0 + bb * s1];
+                                p[(a * 2 + bb) * 2 + 1] = rec[b + a * s0 + bb * s1 + 1];
+                            }
+                        const Basis<T> Z = {bin[q2][0], bin[q2][1], bin[q2][2], bin[q2][3]};
+                        const Basis<T> B[3] = {X, Y, Z};
+                        part += w1[q2] * hermite_value<T, 3, R>(p, B, uref);
+                    }
+                    acc += w01 * part;
+                    emass += w01 * pex;
+                }
+            }
+        }
+        if (G > 1) {
+            acc = group_sum<G>(acc);
+            emass = group_sum<G>(emass);
+            if (!valid || lane != 0) continue;
+        }
+        const T v = uref + acc + emass * (T(1) - uref);
+        flag_nonfinite(P.flags, v);
+        store_node<D, T>(I, idx, node, v, u_out);
     }
 }
 
@@ -1090,8 +1360,6 @@ static hipError_t step_fused_dispatch(const PlanDev &P, int n, const void *packe
 {
     const int nq = (P.n_quad + P.group - 1) / P.group;
     switch (P.group) {
-    case 1: step_fused_launch<T, D, 1, 1>(P, n, packed, u_out, s); break;
-    case 2: step_fused_launch<T, D, 2, 1>(P, n, packed, u_out, s); break;
     case 4: step_fused_launch<T, D, 4, 1>(P, n, packed, u_out, s); break;
     case 8: step_fused_launch<T, D, 8, 1>(P, n, packed, u_out, s); break;
     case 16: step_fused_launch<T, D, 16, 1>(P, n, packed, u_out, s); break;
@@ -1107,9 +1375,60 @@ static hipError_t step_fused_dispatch(const PlanDev &P, int n, const void *packe
     return hipGetLastError();
 }
 
+template <typename T, int D, int QS>
+static void step_node_launch(const PlanDev &P, int n, const void *packed, void *u_out,
+                             hipStream_t s)
+{
+    constexpr int GS = (QS <= 2) ? 2 : (QS <= 4) ? 4 : (QS <= 8) ? 8 : 16;
+#define FK_NODE(G_, AFF_, grid_, nw_, wl_)                                                     \
+    k_step_node<T, D, QS, G_, AFF_><<<grid_, kBlock, 0, s>>>(                                  \
+        P, n, nw_, P.inst, wl_, P.active, P.trig, P.coords, (const T *)packed, (T *)u_out)
+    if (P.step_kind == 2) {
+        if (P.all_affine) FK_NODE(GS, true, P.split_grid, P.n_split_work, P.split_work);
+        else FK_NODE(GS, false, P.split_grid, P.n_split_work, P.split_work);
+    } else {
+        if (P.all_affine) FK_NODE(1, true, P.row_grid, P.n_row_work, P.row_work);
+        else FK_NODE(1, false, P.row_grid, P.n_row_work, P.row_work);
+    }
+#undef FK_NODE
+}
+
+// Q* values with a compiled thread-per-node specialisation.
+template <typename T, int D>
+static bool step_node_dispatch(const PlanDev &P, int n, const void *packed, void *u_out,
+                               hipStream_t s)
+{
+#define FK_QS(v) case v: step_node_launch<T, D, v>(P, n, packed, u_out, s); return true;
+    if constexpr (D == 1) {
+        switch (P.qs) { FK_QS(2) FK_QS(3) FK_QS(4) FK_QS(5) FK_QS(6) FK_QS(7) FK_QS(8)
+                        FK_QS(10) FK_QS(12) FK_QS(16) default: return false; }
+    } else if constexpr (D == 2) {
+        switch (P.qs) { FK_QS(2) FK_QS(3) FK_QS(4) FK_QS(5) FK_QS(6) FK_QS(7) FK_QS(8)
+                        default: return false; }
+    } else {
+        switch (P.qs) { FK_QS(2) FK_QS(3) FK_QS(4) FK_QS(5) FK_QS(6) default: return false; }
+    }
+#undef FK_QS
+}
+
+bool step_node_compiled(int d, int qs)
+{
+    if (d == 1) return (qs >= 2 && qs <= 8) || qs == 10 || qs == 12 || qs == 16;
+    if (d == 2) return qs >= 2 && qs <= 8;
+    if (d == 3) return qs >= 2 && qs <= 6;
+    return false;
+}
+
 hipError_t launch_step_fused(const PlanDev &P, bool f32, int n, const void *packed, void *u_out,
                              hipStream_t s)
 {
+    if (P.step_kind != 1) {
+        bool ok = false;
+        FK_DISPATCH_D(P.d,
+            ok = f32 ? step_node_dispatch<float, D>(P, n, packed, u_out, s)
+                     : step_node_dispatch<double, D>(P, n, packed, u_out, s));
+        if (ok) return hipGetLastError();
+    }
     FK_DISPATCH_D(P.d,
         return f32 ? step_fused_dispatch<float, D>(P, n, packed, u_out, s)
                    : step_fused_dispatch<double, D>(P, n, packed, u_out, s));

@@ -23,6 +23,7 @@ COEF = {"const": 0, "cellular2d": 1, "abc3d": 2}
 REGION = {"box": 0, "ball": 1}
 PREC = {"f64": 0, "f32": 1}
 FORM = {"fused": 0, "ell": 1}
+STEP_KERNEL = {"auto": 0, "node": 1, "group": 2, "split": 3}
 MAX_THETA = 8
 
 EXPORTED = ["fk_last_error", "fk_version", "fk_gh_rule", "fk_plan_create", "fk_plan_destroy",
@@ -53,7 +54,7 @@ class _Problem(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("form", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("ckpt_every", ctypes.c_int), ("block", ctypes.c_int),
-                ("reserved", ctypes.c_int * 3)]
+                ("step_kernel", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
 
 
 class _Info(ctypes.Structure):
@@ -167,7 +168,8 @@ class Plan:
     """
 
     def __init__(self, problems, precision: str = "f64", form: str = "fused",
-                 use_graph: bool = False, ckpt_every: int = 0, device: str = "cuda"):
+                 use_graph: bool = False, ckpt_every: int = 0, device: str = "cuda",
+                 step_kernel: str = "auto"):
         import torch
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
@@ -179,6 +181,7 @@ class Plan:
         opt.form = FORM[form]
         opt.use_graph = int(bool(use_graph))
         opt.ckpt_every = int(ckpt_every)
+        opt.step_kernel = STEP_KERNEL[step_kernel]
         h = ctypes.c_void_p()
         _check(lib.fk_plan_create(arr, len(self.problems), ctypes.byref(opt), ctypes.byref(h)))
         del keep

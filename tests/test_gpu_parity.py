@@ -52,26 +52,40 @@ def test_bm1d_full(prec):
     assert err <= TOL[prec]
 
 
+@pytest.mark.parametrize("kernel", ["node", "group", "split"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("shape", [(129, 65), (97, 53)])
-def test_cell2d_small(prec, shape):
+def test_cell2d_small(prec, shape, kernel):
     prob = W.cell2d(nx=shape[0], ny=shape[1], n_steps=100, D=2e-3)
     snaps = [100, 50, 0]
     ref = oracle.solve(prob, snaps=snaps)
-    got = _run(prob, prec, snaps)[0]
+    got = _run(prob, prec, snaps, step_kernel=kernel)[0]
     err = _maxerr(got, ref)
-    print(f"cell2d {shape} {prec}: {err:.3e}")
+    print(f"cell2d {shape} {prec} {kernel}: {err:.3e}")
     assert err <= TOL[prec]
 
 
+@pytest.mark.parametrize("kernel", ["node", "group", "split"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_abc3d_small(prec):
+def test_abc3d_small(prec, kernel):
     prob = W.abc3d(n=21, n_steps=12, dt=0.02, D=2e-3)
     ref = oracle.solve(prob, snaps=[0, 6])
-    got = _run(prob, prec, [0, 6])[0]
+    got = _run(prob, prec, [0, 6], step_kernel=kernel)[0]
     err = _maxerr(got, ref)
-    print(f"abc3d 21^3 {prec}: {err:.3e}")
+    print(f"abc3d 21^3 {prec} {kernel}: {err:.3e}")
     assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("kernel", ["node", "group", "split"])
+def test_box_exit_2d_and_ragged_q(kernel):
+    """Box exit on both axes (separable exit mass), odd Q* and a grid that is
+    not a multiple of any tile."""
+    prob = W.Problem(axes=[W.uniform_axis(0, 1, 37), W.uniform_axis(0, 2, 71)],
+                     coef_kind="const", coef=(0.4, -0.7), D=0.01, region_kind="box",
+                     gh_q=5, dt=0.01, n_steps=25)
+    ref = oracle.solve(prob, snaps=[0, 13])
+    got = _run(prob, "f64", [0, 13], step_kernel=kernel)[0]
+    assert _maxerr(got, ref) <= 1e-12
 
 
 def test_const_drift_nonuniform_grid():
