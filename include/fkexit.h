@@ -113,11 +113,14 @@ typedef struct {
     int block;       /* threads per workgroup, 0 = library default */
     int step_kernel; /* fused step layout: 0 = auto; 1 = one thread per node;
                         2 = a lane group per node over the tensor points (any gh_q);
-                        3 = Q* lanes per node over the outermost axis.  1 and 3
-                        exist for d=1: gh_q 2..8,10,12,16; d=2: 2..8; d=3: 2..6
-                        (FK_ERR_UNSUPPORTED otherwise).  auto picks 1 for plans
-                        with many active nodes, 3 for small ones, 2 when 1/3
-                        are not compiled for gh_q */
+                        3 = Q* lanes per node over the outermost axis;
+                        4 = separable box form for nodes whose landing points
+                        cannot reach a ball boundary (footprint up to 8 nodes
+                        per axis), one thread per node for the others.  1, 3
+                        and 4 exist for d=1: gh_q 2..8,10,12,16; d=2: 2..8;
+                        d=3: 2..6 (FK_ERR_UNSUPPORTED otherwise).  auto picks 4
+                        for plans with many active nodes, 3 for small ones, 2
+                        when the others are not compiled for gh_q */
     int reserved[2];
 } fk_options;
 

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -157,11 +158,20 @@ struct fk_plan {
     std::vector<float> gh_wf, gh_w1f;
     std::vector<double> tfac;
     std::vector<fk::WorkItem> slope_work, node_work, act_work, row_work, split_work;
+    std::vector<fk::TileBox> fw_tiles, box_tiles;
+    int tile_elems = 0;
+    // forward step lists
+    std::vector<int> fw_nodes, box_nodes;
+    std::vector<fk::WorkItem> fw_work, fw_split_work, box_work;
+    int box_work_off[fk::kBoxClasses] = {0}, n_box_work[fk::kBoxClasses] = {0};
+    bool use_box = false;
+    int step_kind = 0;
     int n_table_work = 0;
     std::vector<int64_t> node_off, act_count;
     long long n_nodes = 0, n_active = 0;
     int ell_box[3] = {1, 1, 1};
     int ell_width = 0;
+    long long ell_total = 0;
     // workspace
     std::map<std::string, Region> reg;
     size_t ws_bytes = 0;
@@ -351,6 +361,10 @@ fk_status build_plan(fk_plan *p)
 
     const int npb = kBlock / p->G;
     std::vector<fk::WorkItem> tables, runs;
+    long long ell_total = 0, ell_wmax = 0;
+    std::vector<std::vector<int>> inst_sep, inst_rest;
+    std::vector<int> inst_cls;
+    std::vector<std::array<int, 3>> inst_dils;
     p->node_off.assign(p->n_inst + 1, 0);
     p->act_count.assign(p->n_inst, 0);
     long long coord_total = 0;
@@ -435,6 +449,7 @@ fk_status build_plan(fk_plan *p)
         // slope records are needed only where landing cells of active nodes can
         // reach: the active bounding box widened by the reach plus the corner
         int blo[3] = {0, 0, 0}, bhi[3] = {0, 0, 0};
+        int dils[3] = {0, 0, 0};
         for (int a = 0; a < pr.d; ++a) {
             double hmin = 1e300;
             for (int k = 1; k < pr.ax[a].n; ++k)
@@ -442,6 +457,7 @@ fk_status build_plan(fk_plan *p)
             const double reach = drift_bound(pr, a) * pr.dt + I.S * amax;
             const double cells = std::ceil(reach / hmin) + 2.0;
             const int dil = cells > 1e9 ? (1 << 30) : (int)cells;
+            dils[a] = std::min(dil, pr.ax[a].n);
             if (pr.ax[a].periodic || na == 0) {
                 blo[a] = 0;
                 bhi[a] = pr.ax[a].n - 1;
@@ -472,22 +488,193 @@ fk_status build_plan(fk_plan *p)
         p->act_count[i] = na;
         build_work(p->node_work, i, (int)J, kBlock);
         build_work(p->act_work, i, na, npb);
+        // separable nodes: every active node of a box region; for a ball, nodes
+        // whose landing points stay strictly inside it (distance + reach < r)
+        {
+            double reach2 = 0.0;
+            for (int a = 0; a < pr.d; ++a) {
+                const double ra = drift_bound(pr, a) * pr.dt + I.S * amax;
+                reach2 += ra * ra;
+            }
+            const double reach = std::sqrt(reach2);
+            int Lneed = 0;
+            for (int a = 0; a < pr.d; ++a) {
+                double hmin = 1e300;
+                for (int k = 1; k < pr.ax[a].n; ++k)
+                    hmin = std::min(hmin, pr.ax[a].nodes[k] - pr.ax[a].nodes[k - 1]);
+                Lneed = std::max(Lneed, (int)std::floor(2.0 * I.S * amax / hmin) + 3);
+            }
+            static const int kL[fk::kBoxClasses] = {3, 4, 5, 6, 8};
+            int cls_box = -1;
+            for (int c2 = 0; c2 < fk::kBoxClasses; ++c2)
+                if (Lneed <= kL[c2]) { cls_box = c2; break; }
+            std::vector<int> sep, rest;
+            for (int t = 0; t < na; ++t) {
+                const int j = p->active[I.act_off + t];
+                bool separable = cls_box >= 0;
+                if (separable && pr.region_kind == FK_REGION_BALL) {
+                    long long r = j;
+                    double dist2 = 0.0;
+                    for (int a = pr.d - 1; a >= 0; --a) {
+                        const int ia = (int)(r % pr.ax[a].n);
+                        r /= pr.ax[a].n;
+                        const double dx = pr.ax[a].nodes[ia] - pr.center[a];
+                        dist2 += dx * dx;
+                    }
+                    separable = std::sqrt(dist2) + reach < pr.radius * (1.0 - 1e-9);
+                }
+                (separable ? sep : rest).push_back(j);
+            }
+            inst_sep.push_back(sep);
+            inst_rest.push_back(rest);
+            inst_cls.push_back(cls_box);
+        }
         build_work(p->row_work, i, na, kBlock);
+        inst_dils.push_back({dils[0], dils[1], dils[2]});
         build_work(p->split_work, i, na, kBlock / std::max(2, group_of(p->qs)));
         p->n_nodes += J;
         p->n_active += na;
 
         // ELL row box: the landing points of one node spread over 2 S max|a|
-        for (int a = 0; a < pr.d; ++a) {
-            double hmin = 1e300;
-            for (int k = 1; k < pr.ax[a].n; ++k)
-                hmin = std::min(hmin, pr.ax[a].nodes[k] - pr.ax[a].nodes[k - 1]);
-            int L = (int)std::floor(2.0 * I.S * amax / hmin) + 3;
-            L = std::min(L, pr.ax[a].n);
-            box[a] = std::max(box[a], L);
+        {
+            long long Wi = pr.d + 1;
+            for (int a = 0; a < pr.d; ++a) {
+                double hmin = 1e300;
+                for (int k = 1; k < pr.ax[a].n; ++k)
+                    hmin = std::min(hmin, pr.ax[a].nodes[k] - pr.ax[a].nodes[k - 1]);
+                int L = (int)std::floor(2.0 * I.S * amax / hmin) + 3;
+                L = std::min(L, pr.ax[a].n);
+                p->inst.back().ell_box[a] = L;
+                box[a] = std::max(box[a], L);
+                Wi *= L;
+            }
+            for (int a = pr.d; a < 3; ++a) p->inst.back().ell_box[a] = 1;
+            p->inst.back().ell_w = (int)Wi;
+            p->inst.back().ell_off = ell_total;
+            ell_total += Wi * na;
+            ell_wmax = std::max(ell_wmax, Wi);
         }
     }
     p->node_off[p->n_inst] = p->n_nodes;
+    // forward step layout: thread per node for large plans (with the box form
+    // for separable nodes), Q* lanes per node for small ones
+    {
+        const int sk = p->opt.step_kernel;
+        const bool large = p->n_active >= 256LL * 4 * 64 * 2;
+        const bool node_ok = fk::step_node_compiled(p->d, p->qs);
+        if (sk == 2 || !node_ok) p->step_kind = 1;
+        else if (sk == 3 || (sk == 0 && !large)) p->step_kind = 2;
+        else p->step_kind = 0;
+        p->use_box = node_ok && (sk == 4 || (sk == 0 && large));
+        const int gs = std::max(2, group_of(p->qs));
+        std::vector<std::vector<fk::WorkItem>> bw(fk::kBoxClasses);
+        // node lists in patch order (16x16 in 2D, 4x8x8 in 3D, 256 in 1D):
+        // a work item never straddles a patch, so its landing footprint (and
+        // the adjoint's LDS tile of mu) stays compact
+        static const int kPatch[3][3] = {{256, 1, 1}, {16, 16, 1}, {4, 8, 8}};
+        auto patch_sort = [&](std::vector<int> &list, const fk_problem &pr,
+                              std::vector<long long> &keys) {
+            const int *pd = kPatch[pr.d - 1];
+            std::vector<std::pair<long long, int>> kv;
+            kv.reserve(list.size());
+            for (int j : list) {
+                long long r = j, key = 0;
+                int ia[3];
+                for (int a = pr.d - 1; a >= 0; --a) {
+                    ia[a] = (int)(r % pr.ax[a].n);
+                    r /= pr.ax[a].n;
+                }
+                for (int a = 0; a < pr.d; ++a) {
+                    const int np = (pr.ax[a].n + pd[a] - 1) / pd[a];
+                    key = key * np + ia[a] / pd[a];
+                }
+                kv.push_back({key * (1LL << 31) + j, j});
+            }
+            std::sort(kv.begin(), kv.end());
+            keys.clear();
+            for (size_t t = 0; t < kv.size(); ++t) {
+                list[t] = kv[t].second;
+                keys.push_back(kv[t].first >> 31);
+            }
+        };
+        auto patch_work = [&](std::vector<fk::WorkItem> &out, int inst, const std::vector<long long> &keys,
+                              int first, int chunk) {
+            size_t t = 0;
+            while (t < keys.size()) {
+                size_t e = t;
+                while (e < keys.size() && keys[e] == keys[t] && (int)(e - t) < chunk) ++e;
+                fk::WorkItem w;
+                w.inst = inst;
+                w.first = first + (int)t;
+                w.count = (int)(e - t);
+                w.kind = 0;
+                out.push_back(w);
+                t = e;
+            }
+        };
+        std::vector<long long> keys;
+        for (int i = 0; i < p->n_inst; ++i) {
+            const fk_problem &pr = p->probs[i];
+            std::vector<int> fw = inst_rest[i];
+            if (!p->use_box || inst_cls[i] < 0) {
+                fw.insert(fw.end(), inst_sep[i].begin(), inst_sep[i].end());
+            } else {
+                std::vector<int> sep = inst_sep[i];
+                patch_sort(sep, pr, keys);
+                const int f0 = (int)p->box_nodes.size();
+                p->box_nodes.insert(p->box_nodes.end(), sep.begin(), sep.end());
+                patch_work(bw[inst_cls[i]], i, keys, f0, kBlock);
+            }
+            patch_sort(fw, pr, keys);
+            const int f1 = (int)p->fw_nodes.size();
+            p->fw_nodes.insert(p->fw_nodes.end(), fw.begin(), fw.end());
+            patch_work(p->fw_work, i, keys, f1, kBlock);
+            patch_work(p->fw_split_work, i, keys, f1, kBlock / gs);
+        }
+        for (int c2 = 0; c2 < fk::kBoxClasses; ++c2) {
+            p->box_work_off[c2] = (int)p->box_work.size();
+            p->n_box_work[c2] = (int)bw[c2].size();
+            p->box_work.insert(p->box_work.end(), bw[c2].begin(), bw[c2].end());
+        }
+        // adjoint LDS tiles: node box of each work item widened by the reach
+        const int PS = p->d == 1 ? 2 : 4;
+        const size_t elt_b = p->f32 ? 4 : 8;
+        const size_t budget = 60 * 1024;   // plus static LDS, within 64 KB per workgroup
+        auto tile_of = [&](const fk::WorkItem &it, const std::vector<int> &list) {
+            const fk_problem &pr = p->probs[it.inst];
+            int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-1, -1, -1};
+            for (int t = 0; t < it.count; ++t) {
+                long long r = list[it.first + t];
+                for (int a = pr.d - 1; a >= 0; --a) {
+                    const int ia = (int)(r % pr.ax[a].n);
+                    r /= pr.ax[a].n;
+                    mn[a] = std::min(mn[a], ia);
+                    mx[a] = std::max(mx[a], ia);
+                }
+            }
+            fk::TileBox tb;
+            std::memset(&tb, 0, sizeof(tb));
+            bool ok = it.count > 0;
+            size_t elems = PS;
+            for (int a = 0; a < pr.d; ++a) {
+                const int dil = inst_dils[it.inst][a];
+                int lo = mn[a] - dil, hi = mx[a] + dil;
+                if (pr.ax[a].periodic && (lo < 0 || hi > pr.ax[a].n - 1)) ok = false;
+                lo = std::max(lo, 0);
+                hi = std::min(hi, pr.ax[a].n - 1);
+                tb.lo[a] = lo;
+                tb.ext[a] = std::max(hi - lo + 1, 1);
+                elems *= (size_t)tb.ext[a];
+            }
+            for (int a = pr.d; a < 3; ++a) tb.ext[a] = 1;
+            if (elems * elt_b > budget) ok = false;
+            tb.use_lds = ok ? 1 : 0;
+            if (ok) p->tile_elems = std::max<int>(p->tile_elems, (int)elems);
+            return tb;
+        };
+        for (const fk::WorkItem &it : p->fw_work) p->fw_tiles.push_back(tile_of(it, p->fw_nodes));
+        for (const fk::WorkItem &it : p->box_work) p->box_tiles.push_back(tile_of(it, p->box_nodes));
+    }
     p->slope_work = tables;
     p->slope_work.insert(p->slope_work.end(), runs.begin(), runs.end());
     p->n_table_work = (int)tables.size();
@@ -519,11 +706,12 @@ fk_status build_plan(fk_plan *p)
             for (int i = 0; i < p->n_inst; ++i)
                 if (p->probs[i].ax[a].periodic)
                     return fail(FK_ERR_UNSUPPORTED, "ELL form needs non-periodic axes");
-        long long W = p->d + 1;
-        for (int a = 0; a < p->d; ++a) { p->ell_box[a] = box[a]; W *= box[a]; }
+        for (int a = 0; a < p->d; ++a) p->ell_box[a] = box[a];
+        const long long W = ell_wmax;
         if (W * (long long)(kBlock / p->G) * (p->f32 ? 4 : 8) > 64 * 1024)
             return fail(FK_ERR_UNSUPPORTED, "ELL row box too large for LDS (%lld entries)", W);
         p->ell_width = (int)W;
+        p->ell_total = ell_total;
     }
 
     // workspace layout
@@ -544,14 +732,21 @@ fk_status build_plan(fk_plan *p)
     add_region(p, "act_work", sizeof(fk::WorkItem) * std::max<size_t>(p->act_work.size(), 1));
     add_region(p, "row_work", sizeof(fk::WorkItem) * std::max<size_t>(p->row_work.size(), 1));
     add_region(p, "split_work", sizeof(fk::WorkItem) * std::max<size_t>(p->split_work.size(), 1));
+    add_region(p, "fw_tiles", sizeof(fk::TileBox) * std::max<size_t>(p->fw_tiles.size(), 1));
+    add_region(p, "box_tiles", sizeof(fk::TileBox) * std::max<size_t>(p->box_tiles.size(), 1));
+    add_region(p, "fw_nodes", sizeof(int) * std::max<size_t>(p->fw_nodes.size(), 1));
+    add_region(p, "fw_work", sizeof(fk::WorkItem) * std::max<size_t>(p->fw_work.size(), 1));
+    add_region(p, "fw_split_work", sizeof(fk::WorkItem) * std::max<size_t>(p->fw_split_work.size(), 1));
+    add_region(p, "box_nodes", sizeof(int) * std::max<size_t>(p->box_nodes.size(), 1));
+    add_region(p, "box_work", sizeof(fk::WorkItem) * std::max<size_t>(p->box_work.size(), 1));
     add_region(p, "flags", 64);
     const size_t fb = elt(p) * (size_t)p->n_nodes;
     add_region(p, "uA", fb);
     add_region(p, "uB", fb);
     add_region(p, "packed", fb * rec_stride(p->d));
     if (p->opt.form == FK_FORM_ELL) {
-        add_region(p, "ell_cols", sizeof(int) * (size_t)p->n_active * p->ell_width);
-        add_region(p, "ell_vals", elt(p) * (size_t)p->n_active * p->ell_width);
+        add_region(p, "ell_cols", sizeof(int) * (size_t)std::max<long long>(p->ell_total, 1));
+        add_region(p, "ell_vals", elt(p) * (size_t)std::max<long long>(p->ell_total, 1));
         add_region(p, "ell_em", elt(p) * (size_t)std::max<long long>(p->n_active, 1));
     }
     if (p->opt.ckpt_every > 0) {
@@ -587,6 +782,23 @@ void fill_dev(fk_plan *p)
     D.act_work = (const fk::WorkItem *)p->at("act_work");
     D.row_work = (const fk::WorkItem *)p->at("row_work");
     D.split_work = (const fk::WorkItem *)p->at("split_work");
+    D.fw_tiles = (const fk::TileBox *)p->at("fw_tiles");
+    D.box_tiles = (const fk::TileBox *)p->at("box_tiles");
+    D.fw_nodes = (const int *)p->at("fw_nodes");
+    D.fw_work = (const fk::WorkItem *)p->at("fw_work");
+    D.n_fw_work = (int)p->fw_work.size();
+    D.fw_grid = grid_for(p->fw_work.size());
+    D.fw_split_work = (const fk::WorkItem *)p->at("fw_split_work");
+    D.n_fw_split_work = (int)p->fw_split_work.size();
+    D.fw_split_grid = grid_for(p->fw_split_work.size());
+    D.box_nodes = (const int *)p->at("box_nodes");
+    D.box_work = (const fk::WorkItem *)p->at("box_work");
+    for (int c2 = 0; c2 < fk::kBoxClasses; ++c2) {
+        D.box_work_off[c2] = p->box_work_off[c2];
+        D.n_box_work[c2] = p->n_box_work[c2];
+        D.box_grid[c2] = grid_for(p->n_box_work[c2]);
+    }
+    D.tile_elems = p->tile_elems;
     D.n_split_work = (int)p->split_work.size();
     D.split_grid = grid_for(p->split_work.size());
     D.flags = (int *)p->at("flags");
@@ -606,12 +818,7 @@ void fill_dev(fk_plan *p)
     for (const fk::DevInst &I : p->inst)
         for (int a = 0; a < p->d; ++a)
             if (!I.affine[a]) D.all_affine = 0;
-    // auto: one thread per node once there are enough nodes to fill the chip
-    // (about 2 waves per SIMD), else split each node over Q* lanes
-    if (p->opt.step_kernel == 2) D.step_kind = 1;
-    else if (p->opt.step_kernel == 3) D.step_kind = 2;
-    else if (p->opt.step_kernel == 1) D.step_kind = 0;
-    else D.step_kind = (p->n_active >= 256LL * 4 * 64 * 2) ? 0 : 2;
+    D.step_kind = p->step_kind;
     D.slope_grid = grid_for(p->slope_work.size());
     D.node_grid = grid_for(p->node_work.size());
     D.act_grid = grid_for(p->act_work.size());
@@ -779,8 +986,9 @@ fk_status fk_plan_create(const fk_problem *probs, int n_inst, const fk_options *
         return fail(FK_ERR_ARG, "form must be FK_FORM_FUSED or FK_FORM_ELL");
     if (o.ckpt_every < 0) return fail(FK_ERR_ARG, "ckpt_every must be >= 0");
     if (o.block != 0 && o.block != kBlock) return fail(FK_ERR_UNSUPPORTED, "block must be 0 or 256");
-    if (o.step_kernel < 0 || o.step_kernel > 3) return fail(FK_ERR_ARG, "step_kernel must be 0..3");
-    if ((o.step_kernel == 1 || o.step_kernel == 3) && !fk::step_node_compiled(probs[0].d, probs[0].gh_q))
+    if (o.step_kernel < 0 || o.step_kernel > 4) return fail(FK_ERR_ARG, "step_kernel must be 0..4");
+    if ((o.step_kernel == 1 || o.step_kernel == 3 || o.step_kernel == 4) &&
+        !fk::step_node_compiled(probs[0].d, probs[0].gh_q))
         return fail(FK_ERR_UNSUPPORTED, "no thread-per-node kernel compiled for d=%d, gh_q=%d",
                     probs[0].d, probs[0].gh_q);
     for (int i = 0; i < n_inst; ++i) FK_TRY(validate(probs[i], i));
@@ -884,6 +1092,13 @@ fk_status fk_plan_set_workspace(fk_plan *p, void *dev_ptr, size_t bytes, void *s
     FK_TRY(up("act_work", p->act_work.data(), sizeof(fk::WorkItem) * p->act_work.size()));
     FK_TRY(up("row_work", p->row_work.data(), sizeof(fk::WorkItem) * p->row_work.size()));
     FK_TRY(up("split_work", p->split_work.data(), sizeof(fk::WorkItem) * p->split_work.size()));
+    FK_TRY(up("fw_tiles", p->fw_tiles.data(), sizeof(fk::TileBox) * p->fw_tiles.size()));
+    FK_TRY(up("box_tiles", p->box_tiles.data(), sizeof(fk::TileBox) * p->box_tiles.size()));
+    FK_TRY(up("fw_nodes", p->fw_nodes.data(), sizeof(int) * p->fw_nodes.size()));
+    FK_TRY(up("fw_work", p->fw_work.data(), sizeof(fk::WorkItem) * p->fw_work.size()));
+    FK_TRY(up("fw_split_work", p->fw_split_work.data(), sizeof(fk::WorkItem) * p->fw_split_work.size()));
+    FK_TRY(up("box_nodes", p->box_nodes.data(), sizeof(int) * p->box_nodes.size()));
+    FK_TRY(up("box_work", p->box_work.data(), sizeof(fk::WorkItem) * p->box_work.size()));
     FK_LAUNCH(fk::launch_clear_flags(p->dev, s));
     FK_HIP(hipStreamSynchronize(s));
     return FK_OK;
@@ -939,9 +1154,7 @@ fk_status fk_export_ell(fk_plan *p, int n, int *cols, void *vals, void *exit_mas
     void *ivals = p->at("ell_vals"), *iem = p->at("ell_em");
     FK_LAUNCH(fk::launch_tables(p->dev, n, s));
     FK_LAUNCH(fk::launch_assemble_ell(p->dev, p->f32, n, icols, ivals, iem, s));
-    FK_LAUNCH(fk::launch_export_ell(p->dev, p->f32, icols, cols, s));
-    const size_t nv = (size_t)p->n_active * p->ell_width;
-    FK_HIP(hipMemcpyAsync(vals, ivals, nv * elt(p), hipMemcpyDeviceToDevice, s));
+    FK_LAUNCH(fk::launch_export_ell(p->dev, p->f32, icols, ivals, cols, vals, s));
     FK_HIP(hipMemcpyAsync(exit_mass, iem, (size_t)p->n_active * elt(p), hipMemcpyDeviceToDevice, s));
     return FK_OK;
 }

@@ -10,6 +10,7 @@ namespace fk {
 constexpr int kMaxDim = 3;
 constexpr int kTimeFactors = 4;   // per (step, instance) time table entries
 constexpr int kThetaSlots = 8;    // gradient entries per instance (FK_MAX_THETA)
+constexpr int kBoxClasses = 5;    // separable-form box sizes L = 3, 4, 5, 6, 8
 
 // Per-instance record read by every kernel (one per instance of a plan).
 struct DevInst {
@@ -33,6 +34,10 @@ struct DevInst {
     double r2;
     double S;       // sqrt(2 D) * sqrt(2 dt)
     double dSdD;    // S / (2 D)  (adjoint)
+    // assembled (ELL) form: this instance's row box, width and storage offset
+    int ell_box[kMaxDim];
+    int ell_w;
+    long long ell_off;
 };
 
 // A contiguous chunk of one instance's nodes (slope pass) or active nodes
@@ -43,6 +48,14 @@ struct WorkItem {
     int first;
     int count;
     int kind;
+};
+
+// LDS tile of an adjoint work item: node box lo[a] .. lo[a] + ext[a] - 1.
+struct TileBox {
+    int lo[kMaxDim];
+    int ext[kMaxDim];
+    int use_lds;
+    int pad;
 };
 
 // Pointers into the workspace that every launch needs.
@@ -77,6 +90,23 @@ struct PlanDev {
     int group;                  // lanes per active node in the step passes
     int step_kind;              // 0: thread per node, 1: lane group, 2: split node
     int all_affine;             // every axis of every instance is affine
+    // forward step work: nodes handled per landing point (fw) and separable
+    // nodes handled in box form, by box class
+    const int *fw_nodes;
+    const WorkItem *fw_work;
+    int n_fw_work;
+    int fw_grid;
+    const WorkItem *fw_split_work;
+    int n_fw_split_work;
+    int fw_split_grid;
+    const int *box_nodes;
+    const WorkItem *box_work;
+    int box_work_off[kBoxClasses];
+    int n_box_work[kBoxClasses];
+    int box_grid[kBoxClasses];
+    const TileBox *fw_tiles;    // adjoint LDS tile per fw_work item
+    const TileBox *box_tiles;   // adjoint LDS tile per box_work item
+    int tile_elems;             // LDS entries of the largest tile in use
     const WorkItem *split_work; // chunks of block / pow2(Q*) active nodes
     int n_split_work;
     int split_grid;
@@ -108,8 +138,8 @@ hipError_t launch_assemble_ell(const PlanDev &P, bool f32, int n, int *cols, voi
 hipError_t launch_ell_apply(const PlanDev &P, bool f32, const int *cols, const void *vals,
                             const void *exit_mass, const void *packed, void *u_out,
                             hipStream_t s);
-hipError_t launch_export_ell(const PlanDev &P, bool f32, const int *cols_in, int *cols_out,
-                             hipStream_t s);
+hipError_t launch_export_ell(const PlanDev &P, bool f32, const int *cols_in, const void *vals_in,
+                             int *cols_out, void *vals_out, hipStream_t s);
 hipError_t launch_export_cells(const PlanDev &P, int inst, int n, int *cells,
                                unsigned char *exit_flags, hipStream_t s);
 hipError_t launch_clear_flags(const PlanDev &P, hipStream_t s);

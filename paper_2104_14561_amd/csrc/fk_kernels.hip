@@ -741,7 +741,7 @@ __global__ void __launch_bounds__(kBlock) k_step_fused(
 template <typename T, int D, int QS, int G, bool AFF>
 __global__ void __launch_bounds__(kBlock) k_step_node(
     const PlanDev P, int n, int n_work, const DevInst *__restrict__ insts,
-    const WorkItem *__restrict__ work, const int *__restrict__ active,
+    const WorkItem *__restrict__ work, const int *__restrict__ nodes,
     const double2 *__restrict__ trig, const double *__restrict__ coords,
     const T *__restrict__ packed, T *__restrict__ u_out)
 {
@@ -761,7 +761,7 @@ __global__ void __launch_bounds__(kBlock) k_step_node(
         if (G == 1 && slot >= it.count) continue;
         const bool valid = slot < it.count;
         const DevInst &I = insts[it.inst];
-        const int node = valid ? active[I.act_off + it.first + slot] : active[I.act_off + it.first];
+        const int node = valid ? nodes[it.first + slot] : nodes[it.first];
         int idx[3];
         split_node<D>(I, node, idx);
         const T uref = rec[I.node_off + node].x;
@@ -892,6 +892,205 @@ __global__ void __launch_bounds__(kBlock) k_step_node(
     }
 }
 
+// ---------------------------------------------------------------------------
+// Separable (box) form.  For a node none of whose landing points can reach a
+// ball boundary, the exit test is a per-axis box test and the tensor rule
+// factorises: the row of A_n over the footprint box B = B_0 x .. x B_{d-1}
+// is sum_a-products of per-axis weight vectors
+//   V_a[l] = sum_{q inside on axis a} w_q (H00(s_q) [l = k_q - o_a] + H01(s_q) [l = k_q - o_a + 1])
+//   S_a[l] = same with the slope basis h H10, h H11,
+// so u^n_j = u_ref + sum_B prod V (u - u_ref) + (slope terms) + exit mass (1 - u_ref),
+// exit mass = (sum_q w_q)^d - prod_a m_a, m_a = sum of inside weights on axis a.
+// o_a is the (unwrapped) cell of the smallest landing coordinate, and every
+// landing cell lies in [o_a, o_a + L - 2] (host bound).
+// ---------------------------------------------------------------------------
+struct AxisBox {
+    int o;       // unwrapped cell of the first GH point
+    int n;       // nodes on the axis
+    int per;     // periodic
+};
+
+// Cell of a landing coordinate, unwrapped across a periodic seam.
+template <bool AFF>
+__device__ inline AxisEval eval_axis_unwrapped(const DevInst &I, const double *coords, int a,
+                                               double c, double ga, int &ku)
+{
+#pragma clang fp contract(off)
+    const AxisEval e = eval_axis_t<AFF>(I, coords, a, c, ga);
+    ku = e.k;
+    if (I.periodic[a]) {
+        const double z = c + I.S * ga;
+        if (z >= I.hi[a]) ku += I.n[a] - 1;
+        else if (z < I.lo[a]) ku -= I.n[a] - 1;
+    }
+    return e;
+}
+
+// Per-axis weight vectors of one node; returns false if a landing cell left
+// the box (cannot happen when the host bound holds).
+template <typename T, int QS, int L, bool AFF, bool DERIV>
+__device__ inline bool axis_vectors(const DevInst &I, const double *coords, const double *ga,
+                                    const T *w1, int a, double c, int &o, T &m, T *V, T *Sv,
+                                    T *dV, T *dS, T *aV, T *aS)
+{
+    bool ok = true;
+    m = T(0);
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        V[j] = T(0); Sv[j] = T(0);
+        if (DERIV) { dV[j] = T(0); dS[j] = T(0); aV[j] = T(0); aS[j] = T(0); }
+    }
+#pragma unroll
+    for (int q = 0; q < QS; ++q) {
+        int ku;
+        const AxisEval e = eval_axis_unwrapped<AFF>(I, coords, a, c, ga[q], ku);
+        if (q == 0) o = ku;
+        const int l = ku - o;
+        if (l < 0 || l > L - 2) { ok = false; continue; }
+        if (e.ex) continue;
+        const T w = w1[q];
+        m += w;
+        const Basis<T> B = hermite<T>(e.s, e.h);
+        Basis<T> Bz;
+        if (DERIV) Bz = hermite_dz<T>(e.s, e.h);
+#pragma unroll
+        for (int j = 0; j < L; ++j) {
+            const bool a0 = (j == l), a1 = (j == l + 1);
+            V[j] += a0 ? w * B.v0 : (a1 ? w * B.v1 : T(0));
+            Sv[j] += a0 ? w * B.d0 : (a1 ? w * B.d1 : T(0));
+            if (DERIV) {
+                const T wa = w * (T)ga[q];
+                dV[j] += a0 ? w * Bz.v0 : (a1 ? w * Bz.v1 : T(0));
+                dS[j] += a0 ? w * Bz.d0 : (a1 ? w * Bz.d1 : T(0));
+                aV[j] += a0 ? wa * Bz.v0 : (a1 ? wa * Bz.v1 : T(0));
+                aS[j] += a0 ? wa * Bz.d0 : (a1 ? wa * Bz.d1 : T(0));
+            }
+        }
+    }
+    return ok;
+}
+
+__device__ inline int wrap_index(int i, int n, int per)
+{
+    if (per) {
+        if (i < 0) i += n - 1;
+        else if (i > n - 1) i -= n - 1;
+    }
+    return i;
+}
+
+// Box contraction: value and slope-weighted sum over the footprint box of
+// the records, with per-axis vector sets (Va, Sa) for each axis.
+template <typename T, int D, int L, typename R>
+__device__ inline T box_contract(const R *rec, const DevInst &I, const int *o, T uref,
+                                 const T (*V)[L], const T (*Sv)[L])
+{
+    if constexpr (D == 1) {
+        T acc = T(0);
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const R r = rec[I.node_off + wrap_index(o[0] + i, I.n[0], I.periodic[0])];
+            acc += V[0][i] * (r.x - uref) + Sv[0][i] * r.y;
+        }
+        return acc;
+    } else if constexpr (D == 2) {
+        int j1[L];
+#pragma unroll
+        for (int j = 0; j < L; ++j) j1[j] = wrap_index(o[1] + j, I.n[1], I.periodic[1]);
+        T acc = T(0);
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const long long row = I.node_off +
+                (long long)wrap_index(o[0] + i, I.n[0], I.periodic[0]) * I.stride[0];
+            T tv = T(0), tg = T(0);
+#pragma unroll
+            for (int j = 0; j < L; ++j) {
+                const R r = rec[row + j1[j]];
+                tv += V[1][j] * (r.x - uref) + Sv[1][j] * r.z;
+                tg += V[1][j] * r.y;
+            }
+            acc += V[0][i] * tv + Sv[0][i] * tg;
+        }
+        return acc;
+    } else {
+        int j2[L], j1[L];
+#pragma unroll
+        for (int j = 0; j < L; ++j) {
+            j2[j] = wrap_index(o[2] + j, I.n[2], I.periodic[2]);
+            j1[j] = wrap_index(o[1] + j, I.n[1], I.periodic[1]);
+        }
+        T acc = T(0);
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const long long b0 = I.node_off +
+                (long long)wrap_index(o[0] + i, I.n[0], I.periodic[0]) * I.stride[0];
+            T sv = T(0), sg0 = T(0);
+#pragma unroll
+            for (int j = 0; j < L; ++j) {
+                const long long b1 = b0 + (long long)j1[j] * I.stride[1];
+                T tv = T(0), tg0 = T(0), tg1 = T(0);
+#pragma unroll
+                for (int kk = 0; kk < L; ++kk) {
+                    const R r = rec[b1 + j2[kk]];
+                    tv += V[2][kk] * (r.x - uref) + Sv[2][kk] * r.w;
+                    tg0 += V[2][kk] * r.y;
+                    tg1 += V[2][kk] * r.z;
+                }
+                sv += V[1][j] * tv + Sv[1][j] * tg1;
+                sg0 += V[1][j] * tg0;
+            }
+            acc += V[0][i] * sv + Sv[0][i] * sg0;
+        }
+        return acc;
+    }
+}
+
+template <typename T, int D, int QS, int L, bool AFF>
+__global__ void __launch_bounds__(kBlock) k_step_box(
+    const PlanDev P, int n, int n_work, const DevInst *__restrict__ insts,
+    const WorkItem *__restrict__ work, const int *__restrict__ nodes,
+    const double2 *__restrict__ trig, const double *__restrict__ coords,
+    const T *__restrict__ packed, T *__restrict__ u_out)
+{
+    constexpr int PS = RecStride<D>::value;
+    using R = typename RecT<T, PS>::type;
+    const R *rec = reinterpret_cast<const R *>(packed);
+    const double *ga = P.gh_a;
+    const T *w1 = weights1<T>(P);
+    T wsum = T(0);
+#pragma unroll
+    for (int q = 0; q < QS; ++q) wsum += w1[q];
+    const WorkRange wr = work_range(0, n_work);
+    for (int w = wr.begin; w < wr.end; w += wr.step) {
+        const WorkItem it = work[w];
+        if ((int)threadIdx.x >= it.count) continue;
+        const DevInst &I = insts[it.inst];
+        const int node = nodes[it.first + threadIdx.x];
+        int idx[3];
+        split_node<D>(I, node, idx);
+        const T uref = rec[I.node_off + node].x;
+        double c[3];
+        node_centre<D>(I, coords, time_factors(P, n, it.inst), trig, idx, P.dt, c);
+        T V[D][L], Sv[D][L];
+        int o[3];
+        T m[3];
+        bool ok = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+            ok = axis_vectors<T, QS, L, AFF, false>(I, coords, ga, w1, a, c[a], o[a], m[a], V[a],
+                                                    Sv[a], nullptr, nullptr, nullptr, nullptr) && ok;
+        if (!ok) atomicOr(P.flags, 2);
+        T prod = m[0], wd = wsum;
+#pragma unroll
+        for (int a = 1; a < D; ++a) { prod *= m[a]; wd *= wsum; }
+        const T emass = wd - prod;
+        const T acc = box_contract<T, D, L, R>(rec, I, o, uref, V, Sv);
+        const T v = uref + acc + emass * (T(1) - uref);
+        flag_nonfinite(P.flags, v);
+        store_node<D, T>(I, idx, node, v, u_out);
+    }
+}
+
 // Landing cells and exit flags of one instance (index parity checks).
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_export_cells(PlanDev P, int inst, int n,
@@ -932,7 +1131,6 @@ __global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n, int *
     constexpr int PS = RecStride<D>::value;
     extern __shared__ unsigned char smem_raw[];
     T *box = reinterpret_cast<T *>(smem_raw);
-    const int W = P.ell_width;
     const T *Wq = weights<T>(P);
     const int lane = threadIdx.x % G;
     const int slot = threadIdx.x / G;
@@ -941,7 +1139,8 @@ __global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n, int *
         const WorkItem it = P.act_work[w];
         const bool valid = slot < it.count;
         const DevInst &I = P.inst[it.inst];
-        T *mybox = box + (long long)slot * W;
+        const int W = I.ell_w;
+        T *mybox = box + (long long)slot * P.ell_width;
         for (int k = lane; k < W; k += G) mybox[k] = T(0);
         __syncthreads();
         int idx[3] = {0, 0, 0};
@@ -975,8 +1174,8 @@ __global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n, int *
                     for (int a = 0; a < D; ++a) {
                         const int bit = (cb >> (D - 1 - a)) & 1;
                         const int l = k[a] + bit - origin[a];
-                        in = in && l >= 0 && l < P.ell_box[a];
-                        off = off * P.ell_box[a] + l;
+                        in = in && l >= 0 && l < I.ell_box[a];
+                        off = off * I.ell_box[a] + l;
                         wv *= bit ? B[a].v1 : B[a].v0;
                     }
                     if (!in) {
@@ -999,20 +1198,21 @@ __global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n, int *
         em = group_sum<G>(em);
         __syncthreads();
         if (valid) {
-            const long long na = P.n_active;
+            const long long rows = I.n_act;
+            const long long r = row - I.act_off;
             for (int k = lane; k < W; k += G) {
                 const int f = k % (D + 1);
                 int l = k / (D + 1);
                 long long nd = I.node_off;
                 for (int a = D - 1; a >= 0; --a) {
-                    const int la = l % P.ell_box[a];
-                    l /= P.ell_box[a];
+                    const int la = l % I.ell_box[a];
+                    l /= I.ell_box[a];
                     int ia = origin[a] + la;
                     if (ia > I.n[a] - 1) ia = I.n[a] - 1;   // padding stays in range
                     nd += (long long)ia * I.stride[a];
                 }
-                cols[k * na + row] = (int)(nd * PS + f);
-                vals[k * na + row] = mybox[k];
+                cols[I.ell_off + k * rows + r] = (int)(nd * PS + f);
+                vals[I.ell_off + k * rows + r] = mybox[k];
             }
             if (lane == 0) exit_mass[row] = em;
         }
@@ -1031,21 +1231,24 @@ __global__ void __launch_bounds__(kBlock) k_ell_apply(PlanDev P, const int *__re
                                                       T *__restrict__ u_out)
 {
     constexpr int PS = RecStride<D>::value;
-    const long long na = P.n_active;
-    const int W = P.ell_width;
     const WorkRange wr = work_range(0, P.n_row_work);
     for (int w = wr.begin; w < wr.end; w += wr.step) {
         const WorkItem it = P.row_work[w];
         if ((int)threadIdx.x >= it.count) continue;
         const DevInst &I = P.inst[it.inst];
-        const long long row = I.act_off + it.first + threadIdx.x;
+        const int W = I.ell_w;
+        const long long rows = I.n_act;
+        const long long r = it.first + threadIdx.x;
+        const long long row = I.act_off + r;
         const int node = P.active[row];
         const T uref = packed[(I.node_off + node) * PS];
         T acc = exit_mass[row] * (T(1) - uref);
+        const int *cr = cols + I.ell_off + r;
+        const T *vr = vals + I.ell_off + r;
         for (int k = 0; k < W; ++k) {
-            const int col = cols[k * na + row];
+            const int col = cr[k * rows];
             const T x = packed[col];
-            acc += vals[k * na + row] * ((col % PS) == 0 ? x - uref : x);
+            acc += vr[k * rows] * ((col % PS) == 0 ? x - uref : x);
         }
         int idx[3];
         split_node<D>(I, node, idx);
@@ -1055,16 +1258,37 @@ __global__ void __launch_bounds__(kBlock) k_ell_apply(PlanDev P, const int *__re
     }
 }
 
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_export_ell_cols(PlanDev P, const int *cols_in,
-                                                            int *cols_out)
+// Export in the documented layout: width P.ell_width (the largest instance
+// width), column-major over all active rows, columns (d+1) node + field,
+// padding entries value 0 (column of the row's own node value).
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_export_ell(PlanDev P, const int *cols_in,
+                                                       const T *vals_in, int *cols_out,
+                                                       T *vals_out)
 {
     constexpr int PS = RecStride<D>::value;
-    const long long total = P.n_active * (long long)P.ell_width;
+    const long long na = P.n_active;
+    const long long total = na * (long long)P.ell_width;
     for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
          t += (long long)gridDim.x * blockDim.x) {
-        const int c = cols_in[t];
-        cols_out[t] = (c / PS) * (D + 1) + (c % PS);
+        const int k = (int)(t / na);
+        const long long row = t - (long long)k * na;
+        // instance of the row (binary search over act_off)
+        int lo = 0, hi = P.n_inst - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (P.inst[mid].act_off <= row) lo = mid; else hi = mid - 1;
+        }
+        const DevInst &I = P.inst[lo];
+        const long long r = row - I.act_off;
+        if (k < I.ell_w) {
+            const int c = cols_in[I.ell_off + (long long)k * I.n_act + r];
+            cols_out[t] = (c / PS) * (D + 1) + (c % PS);
+            vals_out[t] = vals_in[I.ell_off + (long long)k * I.n_act + r];
+        } else {
+            cols_out[t] = (int)((I.node_off + P.active[row]) * (D + 1));
+            vals_out[t] = T(0);
+        }
     }
 }
 
@@ -1171,6 +1395,385 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_step(PlanDev P, int n,
             }
         }
         // block reduction of the parameter gradient, one atomic per entry
+        const int wave = threadIdx.x / 64, wl = threadIdx.x % 64;
+        for (int kk = 0; kk < kThetaSlots; ++kk) {
+            double v = gth[kk];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (wl == 0) red[wave][kk] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < kThetaSlots) {
+            double v = 0.0;
+            for (int wv = 0; wv < kBlock / 64; ++wv) v += red[wv][threadIdx.x];
+            if (v != 0.0) atomicAdd(&grad[it.inst * kThetaSlots + threadIdx.x], v);
+        }
+        __syncthreads();
+    }
+}
+
+// Thread-per-node adjoint step.  Lane = active node; the innermost axis is
+// hoisted as in k_step_node.  The transposed interpolation weights of all
+// nodes of a work item go into an LDS tile of mu covering their landing
+// footprint (host-computed box), flushed once with global atomics; items
+// whose box does not fit (or wraps a periodic seam) add to global memory.
+template <typename T, int D, int QS, bool AFF>
+__global__ void __launch_bounds__(kBlock) k_adjoint_node(
+    const PlanDev P, int n, int n_work, const DevInst *__restrict__ insts,
+    const WorkItem *__restrict__ work, const TileBox *__restrict__ tiles,
+    const int *__restrict__ nodes, const double2 *__restrict__ trig,
+    const double *__restrict__ coords, const T *__restrict__ packed,
+    const T *__restrict__ lam, T *__restrict__ mu, double *__restrict__ grad)
+{
+    constexpr int PS = RecStride<D>::value;
+    using R = typename RecT<T, PS>::type;
+    extern __shared__ unsigned char smem_raw[];
+    T *tile = reinterpret_cast<T *>(smem_raw);
+    __shared__ double red[kBlock / 64][kThetaSlots];
+    const R *rec = reinterpret_cast<const R *>(packed);
+    const double *ga = P.gh_a;
+    const T *w1 = weights1<T>(P);
+    const WorkRange wr = work_range(0, n_work);
+    for (int w = wr.begin; w < wr.end; w += wr.step) {
+        const WorkItem it = work[w];
+        const TileBox tb = tiles[w];
+        const DevInst &I = insts[it.inst];
+        int ext_all = PS;
+        for (int a = 0; a < D; ++a) ext_all *= tb.ext[a];
+        if (tb.use_lds) {
+            for (int e = threadIdx.x; e < ext_all; e += blockDim.x) tile[e] = T(0);
+        }
+        __syncthreads();
+        // mu entry (node index, field) -> LDS tile or global
+        auto scatter = [&](const int *cidx, int f, T v) {
+            if (tb.use_lds) {
+                int off = 0;
+                bool in = true;
+                for (int a = 0; a < D; ++a) {
+                    const int l = cidx[a] - tb.lo[a];
+                    in = in && l >= 0 && l < tb.ext[a];
+                    off = off * tb.ext[a] + l;
+                }
+                if (in) {
+                    atomicAdd(&tile[off * PS + f], v);
+                    return;
+                }
+            }
+            long long o = I.node_off;
+            for (int a = 0; a < D; ++a) o += (long long)cidx[a] * I.stride[a];
+            atomicAdd(&mu[o * PS + f], v);
+        };
+        double gth[kThetaSlots];
+        for (int kk = 0; kk < kThetaSlots; ++kk) gth[kk] = 0.0;
+        const bool valid = (int)threadIdx.x < it.count;
+        const int node = valid ? nodes[it.first + threadIdx.x] : 0;
+        const T L = valid ? lam[I.node_off + node] : T(0);
+        if (valid && L != T(0)) {
+            int idx[3];
+            split_node<D>(I, node, idx);
+            const double *tf = time_factors(P, n, it.inst);
+            double c[3];
+            node_centre<D>(I, coords, tf, trig, idx, P.dt, c);
+            const bool ball = I.region_kind == 1;
+            const double r2 = I.r2;
+            constexpr int AI = D - 1;
+            int kin[QS];
+            Basis<T> bin[QS], dbin[QS];
+            bool exin[QS];
+            double din[QS];
+#pragma unroll
+            for (int q = 0; q < QS; ++q) {
+                const AxisEval e = eval_axis_t<AFF>(I, coords, AI, c[AI], ga[q]);
+                kin[q] = e.k;
+                bin[q] = hermite<T>(e.s, e.h);
+                dbin[q] = hermite_dz<T>(e.s, e.h);
+                exin[q] = e.ex;
+                din[q] = e.dz2;
+            }
+            T Gz[3] = {T(0), T(0), T(0)}, Hz[3] = {T(0), T(0), T(0)};
+            // one landing point: gradient of the interpolant and the scatter
+            auto point = [&](const int *k, const Basis<T> *B, const Basis<T> *Bz, const T *aq, T wq) {
+                R p[1 << D];
+                gather_corners<D, R>(rec, I, k, p);
+                T gz[3];
+                hermite_grad<T, D, R>(p, B, Bz, gz);
+                for (int a = 0; a < D; ++a) {
+                    Gz[a] += wq * gz[a];
+                    Hz[a] += wq * aq[a] * gz[a];
+                }
+                const T Lw = L * wq;
+                for (int cb = 0; cb < (1 << D); ++cb) {
+                    int cidx[3];
+                    T wv = Lw;
+                    for (int a = 0; a < D; ++a) {
+                        const int bit = (cb >> (D - 1 - a)) & 1;
+                        cidx[a] = k[a] + bit;
+                        wv *= bit ? B[a].v1 : B[a].v0;
+                    }
+                    scatter(cidx, 0, wv);
+                    for (int a = 0; a < D; ++a) {
+                        T ws = Lw;
+                        for (int i = 0; i < D; ++i) {
+                            const int bit = (cb >> (D - 1 - i)) & 1;
+                            if (i == a) ws *= bit ? B[i].d1 : B[i].d0;
+                            else ws *= bit ? B[i].v1 : B[i].v0;
+                        }
+                        scatter(cidx, 1 + a, ws);
+                    }
+                }
+            };
+            if constexpr (D == 1) {
+#pragma unroll
+                for (int q = 0; q < QS; ++q) {
+                    if (exin[q] || (ball && din[q] >= r2)) continue;
+                    int k[1] = {kin[q]};
+                    const T aq[1] = {(T)ga[q]};
+                    point(k, &bin[q], &dbin[q], aq, w1[q]);
+                }
+            } else if constexpr (D == 2) {
+                for (int q0 = 0; q0 < QS; ++q0) {
+                    const AxisEval e0 = eval_axis_t<AFF>(I, coords, 0, c[0], ga[q0]);
+                    if (e0.ex) continue;
+                    const Basis<T> X = hermite<T>(e0.s, e0.h), dX = hermite_dz<T>(e0.s, e0.h);
+#pragma unroll
+                    for (int q1 = 0; q1 < QS; ++q1) {
+                        if (exin[q1] || (ball && ball_exit2(e0.dz2, din[q1], r2))) continue;
+                        int k[2] = {e0.k, kin[q1]};
+                        const Basis<T> B[2] = {X, bin[q1]}, Bz[2] = {dX, dbin[q1]};
+                        const T aq[2] = {(T)ga[q0], (T)ga[q1]};
+                        point(k, B, Bz, aq, w1[q0] * w1[q1]);
+                    }
+                }
+            } else {
+                for (int q0 = 0; q0 < QS; ++q0) {
+                    const AxisEval e0 = eval_axis_t<AFF>(I, coords, 0, c[0], ga[q0]);
+                    if (e0.ex) continue;
+                    const Basis<T> X = hermite<T>(e0.s, e0.h), dX = hermite_dz<T>(e0.s, e0.h);
+                    for (int q1 = 0; q1 < QS; ++q1) {
+                        const AxisEval e1 = eval_axis_t<AFF>(I, coords, 1, c[1], ga[q1]);
+                        if (e1.ex) continue;
+                        const Basis<T> Y = hermite<T>(e1.s, e1.h), dY = hermite_dz<T>(e1.s, e1.h);
+#pragma unroll
+                        for (int q2 = 0; q2 < QS; ++q2) {
+                            if (exin[q2]) continue;
+                            if (ball) {
+                                const double dz[3] = {e0.dz2, e1.dz2, din[q2]};
+                                if (ball_exit(dz, 3, r2)) continue;
+                            }
+                            int k[3] = {e0.k, e1.k, kin[q2]};
+                            const Basis<T> B[3] = {X, Y, bin[q2]}, Bz[3] = {dX, dY, dbin[q2]};
+                            const T aq[3] = {(T)ga[q0], (T)ga[q1], (T)ga[q2]};
+                            point(k, B, Bz, aq, w1[q0] * w1[q1] * w1[q2]);
+                        }
+                    }
+                }
+            }
+            double db[12];
+            const int nt = drift_dtheta(I, tf, trig, idx, db);
+            for (int kk = 0; kk < nt; ++kk) {
+                double sdot = 0.0;
+                for (int a = 0; a < D; ++a) sdot += (double)Gz[a] * db[kk * 3 + a];
+                gth[kk] = (double)L * P.dt * sdot;
+            }
+            double sd = 0.0;
+            for (int a = 0; a < D; ++a) sd += (double)Hz[a];
+            gth[nt] = (double)L * sd * I.dSdD;
+        }
+        __syncthreads();
+        if (tb.use_lds) {
+            for (int e = threadIdx.x; e < ext_all; e += blockDim.x) {
+                const T v = tile[e];
+                if (v == T(0)) continue;
+                int l = e / PS;
+                const int f = e - l * PS;
+                long long o = I.node_off;
+                for (int a = D - 1; a >= 0; --a) {
+                    const int la = l % tb.ext[a];
+                    l /= tb.ext[a];
+                    o += (long long)(tb.lo[a] + la) * I.stride[a];
+                }
+                atomicAdd(&mu[o * PS + f], v);
+            }
+        }
+        const int wave = threadIdx.x / 64, wl = threadIdx.x % 64;
+        for (int kk = 0; kk < kThetaSlots; ++kk) {
+            double v = gth[kk];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (wl == 0) red[wave][kk] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < kThetaSlots) {
+            double v = 0.0;
+            for (int wv = 0; wv < kBlock / 64; ++wv) v += red[wv][threadIdx.x];
+            if (v != 0.0) atomicAdd(&grad[it.inst * kThetaSlots + threadIdx.x], v);
+        }
+        __syncthreads();
+    }
+}
+
+// Box-form adjoint step for separable nodes: the transposed row of A_n is the
+// outer product of the per-axis weight vectors, and the theta-gradient needs
+// the same box contraction with the derivative vectors (dV, dS) and the
+// GH-node-weighted derivative vectors (aV, aS) on one axis at a time.
+template <typename T, int D, int QS, int L, bool AFF>
+__global__ void __launch_bounds__(kBlock) k_adjoint_box(
+    const PlanDev P, int n, int n_work, const DevInst *__restrict__ insts,
+    const WorkItem *__restrict__ work, const TileBox *__restrict__ tiles,
+    const int *__restrict__ nodes, const double2 *__restrict__ trig,
+    const double *__restrict__ coords, const T *__restrict__ packed,
+    const T *__restrict__ lam, T *__restrict__ mu, double *__restrict__ grad)
+{
+    constexpr int PS = RecStride<D>::value;
+    using R = typename RecT<T, PS>::type;
+    extern __shared__ unsigned char smem_raw[];
+    T *tile = reinterpret_cast<T *>(smem_raw);
+    __shared__ double red[kBlock / 64][kThetaSlots];
+    const R *rec = reinterpret_cast<const R *>(packed);
+    const double *ga = P.gh_a;
+    const T *w1 = weights1<T>(P);
+    const WorkRange wr = work_range(0, n_work);
+    for (int w = wr.begin; w < wr.end; w += wr.step) {
+        const WorkItem it = work[w];
+        const TileBox tb = tiles[w];
+        const DevInst &I = insts[it.inst];
+        int ext_all = PS;
+        for (int a = 0; a < D; ++a) ext_all *= tb.ext[a];
+        if (tb.use_lds)
+            for (int e = threadIdx.x; e < ext_all; e += blockDim.x) tile[e] = T(0);
+        __syncthreads();
+        auto scatter = [&](const int *cidx, int f, T v) {
+            if (tb.use_lds) {
+                int off = 0;
+                bool in = true;
+                for (int a = 0; a < D; ++a) {
+                    const int l = cidx[a] - tb.lo[a];
+                    in = in && l >= 0 && l < tb.ext[a];
+                    off = off * tb.ext[a] + l;
+                }
+                if (in) {
+                    atomicAdd(&tile[off * PS + f], v);
+                    return;
+                }
+            }
+            long long o = I.node_off;
+            for (int a = 0; a < D; ++a) o += (long long)cidx[a] * I.stride[a];
+            atomicAdd(&mu[o * PS + f], v);
+        };
+        double gth[kThetaSlots];
+        for (int kk = 0; kk < kThetaSlots; ++kk) gth[kk] = 0.0;
+        const bool valid = (int)threadIdx.x < it.count;
+        const int node = valid ? nodes[it.first + threadIdx.x] : 0;
+        const T Lm = valid ? lam[I.node_off + node] : T(0);
+        if (valid && Lm != T(0)) {
+            int idx[3];
+            split_node<D>(I, node, idx);
+            const double *tf = time_factors(P, n, it.inst);
+            double c[3];
+            node_centre<D>(I, coords, tf, trig, idx, P.dt, c);
+            T V[D][L], Sv[D][L], dV[D][L], dS[D][L], aV[D][L], aS[D][L];
+            int o[3];
+            T m[3];
+            bool ok = true;
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+                ok = axis_vectors<T, QS, L, AFF, true>(I, coords, ga, w1, a, c[a], o[a], m[a],
+                                                       V[a], Sv[a], dV[a], dS[a], aV[a], aS[a]) && ok;
+            if (!ok) atomicOr(P.flags, 2);
+            T Gz[3] = {T(0), T(0), T(0)}, Hz[3] = {T(0), T(0), T(0)};
+            if constexpr (D == 1) {
+#pragma unroll
+                for (int i = 0; i < L; ++i) {
+                    const int ci = wrap_index(o[0] + i, I.n[0], I.periodic[0]);
+                    const R r = rec[I.node_off + ci];
+                    Gz[0] += dV[0][i] * r.x + dS[0][i] * r.y;
+                    Hz[0] += aV[0][i] * r.x + aS[0][i] * r.y;
+                    int cidx[1] = {ci};
+                    scatter(cidx, 0, Lm * V[0][i]);
+                    scatter(cidx, 1, Lm * Sv[0][i]);
+                }
+            } else if constexpr (D == 2) {
+#pragma unroll
+                for (int i = 0; i < L; ++i) {
+                    const int ci = wrap_index(o[0] + i, I.n[0], I.periodic[0]);
+#pragma unroll
+                    for (int j = 0; j < L; ++j) {
+                        const int cj = wrap_index(o[1] + j, I.n[1], I.periodic[1]);
+                        const R r = rec[I.node_off + (long long)ci * I.stride[0] + cj];
+                        Gz[0] += dV[0][i] * (V[1][j] * r.x + Sv[1][j] * r.z) + dS[0][i] * V[1][j] * r.y;
+                        Gz[1] += V[0][i] * (dV[1][j] * r.x + dS[1][j] * r.z) + Sv[0][i] * dV[1][j] * r.y;
+                        Hz[0] += aV[0][i] * (V[1][j] * r.x + Sv[1][j] * r.z) + aS[0][i] * V[1][j] * r.y;
+                        Hz[1] += V[0][i] * (aV[1][j] * r.x + aS[1][j] * r.z) + Sv[0][i] * aV[1][j] * r.y;
+                        int cidx[2] = {ci, cj};
+                        scatter(cidx, 0, Lm * V[0][i] * V[1][j]);
+                        scatter(cidx, 1, Lm * Sv[0][i] * V[1][j]);
+                        scatter(cidx, 2, Lm * V[0][i] * Sv[1][j]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < L; ++i) {
+                    const int ci = wrap_index(o[0] + i, I.n[0], I.periodic[0]);
+#pragma unroll
+                    for (int j = 0; j < L; ++j) {
+                        const int cj = wrap_index(o[1] + j, I.n[1], I.periodic[1]);
+#pragma unroll
+                        for (int kk = 0; kk < L; ++kk) {
+                            const int ck = wrap_index(o[2] + kk, I.n[2], I.periodic[2]);
+                            const R r = rec[I.node_off + (long long)ci * I.stride[0] +
+                                            (long long)cj * I.stride[1] + ck];
+                            // f(A, B, C) = A V1 V2 u + As V1 V2 g0 + A S1 V2 g1 + A V1 S2 g2
+                            // with per-axis pairs (value, slope) for the three axes
+                            const T v12 = V[1][j] * V[2][kk];
+                            const T t0 = v12 * r.x + Sv[1][j] * V[2][kk] * r.z + V[1][j] * Sv[2][kk] * r.w;
+                            const T t0s = v12 * r.y;
+                            Gz[0] += dV[0][i] * t0 + dS[0][i] * t0s;
+                            Hz[0] += aV[0][i] * t0 + aS[0][i] * t0s;
+                            const T v02 = V[0][i] * V[2][kk];
+                            const T t1 = v02 * r.x + Sv[0][i] * V[2][kk] * r.y + V[0][i] * Sv[2][kk] * r.w;
+                            const T t1s = v02 * r.z;
+                            Gz[1] += dV[1][j] * t1 + dS[1][j] * t1s;
+                            Hz[1] += aV[1][j] * t1 + aS[1][j] * t1s;
+                            const T v01 = V[0][i] * V[1][j];
+                            const T t2 = v01 * r.x + Sv[0][i] * V[1][j] * r.y + V[0][i] * Sv[1][j] * r.z;
+                            const T t2s = v01 * r.w;
+                            Gz[2] += dV[2][kk] * t2 + dS[2][kk] * t2s;
+                            Hz[2] += aV[2][kk] * t2 + aS[2][kk] * t2s;
+                            int cidx[3] = {ci, cj, ck};
+                            const T lv = Lm * v01 * V[2][kk];
+                            scatter(cidx, 0, lv);
+                            scatter(cidx, 1, Lm * Sv[0][i] * V[1][j] * V[2][kk]);
+                            scatter(cidx, 2, Lm * V[0][i] * Sv[1][j] * V[2][kk]);
+                            scatter(cidx, 3, Lm * v01 * Sv[2][kk]);
+                        }
+                    }
+                }
+            }
+            double db[12];
+            const int nt = drift_dtheta(I, tf, trig, idx, db);
+            for (int kk = 0; kk < nt; ++kk) {
+                double sdot = 0.0;
+                for (int a = 0; a < D; ++a) sdot += (double)Gz[a] * db[kk * 3 + a];
+                gth[kk] = (double)Lm * P.dt * sdot;
+            }
+            double sd = 0.0;
+            for (int a = 0; a < D; ++a) sd += (double)Hz[a];
+            gth[nt] = (double)Lm * sd * I.dSdD;
+        }
+        __syncthreads();
+        if (tb.use_lds) {
+            for (int e = threadIdx.x; e < ext_all; e += blockDim.x) {
+                const T v = tile[e];
+                if (v == T(0)) continue;
+                int l = e / PS;
+                const int f = e - l * PS;
+                long long o = I.node_off;
+                for (int a = D - 1; a >= 0; --a) {
+                    const int la = l % tb.ext[a];
+                    l /= tb.ext[a];
+                    o += (long long)(tb.lo[a] + la) * I.stride[a];
+                }
+                atomicAdd(&mu[o * PS + f], v);
+            }
+        }
         const int wave = threadIdx.x / 64, wl = threadIdx.x % 64;
         for (int kk = 0; kk < kThetaSlots; ++kk) {
             double v = gth[kk];
@@ -1382,15 +1985,31 @@ static void step_node_launch(const PlanDev &P, int n, const void *packed, void *
     constexpr int GS = (QS <= 2) ? 2 : (QS <= 4) ? 4 : (QS <= 8) ? 8 : 16;
 #define FK_NODE(G_, AFF_, grid_, nw_, wl_)                                                     \
     k_step_node<T, D, QS, G_, AFF_><<<grid_, kBlock, 0, s>>>(                                  \
-        P, n, nw_, P.inst, wl_, P.active, P.trig, P.coords, (const T *)packed, (T *)u_out)
-    if (P.step_kind == 2) {
-        if (P.all_affine) FK_NODE(GS, true, P.split_grid, P.n_split_work, P.split_work);
-        else FK_NODE(GS, false, P.split_grid, P.n_split_work, P.split_work);
-    } else {
-        if (P.all_affine) FK_NODE(1, true, P.row_grid, P.n_row_work, P.row_work);
-        else FK_NODE(1, false, P.row_grid, P.n_row_work, P.row_work);
+        P, n, nw_, P.inst, wl_, P.fw_nodes, P.trig, P.coords, (const T *)packed, (T *)u_out)
+    if (P.n_fw_work > 0) {
+        if (P.step_kind == 2) {
+            if (P.all_affine) FK_NODE(GS, true, P.fw_split_grid, P.n_fw_split_work, P.fw_split_work);
+            else FK_NODE(GS, false, P.fw_split_grid, P.n_fw_split_work, P.fw_split_work);
+        } else {
+            if (P.all_affine) FK_NODE(1, true, P.fw_grid, P.n_fw_work, P.fw_work);
+            else FK_NODE(1, false, P.fw_grid, P.n_fw_work, P.fw_work);
+        }
     }
 #undef FK_NODE
+    // separable nodes, one launch per box class
+#define FK_BOX(c_, L_)                                                                         \
+    if (P.n_box_work[c_] > 0) {                                                                \
+        if (P.all_affine)                                                                      \
+            k_step_box<T, D, QS, L_, true><<<P.box_grid[c_], kBlock, 0, s>>>(                  \
+                P, n, P.n_box_work[c_], P.inst, P.box_work + P.box_work_off[c_], P.box_nodes,  \
+                P.trig, P.coords, (const T *)packed, (T *)u_out);                              \
+        else                                                                                   \
+            k_step_box<T, D, QS, L_, false><<<P.box_grid[c_], kBlock, 0, s>>>(                 \
+                P, n, P.n_box_work[c_], P.inst, P.box_work + P.box_work_off[c_], P.box_nodes,  \
+                P.trig, P.coords, (const T *)packed, (T *)u_out);                              \
+    }
+    FK_BOX(0, 3) FK_BOX(1, 4) FK_BOX(2, 5) FK_BOX(3, 6) FK_BOX(4, 8)
+#undef FK_BOX
 }
 
 // Q* values with a compiled thread-per-node specialisation.
@@ -1454,12 +2073,13 @@ hipError_t launch_ell_apply(const PlanDev &P, bool f32, const int *cols, const v
     return hipGetLastError();
 }
 
-hipError_t launch_export_ell(const PlanDev &P, bool f32, const int *cols_in, int *cols_out,
-                             hipStream_t s)
+hipError_t launch_export_ell(const PlanDev &P, bool f32, const int *cols_in, const void *vals_in,
+                             int *cols_out, void *vals_out, hipStream_t s)
 {
-    (void)f32;
+    const int g = flat_grid(P.n_active * (long long)P.ell_width);
     FK_DISPATCH_D(P.d,
-        k_export_ell_cols<D><<<flat_grid(P.n_active * (long long)P.ell_width), kBlock, 0, s>>>(P, cols_in, cols_out));
+        if (f32) k_export_ell<float, D><<<g, kBlock, 0, s>>>(P, cols_in, (const float *)vals_in, cols_out, (float *)vals_out);
+        else k_export_ell<double, D><<<g, kBlock, 0, s>>>(P, cols_in, (const double *)vals_in, cols_out, (double *)vals_out));
     return hipGetLastError();
 }
 
@@ -1484,9 +2104,65 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename T, int D, int QS>
+static void adjoint_node_launch(const PlanDev &P, int n, const void *packed, const void *lam,
+                                void *mu, double *grad, hipStream_t s)
+{
+    const size_t lds = (size_t)P.tile_elems * sizeof(T);
+    if (P.n_fw_work > 0) {
+        if (P.all_affine)
+            k_adjoint_node<T, D, QS, true><<<P.fw_grid, kBlock, lds, s>>>(
+                P, n, P.n_fw_work, P.inst, P.fw_work, P.fw_tiles, P.fw_nodes, P.trig, P.coords,
+                (const T *)packed, (const T *)lam, (T *)mu, grad);
+        else
+            k_adjoint_node<T, D, QS, false><<<P.fw_grid, kBlock, lds, s>>>(
+                P, n, P.n_fw_work, P.inst, P.fw_work, P.fw_tiles, P.fw_nodes, P.trig, P.coords,
+                (const T *)packed, (const T *)lam, (T *)mu, grad);
+    }
+#define FK_ABOX(c_, L_)                                                                        \
+    if (P.n_box_work[c_] > 0) {                                                                \
+        if (P.all_affine)                                                                      \
+            k_adjoint_box<T, D, QS, L_, true><<<P.box_grid[c_], kBlock, lds, s>>>(             \
+                P, n, P.n_box_work[c_], P.inst, P.box_work + P.box_work_off[c_],               \
+                P.box_tiles + P.box_work_off[c_], P.box_nodes, P.trig, P.coords,               \
+                (const T *)packed, (const T *)lam, (T *)mu, grad);                             \
+        else                                                                                   \
+            k_adjoint_box<T, D, QS, L_, false><<<P.box_grid[c_], kBlock, lds, s>>>(            \
+                P, n, P.n_box_work[c_], P.inst, P.box_work + P.box_work_off[c_],               \
+                P.box_tiles + P.box_work_off[c_], P.box_nodes, P.trig, P.coords,               \
+                (const T *)packed, (const T *)lam, (T *)mu, grad);                             \
+    }
+    FK_ABOX(0, 3) FK_ABOX(1, 4) FK_ABOX(2, 5) FK_ABOX(3, 6) FK_ABOX(4, 8)
+#undef FK_ABOX
+}
+
+template <typename T, int D>
+static bool adjoint_node_dispatch(const PlanDev &P, int n, const void *packed, const void *lam,
+                                  void *mu, double *grad, hipStream_t s)
+{
+#define FK_QS(v) case v: adjoint_node_launch<T, D, v>(P, n, packed, lam, mu, grad, s); return true;
+    if constexpr (D == 1) {
+        switch (P.qs) { FK_QS(2) FK_QS(3) FK_QS(4) FK_QS(5) FK_QS(6) FK_QS(7) FK_QS(8)
+                        FK_QS(10) FK_QS(12) FK_QS(16) default: return false; }
+    } else if constexpr (D == 2) {
+        switch (P.qs) { FK_QS(2) FK_QS(3) FK_QS(4) FK_QS(5) FK_QS(6) FK_QS(7) FK_QS(8)
+                        default: return false; }
+    } else {
+        switch (P.qs) { FK_QS(2) FK_QS(3) FK_QS(4) FK_QS(5) FK_QS(6) default: return false; }
+    }
+#undef FK_QS
+}
+
 hipError_t launch_adjoint_step(const PlanDev &P, bool f32, int n, const void *packed,
                                const void *lam, void *mu, double *grad, hipStream_t s)
 {
+    if (P.step_kind != 1) {
+        bool ok = false;
+        FK_DISPATCH_D(P.d,
+            ok = f32 ? adjoint_node_dispatch<float, D>(P, n, packed, lam, mu, grad, s)
+                     : adjoint_node_dispatch<double, D>(P, n, packed, lam, mu, grad, s));
+        if (ok) return hipGetLastError();
+    }
     FK_DISPATCH_D(P.d, FK_DISPATCH_G(P.group,
         if (f32) k_adjoint_step<float, D, G><<<P.act_grid, kBlock, 0, s>>>(P, n, (const float *)packed, (const float *)lam, (float *)mu, grad);
         else k_adjoint_step<double, D, G><<<P.act_grid, kBlock, 0, s>>>(P, n, (const double *)packed, (const double *)lam, (double *)mu, grad)));

@@ -23,7 +23,7 @@ COEF = {"const": 0, "cellular2d": 1, "abc3d": 2}
 REGION = {"box": 0, "ball": 1}
 PREC = {"f64": 0, "f32": 1}
 FORM = {"fused": 0, "ell": 1}
-STEP_KERNEL = {"auto": 0, "node": 1, "group": 2, "split": 3}
+STEP_KERNEL = {"auto": 0, "node": 1, "group": 2, "split": 3, "box": 4}
 MAX_THETA = 8
 
 EXPORTED = ["fk_last_error", "fk_version", "fk_gh_rule", "fk_plan_create", "fk_plan_destroy",

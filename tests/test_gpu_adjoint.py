@@ -23,8 +23,8 @@ def _lam0(prob, seed=21):
     return rng.uniform(size=prob.shape)
 
 
-def _gpu_adjoint(probs, lam0s, prec="f64", K=4):
-    plan = Plan(probs, precision=prec, ckpt_every=K)
+def _gpu_adjoint(probs, lam0s, prec="f64", K=4, kernel="auto"):
+    plan = Plan(probs, precision=prec, ckpt_every=K, step_kernel=kernel)
     lam = torch.cat([torch.from_numpy(l.reshape(-1)) for l in lam0s]).cuda()
     grad, lamN = plan.adjoint(lam)
     torch.cuda.synchronize()
@@ -38,8 +38,9 @@ def _rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
+@pytest.mark.parametrize("kernel", ["auto", "box", "group"])
 @pytest.mark.parametrize("case", ["cell2d", "const1d", "abc3d"])
-def test_adjoint_matches_oracle_fp64(case):
+def test_adjoint_matches_oracle_fp64(case, kernel):
     if case == "cell2d":
         prob = W.cell2d(nx=65, ny=33, n_steps=14, dt=2e-3, D=2e-3, A=1.1, eps=0.2, omega=5.0)
     elif case == "const1d":
@@ -49,7 +50,7 @@ def test_adjoint_matches_oracle_fp64(case):
         prob = W.abc3d(n=13, n_steps=5, dt=0.05, D=3e-3)
     lam0 = _lam0(prob)
     g_ref, lamN_ref = oracle.adjoint(prob, lam0)
-    gg, ll = _gpu_adjoint([prob], [lam0])
+    gg, ll = _gpu_adjoint([prob], [lam0], kernel=kernel)
     g, lamN = gg[0], ll[0]
     nt = len(g_ref)
     print(case, g[:nt], g_ref)

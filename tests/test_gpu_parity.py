@@ -52,7 +52,7 @@ def test_bm1d_full(prec):
     assert err <= TOL[prec]
 
 
-@pytest.mark.parametrize("kernel", ["node", "group", "split"])
+@pytest.mark.parametrize("kernel", ["node", "group", "split", "box"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("shape", [(129, 65), (97, 53)])
 def test_cell2d_small(prec, shape, kernel):
@@ -65,7 +65,7 @@ def test_cell2d_small(prec, shape, kernel):
     assert err <= TOL[prec]
 
 
-@pytest.mark.parametrize("kernel", ["node", "group", "split"])
+@pytest.mark.parametrize("kernel", ["node", "group", "split", "box"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_abc3d_small(prec, kernel):
     prob = W.abc3d(n=21, n_steps=12, dt=0.02, D=2e-3)
@@ -76,7 +76,7 @@ def test_abc3d_small(prec, kernel):
     assert err <= TOL[prec]
 
 
-@pytest.mark.parametrize("kernel", ["node", "group", "split"])
+@pytest.mark.parametrize("kernel", ["node", "group", "split", "box"])
 def test_box_exit_2d_and_ragged_q(kernel):
     """Box exit on both axes (separable exit mass), odd Q* and a grid that is
     not a multiple of any tile."""
@@ -191,17 +191,22 @@ def test_graph_replay_matches_eager():
     plan.close()
 
 
-def test_batched_uneven_grids_match_single_instances():
+@pytest.mark.parametrize("kernel", ["auto", "box"])
+def test_batched_uneven_grids_match_single_instances(kernel):
     probs = W.cell2d_batch(n_inst=5, n_steps=30, max_m=3)
-    plan = Plan(probs, precision="f64", use_graph=True)
+    plan = Plan(probs, precision="f64", use_graph=True, step_kernel=kernel)
     out = plan.forward([0])
     torch.cuda.synchronize()
     parts = plan.split(out)
     for p, g in zip(probs, parts):
         ref = oracle.solve(p, snaps=[0])
         assert _maxerr(g.cpu().numpy(), ref) <= 1e-12
-        single = _run(p, "f64", [0])[0]
-        assert np.array_equal(g.cpu().numpy(), single)
+        single = _run(p, "f64", [0], step_kernel=kernel)[0]
+        if kernel == "box":
+            # same kernels in the single-instance plan: identical sums
+            assert np.array_equal(g.cpu().numpy(), single)
+        else:
+            assert _maxerr(g.cpu().numpy(), single) <= 1e-13
     plan.close()
 
 

@@ -538,3 +538,29 @@ def test_adjoint_matches_central_differences(which):
         fd = _fd_grad(prob, k, 1e-6, rec, lam)
         scale = max(abs(fd), 1e-8 * np.abs(lam).sum())
         assert abs(grad[k] - fd) <= 1e-5 * scale + 1e-9, (k, grad[k], fd)
+
+
+def _amplification(prob, n_from, n_to, eps=1e-9, seed=0):
+    base = oracle.solve(prob, snaps=[n_from, n_to])
+    cls = oracle.node_class(prob)
+    rng = np.random.default_rng(seed)
+    u = base[0] + eps * rng.standard_normal(prob.shape) * (cls == 0)
+    for n in range(n_from - 1, n_to - 1, -1):
+        u = oracle.step(prob, n, u)
+    return float(np.abs(u - base[1]).max()) / eps
+
+
+def test_conditioning_depends_on_resolution():
+    """The scheme (tensor Hermite interpolant with PCHIP slopes) amplifies a
+    perturbation of the state strongly when diffusion is far below the grid
+    scale (seeded batch instance 16: 129x65, D = 1.25e-4), and damps it on the
+    resolved 513x257 workload.  Any rounding (FP32 apply: ~6e-8) is amplified the
+    same way, which bounds the attainable FP32 accuracy on such instances."""
+    coarse = W.cell2d_batch()[16].replace(n_steps=1000)
+    assert coarse.shape == (129, 65)
+    a_coarse = _amplification(coarse, 1000, 900)
+    fine = W.cell2d(n_steps=100)
+    a_fine = _amplification(fine, 100, 0)
+    print(a_coarse, a_fine)
+    assert a_coarse > 1e3
+    assert a_fine < 1.0
