@@ -184,6 +184,7 @@ def main():
         for p in probs:
             u32_parts.append(u32[off:off + p.n_nodes])
             off += p.n_nodes
+        errs = []
         for i, p in enumerate(probs):
             pl = Plan(p, precision="f64", use_graph=False)
             torch.cuda.synchronize()
@@ -194,15 +195,47 @@ def main():
             e1.record(stream)
             torch.cuda.synchronize()
             t_plain += e0.elapsed_time(e1)
-            err = max(err, float((o[0].cpu() - u32_parts[i]).abs().max()))
+            errs.append(float((o[0].cpu() - u32_parts[i]).abs().max()))
             pl.close()
         plain_rate = Ja * N / (t_plain * 1e-3)
+        errs = np.array(errs)
         result["f64_plain_single_instance"] = {
             "gp_steps_per_s": plain_rate, "ms_all_instances": t_plain,
             "speedup_of_batched_f32": value / plain_rate,
-            "max_abs_diff_f32_batched_vs_f64": err}
+            "f32_vs_f64_max_abs_diff": {
+                "max": float(errs.max()), "median": float(np.median(errs)),
+                "instances_within_1e-5": int((errs <= 1e-5).sum()), "instances": len(errs),
+                "note": "instances beyond 1e-5 are the coarse, advection-dominated ones whose "
+                        "FP64 scheme amplifies any perturbation (see DESIGN.md, conditioning)"}}
         log(f"plain FP64: {plain_rate:.4e} gp-steps/s, speedup {value / plain_rate:.2f}, "
-            f"max|f32-f64| {err:.2e}")
+            f"f32 vs f64: max {errs.max():.2e} median {np.median(errs):.2e}")
+
+        # batched FP32 adjoint of the mean of u^0 over each disc
+        import oracle
+        pa = Plan(probs, precision="f32", ckpt_every=64)
+        lam = torch.zeros(pa.n_nodes, dtype=torch.float32, device="cuda")
+        off = 0
+        for p in probs:
+            m = torch.from_numpy((oracle.node_class(p) == 0).reshape(-1).astype(np.float32))
+            lam[off:off + p.n_nodes] = (m / m.sum()).cuda()
+            off += p.n_nodes
+        pa.adjoint(lam)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g, _ = pa.adjoint(lam)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_adj = e0.elapsed_time(e1)
+        pa.close()
+        result["adjoint_batched_f32"] = {
+            "objective": "mean of u^0 over each instance's disc; gradient w.r.t. (A, eps, omega, D)",
+            "ms_per_pass": ms_adj, "gp_steps_per_s": Ja * N / (ms_adj * 1e-3),
+            "includes": "checkpointed forward (K = 64), segment recompute, transposed sweep",
+            "fwd_plus_adj_gp_steps_per_s": Ja * N / ((ms_adj + ms_step) * 1e-3),
+            "grad_instance0": [float(x) for x in g[0].cpu()]}
+        log(f"adjoint: {ms_adj:.1f} ms per pass")
 
         # assembled ELL form on the single 513x257 instance (HBM roofline)
         single = W.cell2d()
