@@ -1,19 +1,23 @@
-"""Throughput of the backward Feynman-Kac pass on one MI355X.
+"""Throughput of the backward Feynman-Kac pass and its adjoint on one MI355X.
 
-A bench step is one whole backward pass u^N -> u^0 (all 1000 time steps) over
-the batched workload: 64 seeded cellular-flow instances on uneven grids
-(129x65 .. 1025x513), 8x8 Gauss-Hermite nodes, dt = 1e-3, FP32 apply with FP64
-landing points and cells, all instances in one plan whose step loop is
-captured once in a HIP graph and replayed.  Inputs are resident in HBM before
-the timed region.  value = active grid points x time steps per second, summed
-over instances.
+A bench step is the whole hot path over the batched workload: one backward
+pass u^N -> u^0 (all 1000 time steps) followed by one adjoint pass (the
+gradient of each instance's disc-mean exit probability with respect to
+(A, eps, omega, D), with u checkpointed every 64 steps and recomputed).  The
+workload is 64 seeded cellular-flow instances on uneven grids (129x65 ..
+1025x513), 8x8 Gauss-Hermite nodes, dt = 1e-3, FP32 apply with FP64 landing
+points and cells, all instances in one plan (the forward step loop captured
+once in a HIP graph and replayed).  Inputs are resident in HBM before the
+timed region.  value = active grid points x time steps per second of
+forward + adjoint, summed over instances.
 
-Reported beside it: the plain FP64 single-instance GPU path on the same 64
-instances (one plan per instance, per-step launches, no graph), the max abs
-difference of the FP32 batch from that FP64 path, per-kernel durations, the
-roofline of the dominant kernel timed live with HIP events on its launch
-stream, the assembled (ELL) form on the single 513x257 instance against the HBM
-roofline, and the CPU oracle timed on a bounded sample.
+Reported beside it: forward-only and adjoint-only rates; the plain FP64
+single-instance GPU path on the same 64 instances (one plan per instance,
+per-step launches, no graph) with the FP32-vs-FP64 differences of u^0 and of
+the gradients; per-kernel durations; the roofline of the dominant kernel
+timed live with HIP events on its launch stream; the assembled (ELL) form on
+the single 513x257 instance against the HBM roofline; and the CPU oracle
+(forward + adjoint) timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -32,10 +36,11 @@ import workloads as W  # noqa: E402
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (published)
 PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64 (published)
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E (published)
+CKPT = 64
 
 
-def node_kernel_flops(d: int, qs: int):
-    """Algorithmic flops of the thread-per-node step per active node.
+def step_kernel_flops(d: int, qs: int):
+    """Algorithmic flops of the thread-per-node forward step per active node.
 
     FP64 (classification): d*qs per-axis landing coordinates, each z = c + S a
     (2), ball distance (2), floor guess (2), exact fix-up (4), in-cell position
@@ -49,21 +54,35 @@ def node_kernel_flops(d: int, qs: int):
     return f64, fp
 
 
-def alu_roofline(probs, plan, ms_kernel: float, kernel: str):
-    d, qs = probs[0].d, probs[0].gh_q
-    Ja = sum(plan.active_count)
-    f64, f32 = node_kernel_flops(d, qs)
-    if plan.precision == "f64":
+def adjoint_kernel_flops(d: int, qs: int):
+    """Algorithmic flops of the thread-per-node adjoint step per active node (2D).
+
+    FP64: the landing classification as in the forward step.  Plan precision,
+    per tensor point: value and z-derivative Hermite bases of the inner axis
+    (34), the interpolant gradient as two (d+1)-term contractions over the
+    2^d corners (64), the weighted gradient sums (11) and the 2^d (d+1)
+    transposed weights (17); per outer axis point the two bases (34).  The
+    2^d (d+1) = 12 scatter adds per point run as FP64 LDS atomics and are not
+    counted as flops."""
+    Q = qs ** d
+    f64 = 12 * d * qs + (d - 1) * Q
+    fp = Q * (34 + 64 + 11 + 17) + 34 * qs
+    return f64, fp
+
+
+def alu_roofline(flops, n_nodes: int, ms_kernel: float, kernel: str, precision: str):
+    f64, f32 = flops
+    if precision == "f64":
         f64, f32 = f64 + f32, 0
     # FP32-equivalent flops: an FP64 flop takes two FP32 flops of issue rate
-    eq = Ja * (2 * f64 + f32)
+    eq = n_nodes * (2 * f64 + f32)
     achieved = eq / (ms_kernel * 1e-3) / 1e12
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
             "kernel": kernel, "launch_ms": round(ms_kernel, 5),
             "flops_per_active_node": {"fp64": f64, "fp32": f32,
                                       "note": "FP64 counted twice (half the FP32 issue rate)"},
-            "active_nodes_per_launch": Ja}
+            "active_nodes_per_launch": n_nodes}
 
 
 def ell_roofline(plan, ms_apply: float):
@@ -80,6 +99,13 @@ def ell_roofline(plan, ms_apply: float):
             "launch_ms": round(ms_apply, 5), "bytes_per_launch": bytes_, "ell_width": W_}
 
 
+def disc_mean_weights(probs, dtype, device):
+    """lam0 = dJ/du^0 for J = mean of u^0 over each instance's disc nodes."""
+    import torch
+    parts = [torch.from_numpy(W.region_mean_weights(p).reshape(-1)) for p in probs]
+    return torch.cat(parts).to(device=device, dtype=dtype)
+
+
 def cpu_baseline(probs, n_sample_steps: int):
     import oracle
     oracle.build(force=False)
@@ -88,24 +114,25 @@ def cpu_baseline(probs, n_sample_steps: int):
     for p in probs:
         sample = p.replace(n_steps=n_sample_steps)
         oracle.solve(sample, snaps=[0])
+        oracle.adjoint(sample, W.region_mean_weights(sample))
         gp += oracle.active_nodes(sample).shape[0] * n_sample_steps
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": gp / dt, "unit": "grid-point-steps/s", "cores": cores, "kind": "oracle",
             "seconds": round(dt, 2),
-            "sample": f"all {len(probs)} instances, first {n_sample_steps} of "
-                      f"{probs[0].n_steps} steps (steps are equal in cost), FP64 C oracle, "
-                      f"OpenMP over active nodes"}
+            "sample": f"all {len(probs)} instances, first {n_sample_steps} of {probs[0].n_steps} "
+                      f"steps (steps are equal in cost), forward pass + adjoint (recomputing "
+                      f"u in full), FP64 C oracle, OpenMP over active nodes"}
 
 
-def timed_passes(plan, k: int, stream):
+def event_time(fn, k: int, stream):
     import torch
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     out = None
     e0.record(stream)
     for _ in range(k):
-        out = plan.forward([0])
+        out = fn()
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / k, out
@@ -116,7 +143,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="headline line only")
     args = ap.parse_args()
@@ -134,28 +161,56 @@ def main():
     probs = W.cell2d_batch()
     N = probs[0].n_steps
     log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)  # noqa: E731
-    log(f"workload cell2d_batch64: {len(probs)} instances, N={N}, FP32 apply, graph")
+    log(f"workload cell2d_batch64: {len(probs)} instances, N={N}, FP32 apply, forward + adjoint")
 
-    plan = Plan(probs, precision="f32", use_graph=True)
+    plan = Plan(probs, precision="f32", use_graph=True, ckpt_every=CKPT)
     Ja = sum(plan.active_count)
+    lam0 = disc_mean_weights(probs, plan.dtype, plan.device)
+
+    def one_step():
+        u = plan.forward([0])
+        g, _ = plan.adjoint(lam0)
+        return u, g
+
     for _ in range(args.warmup):
-        plan.forward([0])
+        one_step()
     torch.cuda.synchronize()
-    ms_step, out32 = timed_passes(plan, args.steps, stream)
+    ms_step, (out32, g32) = event_time(one_step, args.steps, stream)
     assert plan.check_flags() == 0
     value = Ja * N / (ms_step * 1e-3)
-    log(f"{ms_step:.2f} ms per pass, {value:.4e} gp-steps/s")
+    log(f"{ms_step:.2f} ms per forward + adjoint, {value:.4e} gp-steps/s")
 
-    prof = plan.profile_pass()
-    kernels_ms = {k: v[0] for k, v in prof.items() if v[1]}
-    roof = alu_roofline(probs, plan, prof["step_fused"][0], "k_step_node (fused step)")
+    ms_fwd, _ = event_time(lambda: plan.forward([0]), args.steps, stream)
+    ms_adj, _ = event_time(lambda: plan.adjoint(lam0), max(1, args.steps // 2), stream)
+    log(f"forward {ms_fwd:.2f} ms, adjoint {ms_adj:.2f} ms")
+
+    prof_f = plan.profile_pass()
+    prof_a = plan.profile_adjoint(lam0)
+    kernels_ms = {"forward": {k: v[0] for k, v in prof_f.items() if v[1]},
+                  "adjoint": {k: v[0] for k, v in prof_a.items() if v[1]}}
+    d, qs = probs[0].d, probs[0].gh_q
+    # per bench step: the fused forward step runs in the forward pass (whose
+    # checkpoints the adjoint reuses) and once more per recomputed step of the
+    # adjoint; the transposed step once per step
+    n_recomp = prof_a["recompute_step"][1]
+    t_step_kernel = prof_f["step_fused"][0] * (N + n_recomp)
+    t_adj_kernel = prof_a["adjoint_step"][0] * prof_a["adjoint_step"][1]
+    if t_adj_kernel >= t_step_kernel:
+        roof = alu_roofline(adjoint_kernel_flops(d, qs), Ja, prof_a["adjoint_step"][0],
+                            "k_adjoint_node (transposed step)", plan.precision)
+    else:
+        roof = alu_roofline(step_kernel_flops(d, qs), Ja, prof_f["step_fused"][0],
+                            "k_step_node (fused step)", plan.precision)
+    roof["share_of_step"] = round(max(t_adj_kernel, t_step_kernel) / ms_step, 4)
     u32 = out32[0].double().cpu()
+    g32 = g32.double().cpu().numpy()
     plan.close()
     del plan, out32
     torch.cuda.empty_cache()
 
     result = {
-        "metric": "grid-point-steps/s (active nodes x time steps per second, all instances)",
+        "metric": "grid-point-steps/s of forward + adjoint (active nodes x time steps per second, "
+                  "all instances)",
         "value": value,
         "unit": "grid-point-steps/s",
         "n_gpus": 1,
@@ -165,12 +220,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (apply; f64 landing points and cells)",
+        "dtype": "f32",
         "data": "synthetic: seeded analytic cellular flows, no dataset",
         "config": {"workload": "cell2d_batch64: 64 seeded cellular-flow instances, grids "
                                "(128m+1)x(64m+1) m~U{1..8}, disc exit r=0.3, 8x8 Gauss-Hermite, "
-                               "dt=1e-3, 1000 steps, one plan, one captured HIP graph",
-                   "instances": len(probs), "active_nodes": Ja, "time_steps": N},
+                               "dt=1e-3, 1000 steps, one plan; step = backward pass (captured HIP "
+                               "graph) + adjoint of the disc-mean exit probability w.r.t. "
+                               "(A, eps, omega, D), checkpoint every 64 steps",
+                   "instances": len(probs), "active_nodes": Ja, "time_steps": N,
+                   "precision": "FP32 weights and accumulation, FP64 landing points and cells"},
+        "forward_only": {"ms_per_pass": ms_fwd, "gp_steps_per_s": Ja * N / (ms_fwd * 1e-3)},
+        "adjoint_only": {"ms_per_pass": ms_adj, "gp_steps_per_s": Ja * N / (ms_adj * 1e-3),
+                         "includes": "checkpointed forward, segment recompute, transposed sweep"},
         "kernels_ms": kernels_ms,
         "roofline": roof,
     }
@@ -178,71 +239,47 @@ def main():
     if not args.no_extra:
         # plain FP64 single-instance path: one plan per instance, no graph
         t_plain = 0.0
-        err = 0.0
-        u32_parts = []
         off = 0
-        for p in probs:
-            u32_parts.append(u32[off:off + p.n_nodes])
-            off += p.n_nodes
-        errs = []
+        errs, gerr = [], []
         for i, p in enumerate(probs):
-            pl = Plan(p, precision="f64", use_graph=False)
+            pl = Plan(p, precision="f64", use_graph=False, ckpt_every=CKPT)
+            lam_i = disc_mean_weights([p], pl.dtype, pl.device)
             torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            o = pl.forward([0])
-            e1.record(stream)
-            torch.cuda.synchronize()
-            t_plain += e0.elapsed_time(e1)
-            errs.append(float((o[0].cpu() - u32_parts[i]).abs().max()))
+            t, (o, g) = event_time(lambda: (pl.forward([0]), pl.adjoint(lam_i)[0]), 1, stream)
+            t_plain += t
+            errs.append(float((o[0].cpu() - u32[off:off + p.n_nodes]).abs().max()))
+            g64 = g.cpu().numpy()[0]
+            gerr.append((float(np.abs(g32[i, :len(g64)] - g64).max()), float(np.abs(g64).max())))
+            off += p.n_nodes
             pl.close()
         plain_rate = Ja * N / (t_plain * 1e-3)
         errs = np.array(errs)
+        gabs = np.array([e for e, _ in gerr])
+        big = [e / n for e, n in gerr if n >= 1e-3]
         result["f64_plain_single_instance"] = {
             "gp_steps_per_s": plain_rate, "ms_all_instances": t_plain,
             "speedup_of_batched_f32": value / plain_rate,
-            "f32_vs_f64_max_abs_diff": {
+            "f32_vs_f64_u0_max_abs_diff": {
                 "max": float(errs.max()), "median": float(np.median(errs)),
                 "instances_within_1e-5": int((errs <= 1e-5).sum()), "instances": len(errs),
                 "note": "instances beyond 1e-5 are the coarse, advection-dominated ones whose "
-                        "FP64 scheme amplifies any perturbation (see DESIGN.md, conditioning)"}}
+                        "FP64 scheme amplifies any perturbation (see DESIGN.md, conditioning)"},
+            "f32_vs_f64_grad": {
+                "max_abs_diff": float(gabs.max()), "median_abs_diff": float(np.median(gabs)),
+                "rel_diff_where_norm_ge_1e-3": {"max": float(max(big)), "median": float(np.median(big)),
+                                                "instances": len(big)},
+                "note": "instances whose disc-mean exit probability barely moves (gradient "
+                        "norm below 1e-3) are compared in absolute terms only"}}
         log(f"plain FP64: {plain_rate:.4e} gp-steps/s, speedup {value / plain_rate:.2f}, "
-            f"f32 vs f64: max {errs.max():.2e} median {np.median(errs):.2e}")
-
-        # batched FP32 adjoint of the mean of u^0 over each disc
-        import oracle
-        pa = Plan(probs, precision="f32", ckpt_every=64)
-        lam = torch.zeros(pa.n_nodes, dtype=torch.float32, device="cuda")
-        off = 0
-        for p in probs:
-            m = torch.from_numpy((oracle.node_class(p) == 0).reshape(-1).astype(np.float32))
-            lam[off:off + p.n_nodes] = (m / m.sum()).cuda()
-            off += p.n_nodes
-        pa.adjoint(lam)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        g, _ = pa.adjoint(lam)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms_adj = e0.elapsed_time(e1)
-        pa.close()
-        result["adjoint_batched_f32"] = {
-            "objective": "mean of u^0 over each instance's disc; gradient w.r.t. (A, eps, omega, D)",
-            "ms_per_pass": ms_adj, "gp_steps_per_s": Ja * N / (ms_adj * 1e-3),
-            "includes": "checkpointed forward (K = 64), segment recompute, transposed sweep",
-            "fwd_plus_adj_gp_steps_per_s": Ja * N / ((ms_adj + ms_step) * 1e-3),
-            "grad_instance0": [float(x) for x in g[0].cpu()]}
-        log(f"adjoint: {ms_adj:.1f} ms per pass")
+            f"u0 diff max {errs.max():.2e} median {np.median(errs):.2e}, "
+            f"grad abs diff max {gabs.max():.2e}, rel (norm >= 1e-3) median {np.median(big):.2e}")
 
         # assembled ELL form on the single 513x257 instance (HBM roofline)
         single = W.cell2d()
         pe = Plan(single, precision="f32", form="ell", use_graph=True)
         pe.forward([0])
         torch.cuda.synchronize()
-        ms_ell, _ = timed_passes(pe, 1, stream)
+        ms_ell, _ = event_time(lambda: pe.forward([0]), 1, stream)
         pp = pe.profile_pass()
         result["ell_single_instance"] = {
             "workload": "cell2d 513x257, 1000 steps, FP32, assembled each step",

@@ -209,7 +209,11 @@ fk_status fk_check_flags(fk_plan *p, void *stream, int *flags);
  * n_inst * FK_MAX_THETA, overwritten; entry [i * FK_MAX_THETA + k] is dJ/dtheta_k
  * of instance i for k < n_theta, theta = (coef[0..np-1], D)) and, if lamN is
  * not NULL, dJ/du^N (device, one field; zero on exit nodes).
- * u is checkpointed every ckpt_every steps (fk_options) and recomputed. */
+ * u is checkpointed every ckpt_every steps (fk_options) and recomputed.
+ * With ckpt_every > 0, fk_forward stores these checkpoints on its way, and an
+ * fk_adjoint enqueued after it on the same stream starts from them instead of
+ * running the forward pass again (same values: the pass is deterministic);
+ * any other stream, or a workspace change, makes fk_adjoint recompute them. */
 fk_status fk_adjoint(fk_plan *p, const void *lam0, double *grad, void *lamN,
                      void *stream);
 
@@ -220,6 +224,17 @@ fk_status fk_adjoint(fk_plan *p, const void *lam0, double *grad, void *lamN,
  * (0 for kinds the plan's form does not launch); counts[4] (host) receives the
  * number of launches timed.  Synchronises stream. */
 fk_status fk_profile_pass(fk_plan *p, double *ms, int *counts, void *stream);
+
+/* Measurement hook for the adjoint: runs fk_adjoint(p, lam0, grad, NULL,
+ * stream) with HIP events around every kernel group of the reverse sweep and
+ * returns the mean duration in milliseconds per step of each group in ms[4]
+ * (host): [0] slope pass of u^{n+1} and the clearing of mu, [1] transposed
+ * step (the scatter of A_n^T lam^n and the theta-gradient), [2] transposed
+ * slope pass with the image fold, [3] forward step recomputed inside a
+ * checkpoint segment; counts[4] (host) receives the number of steps timed.
+ * Arguments and errors as fk_adjoint.  Synchronises stream. */
+fk_status fk_profile_adjoint(fk_plan *p, const void *lam0, double *grad, double *ms,
+                             int *counts, void *stream);
 
 #ifdef __cplusplus
 }

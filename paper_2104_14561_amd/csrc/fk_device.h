@@ -1,4 +1,8 @@
-// fk_kernels.hip -- gfx950 kernels of the backward Feynman-Kac step.
+// fk_device.h -- gfx950 device code of the backward Feynman-Kac step.
+//
+// Kernels are templates here; the launcher sources (fk_launch.hip and the
+// per-(precision, dimension) instances of fk_node_inst.hip) instantiate them,
+// so that the library builds as several translation units in parallel.
 //
 // One backward step u^{n+1} -> u^n (paper Section 3.1, Scheme 1; matrix form
 // u^n = Q Psi^n F^n u^{n+1}, Eq. (e36)) is two passes:
@@ -27,6 +31,8 @@
 // c = x + b dt, z = c + S a, with every product rounded (no contraction), so
 // that cells agree bit for bit with any implementation that follows the same
 // order.
+#pragma once
+
 #include "fk_internal.h"
 
 #include <cmath>
@@ -223,12 +229,14 @@ __device__ inline double trig_arg(const DevInst &I, const double *tf, int a, dou
     return x;
 }
 
+template <int D>
 __device__ inline void drift(const DevInst &I, const double *tf, const double2 *trig,
                              const int *idx, double *b)
 {
 #pragma clang fp contract(off)
     if (I.coef_kind == 0) {
-        for (int a = 0; a < I.d; ++a) b[a] = I.coef[a];
+#pragma unroll
+        for (int a = 0; a < D; ++a) b[a] = I.coef[a];
     } else if (I.coef_kind == 1) {
         const double2 t0 = trig[I.coord_off[0] + idx[0]];
         const double2 t1 = trig[I.coord_off[1] + idx[1]];
@@ -249,13 +257,16 @@ __device__ inline void drift(const DevInst &I, const double *tf, const double2 *
 }
 
 // d b_a / d theta_k for the drift parameters (theta_k, k < np); db[k*3 + a].
+template <int D>
 __device__ inline int drift_dtheta(const DevInst &I, const double *tf, const double2 *trig,
                                    const int *idx, double *db)
 {
+#pragma unroll
     for (int k = 0; k < 12; ++k) db[k] = 0.0;
     if (I.coef_kind == 0) {
-        for (int a = 0; a < I.d; ++a) db[a * 3 + a] = 1.0;
-        return I.d;
+#pragma unroll
+        for (int a = 0; a < D; ++a) db[a * 3 + a] = 1.0;
+        return D;
     } else if (I.coef_kind == 1) {
         const double A = I.coef[0], eps = I.coef[1];
         const double swt = tf[1], cwt = tf[2], t = tf[3];
@@ -311,7 +322,7 @@ __device__ inline void node_centre(const DevInst &I, const double *coords, const
 {
 #pragma clang fp contract(off)
     double b[3];
-    drift(I, tf, trig, idx, b);
+    drift<D>(I, tf, trig, idx, b);
     for (int a = 0; a < D; ++a) c[a] = coord(I, coords, a, idx[a]) + b[a] * dt;
 }
 
@@ -1115,6 +1126,16 @@ __global__ void __launch_bounds__(kBlock) k_export_cells(PlanDev P, int inst, in
     }
 }
 
+// Add to an LDS entry (workgroup-scope atomic; a different scope from the
+// global atomics, so that the compiler keeps the two apart).  The tiles hold
+// FP64 in both precisions: on gfx950 an LDS FP64 atomic add issues about ten
+// times faster than an FP32 one (measured ~20 against ~200 CU cycles per wave
+// instruction), and the tile sum gains precision on the way.
+__device__ inline void lds_add(double *p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // ---------------------------------------------------------------------------
 // Assembled form (the paper's GPU formulation, Section 3.2.1): A_n stored in
 // ELL, each row the dense box of nodes covered by its landing points times
@@ -1130,7 +1151,7 @@ __global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n, int *
 {
     constexpr int PS = RecStride<D>::value;
     extern __shared__ unsigned char smem_raw[];
-    T *box = reinterpret_cast<T *>(smem_raw);
+    double *box = reinterpret_cast<double *>(smem_raw);   // FP64 LDS atomics (fast on gfx950)
     const T *Wq = weights<T>(P);
     const int lane = threadIdx.x % G;
     const int slot = threadIdx.x / G;
@@ -1140,8 +1161,8 @@ __global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n, int *
         const bool valid = slot < it.count;
         const DevInst &I = P.inst[it.inst];
         const int W = I.ell_w;
-        T *mybox = box + (long long)slot * P.ell_width;
-        for (int k = lane; k < W; k += G) mybox[k] = T(0);
+        double *mybox = box + (long long)slot * P.ell_width;
+        for (int k = lane; k < W; k += G) mybox[k] = 0.0;
         __syncthreads();
         int idx[3] = {0, 0, 0};
         int origin[3] = {0, 0, 0};
@@ -1182,7 +1203,7 @@ __global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n, int *
                         atomicOr(P.flags, 2);
                         continue;
                     }
-                    atomicAdd(&mybox[off * (D + 1)], wv);
+                    lds_add(&mybox[off * (D + 1)], (double)wv);
                     for (int a = 0; a < D; ++a) {
                         T ws = wq;
                         for (int i = 0; i < D; ++i) {
@@ -1190,7 +1211,7 @@ __global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n, int *
                             if (i == a) ws *= bit ? B[i].d1 : B[i].d0;
                             else ws *= bit ? B[i].v1 : B[i].v0;
                         }
-                        atomicAdd(&mybox[off * (D + 1) + 1 + a], ws);
+                        lds_add(&mybox[off * (D + 1) + 1 + a], (double)ws);
                     }
                 }
             }
@@ -1212,7 +1233,7 @@ __global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n, int *
                     nd += (long long)ia * I.stride[a];
                 }
                 cols[I.ell_off + k * rows + r] = (int)(nd * PS + f);
-                vals[I.ell_off + k * rows + r] = mybox[k];
+                vals[I.ell_off + k * rows + r] = (T)mybox[k];
             }
             if (lane == 0) exit_mass[row] = em;
         }
@@ -1383,7 +1404,7 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_step(PlanDev P, int n,
                     }
                 }
                 double db[12];
-                const int nt = drift_dtheta(I, tf, P.trig, idx, db);
+                const int nt = drift_dtheta<D>(I, tf, P.trig, idx, db);
                 for (int kk = 0; kk < nt; ++kk) {
                     double sdot = 0.0;
                     for (int a = 0; a < D; ++a) sdot += (double)Gz[a] * db[kk * 3 + a];
@@ -1411,13 +1432,148 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_step(PlanDev P, int n,
     }
 }
 
-// Thread-per-node adjoint step.  Lane = active node; the innermost axis is
-// hoisted as in k_step_node.  The transposed interpolation weights of all
-// nodes of a work item go into an LDS tile of mu covering their landing
-// footprint (host-computed box), flushed once with global atomics; items
-// whose box does not fit (or wraps a periodic seam) add to global memory.
+
+// LDS accumulator (FP64) of mu for one work item: D + 1 field planes (value, then the
+// slope along each axis), each a box of nodes [lo, lo + ext) with the
+// innermost axis padded to `pitch` entries (host-chosen so that the rows of a
+// wave's patch fall on distinct banks).  Entries outside the box, or every
+// entry when the box does not fit (use == false), go to global memory.
+template <typename T, int D>
+struct MuTile {
+    static constexpr int NF = D + 1;
+    double *lds;
+    int lo[3], ext[3];
+    int pitch, plane, total;
+    bool use;
+
+    __device__ void init(double *mem, const TileBox &tb)
+    {
+        lds = mem;
+        use = tb.use_lds != 0;
+        plane = 1;
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = tb.lo[a];
+            ext[a] = tb.ext[a];
+        }
+        pitch = tb.pad;
+        for (int a = 0; a < D - 1; ++a) plane *= ext[a];
+        plane *= pitch;
+        total = NF * plane;
+    }
+
+    __device__ void clear() const
+    {
+        if (use)
+            for (int e = threadIdx.x; e < total; e += blockDim.x) lds[e] = 0.0;
+    }
+
+    // plane offset of the cell whose lowest corner is k when all 2^D corners
+    // lie in the box, else -1
+    __device__ int cell_offset(const int *k) const
+    {
+        if (!use) return -1;
+        int off = 0;
+        bool in = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const int l = k[a] - lo[a];
+            in = in && l >= 0 && l + 1 < ext[a];
+            off = (a == D - 1) ? off * pitch + l : off * ext[a] + l;
+        }
+        return in ? off : -1;
+    }
+
+    // plane offset of one node, or -1 outside the box
+    __device__ int node_offset(const int *k) const
+    {
+        if (!use) return -1;
+        int off = 0;
+        bool in = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const int l = k[a] - lo[a];
+            in = in && l >= 0 && l < ext[a];
+            off = (a == D - 1) ? off * pitch + l : off * ext[a] + l;
+        }
+        return in ? off : -1;
+    }
+
+    // add the tile to mu (node records of stride PS) with global atomics
+    template <int PS>
+    __device__ void flush(const DevInst &I, T *mu) const
+    {
+        if (!use) return;
+        for (int e = threadIdx.x; e < total; e += blockDim.x) {
+            const T v = (T)lds[e];
+            if (v == T(0)) continue;
+            const int f = e / plane;
+            int r = e - f * plane;
+            const int ll = r % pitch;
+            if (ll >= ext[D - 1]) continue;
+            r /= pitch;
+            long long o = I.node_off + (long long)(lo[D - 1] + ll) * I.stride[D - 1];
+            for (int a = D - 2; a >= 0; --a) {
+                const int la = r % ext[a];
+                r /= ext[a];
+                o += (long long)(lo[a] + la) * I.stride[a];
+            }
+            atomicAdd(&mu[o * PS + f], v);
+        }
+    }
+};
+
+// Reduce per-lane theta-gradient terms over the workgroup and add them to the
+// instance's slots (one atomic per slot and work item).
+__device__ inline void reduce_theta(double (*red)[kThetaSlots], const double *gth,
+                                    double *grad, int inst)
+{
+    const int wave = threadIdx.x / 64, wl = threadIdx.x % 64;
+    for (int kk = 0; kk < kThetaSlots; ++kk) {
+        double v = gth[kk];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (wl == 0) red[wave][kk] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kThetaSlots) {
+        double v = 0.0;
+        for (int wv = 0; wv < kBlock / 64; ++wv) v += red[wv][threadIdx.x];
+        if (v != 0.0) atomicAdd(&grad[inst * kThetaSlots + threadIdx.x], v);
+    }
+}
+
+// theta-gradient of one node from the weighted interpolant gradients:
+// Gz = sum_q w_q grad I(z_q), Hz = sum_q w_q a_q . grad I(z_q).
+template <int D, typename T>
+__device__ inline void node_theta(const PlanDev &P, const DevInst &I, const double *tf,
+                                  const double2 *trig, const int *idx, T Lm, const T *Gz,
+                                  const T *Hz, double *gth)
+{
+    double db[12];
+    const int nt = drift_dtheta<D>(I, tf, trig, idx, db);
+    double sd = 0.0;
+    for (int a = 0; a < D; ++a) sd += (double)Hz[a];
+    const double gD = (double)Lm * sd * I.dSdD;
+    // constant indices only, so that gth and db stay in registers
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        double sdot = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) sdot += (double)Gz[a] * db[kk * 3 + a];
+        gth[kk] = kk < nt ? (double)Lm * P.dt * sdot : (kk == nt ? gD : 0.0);
+    }
+    gth[4] = nt == 4 ? gD : 0.0;
+}
+
+// Thread-per-node adjoint step.  Lane = active node.  For each inside landing
+// point the kernel adds the transposed interpolation weights (2^D corners x
+// (value, D slopes)) times lam_j w_q to mu, and accumulates the interpolant's
+// gradient for the theta-derivative.  The innermost axis' landing data (cell,
+// in-cell position, width, exit flag, ball distance) are evaluated once per
+// node; the Hermite bases are rebuilt from them per point, which keeps the
+// kernel's registers low enough for several waves per SIMD.  The scatter goes
+// to the work item's LDS tile (field planes, padded rows), flushed once.
 template <typename T, int D, int QS, bool AFF>
-__global__ void __launch_bounds__(kBlock) k_adjoint_node(
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 2))) k_adjoint_node(
     const PlanDev P, int n, int n_work, const DevInst *__restrict__ insts,
     const WorkItem *__restrict__ work, const TileBox *__restrict__ tiles,
     const int *__restrict__ nodes, const double2 *__restrict__ trig,
@@ -1427,7 +1583,6 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_node(
     constexpr int PS = RecStride<D>::value;
     using R = typename RecT<T, PS>::type;
     extern __shared__ unsigned char smem_raw[];
-    T *tile = reinterpret_cast<T *>(smem_raw);
     __shared__ double red[kBlock / 64][kThetaSlots];
     const R *rec = reinterpret_cast<const R *>(packed);
     const double *ga = P.gh_a;
@@ -1435,39 +1590,18 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_node(
     const WorkRange wr = work_range(0, n_work);
     for (int w = wr.begin; w < wr.end; w += wr.step) {
         const WorkItem it = work[w];
-        const TileBox tb = tiles[w];
         const DevInst &I = insts[it.inst];
-        int ext_all = PS;
-        for (int a = 0; a < D; ++a) ext_all *= tb.ext[a];
-        if (tb.use_lds) {
-            for (int e = threadIdx.x; e < ext_all; e += blockDim.x) tile[e] = T(0);
-        }
+        double *const tmem = reinterpret_cast<double *>(smem_raw);
+        MuTile<T, D> tile;
+        tile.init(tmem, tiles[w]);
+        tile.clear();
         __syncthreads();
-        // mu entry (node index, field) -> LDS tile or global
-        auto scatter = [&](const int *cidx, int f, T v) {
-            if (tb.use_lds) {
-                int off = 0;
-                bool in = true;
-                for (int a = 0; a < D; ++a) {
-                    const int l = cidx[a] - tb.lo[a];
-                    in = in && l >= 0 && l < tb.ext[a];
-                    off = off * tb.ext[a] + l;
-                }
-                if (in) {
-                    atomicAdd(&tile[off * PS + f], v);
-                    return;
-                }
-            }
-            long long o = I.node_off;
-            for (int a = 0; a < D; ++a) o += (long long)cidx[a] * I.stride[a];
-            atomicAdd(&mu[o * PS + f], v);
-        };
         double gth[kThetaSlots];
         for (int kk = 0; kk < kThetaSlots; ++kk) gth[kk] = 0.0;
         const bool valid = (int)threadIdx.x < it.count;
         const int node = valid ? nodes[it.first + threadIdx.x] : 0;
-        const T L = valid ? lam[I.node_off + node] : T(0);
-        if (valid && L != T(0)) {
+        const T Lm = valid ? lam[I.node_off + node] : T(0);
+        if (valid && Lm != T(0)) {
             int idx[3];
             split_node<D>(I, node, idx);
             const double *tf = time_factors(P, n, it.inst);
@@ -1477,135 +1611,210 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_node(
             const double r2 = I.r2;
             constexpr int AI = D - 1;
             int kin[QS];
-            Basis<T> bin[QS], dbin[QS];
+            T sin_[QS], hin[QS];
             bool exin[QS];
             double din[QS];
 #pragma unroll
             for (int q = 0; q < QS; ++q) {
                 const AxisEval e = eval_axis_t<AFF>(I, coords, AI, c[AI], ga[q]);
                 kin[q] = e.k;
-                bin[q] = hermite<T>(e.s, e.h);
-                dbin[q] = hermite_dz<T>(e.s, e.h);
+                sin_[q] = (T)e.s;
+                hin[q] = (T)e.h;
                 exin[q] = e.ex;
                 din[q] = e.dz2;
             }
             T Gz[3] = {T(0), T(0), T(0)}, Hz[3] = {T(0), T(0), T(0)};
-            // one landing point: gradient of the interpolant and the scatter
-            auto point = [&](const int *k, const Basis<T> *B, const Basis<T> *Bz, const T *aq, T wq) {
-                R p[1 << D];
-                gather_corners<D, R>(rec, I, k, p);
-                T gz[3];
-                hermite_grad<T, D, R>(p, B, Bz, gz);
-                for (int a = 0; a < D; ++a) {
-                    Gz[a] += wq * gz[a];
-                    Hz[a] += wq * aq[a] * gz[a];
-                }
-                const T Lw = L * wq;
-                for (int cb = 0; cb < (1 << D); ++cb) {
-                    int cidx[3];
-                    T wv = Lw;
-                    for (int a = 0; a < D; ++a) {
-                        const int bit = (cb >> (D - 1 - a)) & 1;
-                        cidx[a] = k[a] + bit;
-                        wv *= bit ? B[a].v1 : B[a].v0;
-                    }
-                    scatter(cidx, 0, wv);
-                    for (int a = 0; a < D; ++a) {
-                        T ws = Lw;
-                        for (int i = 0; i < D; ++i) {
-                            const int bit = (cb >> (D - 1 - i)) & 1;
-                            if (i == a) ws *= bit ? B[i].d1 : B[i].d0;
-                            else ws *= bit ? B[i].v1 : B[i].v0;
-                        }
-                        scatter(cidx, 1 + a, ws);
-                    }
-                }
-            };
-            if constexpr (D == 1) {
-#pragma unroll
-                for (int q = 0; q < QS; ++q) {
-                    if (exin[q] || (ball && din[q] >= r2)) continue;
-                    int k[1] = {kin[q]};
-                    const T aq[1] = {(T)ga[q]};
-                    point(k, &bin[q], &dbin[q], aq, w1[q]);
-                }
-            } else if constexpr (D == 2) {
+            if constexpr (D == 2) {
+                const long long s0 = I.stride[0];
+                const int pl = tile.plane, pitch = tile.pitch;
                 for (int q0 = 0; q0 < QS; ++q0) {
                     const AxisEval e0 = eval_axis_t<AFF>(I, coords, 0, c[0], ga[q0]);
                     if (e0.ex) continue;
-                    const Basis<T> X = hermite<T>(e0.s, e0.h), dX = hermite_dz<T>(e0.s, e0.h);
+                    const Basis<T> X = hermite<T>(e0.s, e0.h), Xz = hermite_dz<T>(e0.s, e0.h);
+                    const T w0 = w1[q0], a0 = (T)ga[q0];
+                    const T Lw0 = Lm * w0;
+                    // the row's LDS offset (cell k0, innermost cell 0) when the
+                    // whole row of cells k0 fits the tile along axis 0
+                    const int l0 = e0.k - tile.lo[0];
+                    const bool row_in = tile.use && l0 >= 0 && l0 + 1 < tile.ext[0];
+                    const int row_off = l0 * pitch - tile.lo[1];
+                    const long long row = I.node_off + (long long)e0.k * s0;
 #pragma unroll
                     for (int q1 = 0; q1 < QS; ++q1) {
-                        if (exin[q1] || (ball && ball_exit2(e0.dz2, din[q1], r2))) continue;
-                        int k[2] = {e0.k, kin[q1]};
-                        const Basis<T> B[2] = {X, bin[q1]}, Bz[2] = {dX, dbin[q1]};
-                        const T aq[2] = {(T)ga[q0], (T)ga[q1]};
-                        point(k, B, Bz, aq, w1[q0] * w1[q1]);
+                        bool ex = exin[q1];
+                        if (ball) ex = ex || ball_exit2(e0.dz2, din[q1], r2);
+                        if (ex) continue;
+                        const T s = sin_[q1], h = hin[q1];
+                        const T om = T(1) - s;
+                        const T yv0 = (T(1) + T(2) * s) * om * om, yv1 = s * s * (T(3) - T(2) * s);
+                        const T yd0 = h * s * om * om, yd1 = h * s * s * (s - T(1));
+                        const T zv0 = (T(6) * s * s - T(6) * s) / h, zv1 = (T(6) * s - T(6) * s * s) / h;
+                        const T zd0 = T(1) - T(4) * s + T(3) * s * s, zd1 = T(3) * s * s - T(2) * s;
+                        const int k1 = kin[q1];
+                        const long long b = row + k1;
+                        const R p00 = rec[b], p01 = rec[b + 1], p10 = rec[b + s0], p11 = rec[b + s0 + 1];
+                        // interpolant gradient: d/dz0 (Xz, Y) and d/dz1 (X, Yz)
+                        const T A0z = p00.x * Xz.v0 + p10.x * Xz.v1 + p00.y * Xz.d0 + p10.y * Xz.d1;
+                        const T A1z = p01.x * Xz.v0 + p11.x * Xz.v1 + p01.y * Xz.d0 + p11.y * Xz.d1;
+                        const T C0z = p00.z * Xz.v0 + p10.z * Xz.v1;
+                        const T C1z = p01.z * Xz.v0 + p11.z * Xz.v1;
+                        const T g0 = yv0 * A0z + yv1 * A1z + yd0 * C0z + yd1 * C1z;
+                        const T A0 = p00.x * X.v0 + p10.x * X.v1 + p00.y * X.d0 + p10.y * X.d1;
+                        const T A1 = p01.x * X.v0 + p11.x * X.v1 + p01.y * X.d0 + p11.y * X.d1;
+                        const T C0 = p00.z * X.v0 + p10.z * X.v1;
+                        const T C1 = p01.z * X.v0 + p11.z * X.v1;
+                        const T g1 = zv0 * A0 + zv1 * A1 + zd0 * C0 + zd1 * C1;
+                        const T wq = w0 * w1[q1];
+                        Gz[0] += wq * g0;
+                        Gz[1] += wq * g1;
+                        Hz[0] += wq * a0 * g0;
+                        Hz[1] += wq * (T)ga[q1] * g1;
+                        // transposed weights: corner (e0, e1) gets
+                        // value X.v Y.v, slope-0 X.d Y.v, slope-1 X.v Y.d
+                        const T w1q = Lw0 * w1[q1];
+                        const T v0 = w1q * yv0, v1 = w1q * yv1, d0 = w1q * yd0, d1 = w1q * yd1;
+                        const T e00 = X.v0 * v0, e01 = X.v0 * v1, e10 = X.v1 * v0, e11 = X.v1 * v1;
+                        const T f00 = X.d0 * v0, f01 = X.d0 * v1, f10 = X.d1 * v0, f11 = X.d1 * v1;
+                        const T g00 = X.v0 * d0, g01 = X.v0 * d1, g10 = X.v1 * d0, g11 = X.v1 * d1;
+                        const int l1 = k1 - tile.lo[1];
+                        if (row_in && l1 >= 0 && l1 + 1 < tile.ext[1]) {
+                            double *t = tmem + row_off + k1;
+                            lds_add(t, e00);
+                            lds_add(t + 1, e01);
+                            lds_add(t + pitch, e10);
+                            lds_add(t + pitch + 1, e11);
+                            t += pl;
+                            lds_add(t, f00);
+                            lds_add(t + 1, f01);
+                            lds_add(t + pitch, f10);
+                            lds_add(t + pitch + 1, f11);
+                            t += pl;
+                            lds_add(t, g00);
+                            lds_add(t + 1, g01);
+                            lds_add(t + pitch, g10);
+                            lds_add(t + pitch + 1, g11);
+                        } else {
+                            T *m = mu + b * PS;
+                            const long long sp = s0 * PS;
+                            atomicAdd(m, e00);
+                            atomicAdd(m + PS, e01);
+                            atomicAdd(m + sp, e10);
+                            atomicAdd(m + sp + PS, e11);
+                            atomicAdd(m + 1, f00);
+                            atomicAdd(m + PS + 1, f01);
+                            atomicAdd(m + sp + 1, f10);
+                            atomicAdd(m + sp + PS + 1, f11);
+                            atomicAdd(m + 2, g00);
+                            atomicAdd(m + PS + 2, g01);
+                            atomicAdd(m + sp + 2, g10);
+                            atomicAdd(m + sp + PS + 2, g11);
+                        }
                     }
                 }
             } else {
-                for (int q0 = 0; q0 < QS; ++q0) {
-                    const AxisEval e0 = eval_axis_t<AFF>(I, coords, 0, c[0], ga[q0]);
-                    if (e0.ex) continue;
-                    const Basis<T> X = hermite<T>(e0.s, e0.h), dX = hermite_dz<T>(e0.s, e0.h);
-                    for (int q1 = 0; q1 < QS; ++q1) {
-                        const AxisEval e1 = eval_axis_t<AFF>(I, coords, 1, c[1], ga[q1]);
-                        if (e1.ex) continue;
-                        const Basis<T> Y = hermite<T>(e1.s, e1.h), dY = hermite_dz<T>(e1.s, e1.h);
+                // d = 1 and d = 3: one landing point at a time
+                auto point = [&](const int *k, const Basis<T> *B, const Basis<T> *Bz, const T *aq, T wq) {
+                    R p[1 << D];
+                    gather_corners<D, R>(rec, I, k, p);
+                    T gz[3];
+                    hermite_grad<T, D, R>(p, B, Bz, gz);
+                    for (int a = 0; a < D; ++a) {
+                        Gz[a] += wq * gz[a];
+                        Hz[a] += wq * aq[a] * gz[a];
+                    }
+                    const T Lw = Lm * wq;
+                    // transposed weights: corner cb, field f (value, then the
+                    // slope along axis f - 1, whose basis swaps to the slope one)
+                    constexpr int NC = 1 << D;
+                    T vals[NC][D + 1];
 #pragma unroll
-                        for (int q2 = 0; q2 < QS; ++q2) {
-                            if (exin[q2]) continue;
-                            if (ball) {
-                                const double dz[3] = {e0.dz2, e1.dz2, din[q2]};
-                                if (ball_exit(dz, 3, r2)) continue;
+                    for (int cb = 0; cb < NC; ++cb) {
+#pragma unroll
+                        for (int f = 0; f <= D; ++f) {
+                            T v = Lw;
+#pragma unroll
+                            for (int i = 0; i < D; ++i) {
+                                const int bi = (cb >> (D - 1 - i)) & 1;
+                                if (f == i + 1) v *= bi ? B[i].d1 : B[i].d0;
+                                else v *= bi ? B[i].v1 : B[i].v0;
                             }
-                            int k[3] = {e0.k, e1.k, kin[q2]};
-                            const Basis<T> B[3] = {X, Y, bin[q2]}, Bz[3] = {dX, dY, dbin[q2]};
-                            const T aq[3] = {(T)ga[q0], (T)ga[q1], (T)ga[q2]};
-                            point(k, B, Bz, aq, w1[q0] * w1[q1] * w1[q2]);
+                            vals[cb][f] = v;
+                        }
+                    }
+                    const int co = tile.cell_offset(k);
+                    if (co >= 0) {
+#pragma unroll
+                        for (int cb = 0; cb < NC; ++cb) {
+                            int loff = co;
+#pragma unroll
+                            for (int a = 0; a < D; ++a)
+                                if ((cb >> (D - 1 - a)) & 1) {
+                                    int st = 1;
+                                    if (a < D - 1) {
+                                        st = tile.pitch;
+                                        for (int a2 = a + 1; a2 < D - 1; ++a2) st *= tile.ext[a2];
+                                    }
+                                    loff += st;
+                                }
+#pragma unroll
+                            for (int f = 0; f <= D; ++f) lds_add(tmem + f * tile.plane + loff, vals[cb][f]);
+                        }
+                    } else {
+                        long long gbase = I.node_off;
+                        for (int a = 0; a < D; ++a) gbase += (long long)k[a] * I.stride[a];
+#pragma unroll
+                        for (int cb = 0; cb < NC; ++cb) {
+                            long long goff = gbase;
+#pragma unroll
+                            for (int a = 0; a < D; ++a)
+                                if ((cb >> (D - 1 - a)) & 1) goff += I.stride[a];
+#pragma unroll
+                            for (int f = 0; f <= D; ++f) atomicAdd(mu + goff * PS + f, vals[cb][f]);
+                        }
+                    }
+                };
+                if constexpr (D == 1) {
+#pragma unroll
+                    for (int q = 0; q < QS; ++q) {
+                        if (exin[q] || (ball && din[q] >= r2)) continue;
+                        int k[1] = {kin[q]};
+                        const Basis<T> B = hermite<T>(sin_[q], hin[q]);
+                        const Basis<T> Bz = hermite_dz<T>(sin_[q], hin[q]);
+                        const T aq[1] = {(T)ga[q]};
+                        point(k, &B, &Bz, aq, w1[q]);
+                    }
+                } else {
+                    for (int q0 = 0; q0 < QS; ++q0) {
+                        const AxisEval e0 = eval_axis_t<AFF>(I, coords, 0, c[0], ga[q0]);
+                        if (e0.ex) continue;
+                        const Basis<T> X = hermite<T>(e0.s, e0.h), dX = hermite_dz<T>(e0.s, e0.h);
+                        for (int q1 = 0; q1 < QS; ++q1) {
+                            const AxisEval e1 = eval_axis_t<AFF>(I, coords, 1, c[1], ga[q1]);
+                            if (e1.ex) continue;
+                            const Basis<T> Y = hermite<T>(e1.s, e1.h), dY = hermite_dz<T>(e1.s, e1.h);
+#pragma unroll
+                            for (int q2 = 0; q2 < QS; ++q2) {
+                                if (exin[q2]) continue;
+                                if (ball) {
+                                    const double dz[3] = {e0.dz2, e1.dz2, din[q2]};
+                                    if (ball_exit(dz, 3, r2)) continue;
+                                }
+                                int k[3] = {e0.k, e1.k, kin[q2]};
+                                const Basis<T> Z = hermite<T>(sin_[q2], hin[q2]);
+                                const Basis<T> dZ = hermite_dz<T>(sin_[q2], hin[q2]);
+                                const Basis<T> B[3] = {X, Y, Z}, Bz[3] = {dX, dY, dZ};
+                                const T aq[3] = {(T)ga[q0], (T)ga[q1], (T)ga[q2]};
+                                point(k, B, Bz, aq, w1[q0] * w1[q1] * w1[q2]);
+                            }
                         }
                     }
                 }
             }
-            double db[12];
-            const int nt = drift_dtheta(I, tf, trig, idx, db);
-            for (int kk = 0; kk < nt; ++kk) {
-                double sdot = 0.0;
-                for (int a = 0; a < D; ++a) sdot += (double)Gz[a] * db[kk * 3 + a];
-                gth[kk] = (double)L * P.dt * sdot;
-            }
-            double sd = 0.0;
-            for (int a = 0; a < D; ++a) sd += (double)Hz[a];
-            gth[nt] = (double)L * sd * I.dSdD;
+            node_theta<D, T>(P, I, tf, trig, idx, Lm, Gz, Hz, gth);
         }
         __syncthreads();
-        if (tb.use_lds) {
-            for (int e = threadIdx.x; e < ext_all; e += blockDim.x) {
-                const T v = tile[e];
-                if (v == T(0)) continue;
-                int l = e / PS;
-                const int f = e - l * PS;
-                long long o = I.node_off;
-                for (int a = D - 1; a >= 0; --a) {
-                    const int la = l % tb.ext[a];
-                    l /= tb.ext[a];
-                    o += (long long)(tb.lo[a] + la) * I.stride[a];
-                }
-                atomicAdd(&mu[o * PS + f], v);
-            }
-        }
-        const int wave = threadIdx.x / 64, wl = threadIdx.x % 64;
-        for (int kk = 0; kk < kThetaSlots; ++kk) {
-            double v = gth[kk];
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            if (wl == 0) red[wave][kk] = v;
-        }
-        __syncthreads();
-        if (threadIdx.x < kThetaSlots) {
-            double v = 0.0;
-            for (int wv = 0; wv < kBlock / 64; ++wv) v += red[wv][threadIdx.x];
-            if (v != 0.0) atomicAdd(&grad[it.inst * kThetaSlots + threadIdx.x], v);
-        }
+        tile.template flush<PS>(I, mu);
+        reduce_theta(red, gth, grad, it.inst);
         __syncthreads();
     }
 }
@@ -1625,7 +1834,6 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_box(
     constexpr int PS = RecStride<D>::value;
     using R = typename RecT<T, PS>::type;
     extern __shared__ unsigned char smem_raw[];
-    T *tile = reinterpret_cast<T *>(smem_raw);
     __shared__ double red[kBlock / 64][kThetaSlots];
     const R *rec = reinterpret_cast<const R *>(packed);
     const double *ga = P.gh_a;
@@ -1633,26 +1841,17 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_box(
     const WorkRange wr = work_range(0, n_work);
     for (int w = wr.begin; w < wr.end; w += wr.step) {
         const WorkItem it = work[w];
-        const TileBox tb = tiles[w];
         const DevInst &I = insts[it.inst];
-        int ext_all = PS;
-        for (int a = 0; a < D; ++a) ext_all *= tb.ext[a];
-        if (tb.use_lds)
-            for (int e = threadIdx.x; e < ext_all; e += blockDim.x) tile[e] = T(0);
+        double *const tmem = reinterpret_cast<double *>(smem_raw);
+        MuTile<T, D> tile;
+        tile.init(tmem, tiles[w]);
+        tile.clear();
         __syncthreads();
         auto scatter = [&](const int *cidx, int f, T v) {
-            if (tb.use_lds) {
-                int off = 0;
-                bool in = true;
-                for (int a = 0; a < D; ++a) {
-                    const int l = cidx[a] - tb.lo[a];
-                    in = in && l >= 0 && l < tb.ext[a];
-                    off = off * tb.ext[a] + l;
-                }
-                if (in) {
-                    atomicAdd(&tile[off * PS + f], v);
-                    return;
-                }
+            const int off = tile.node_offset(cidx);
+            if (off >= 0) {
+                lds_add(&tmem[f * tile.plane + off], v);
+                return;
             }
             long long o = I.node_off;
             for (int a = 0; a < D; ++a) o += (long long)cidx[a] * I.stride[a];
@@ -1747,45 +1946,11 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_box(
                     }
                 }
             }
-            double db[12];
-            const int nt = drift_dtheta(I, tf, trig, idx, db);
-            for (int kk = 0; kk < nt; ++kk) {
-                double sdot = 0.0;
-                for (int a = 0; a < D; ++a) sdot += (double)Gz[a] * db[kk * 3 + a];
-                gth[kk] = (double)Lm * P.dt * sdot;
-            }
-            double sd = 0.0;
-            for (int a = 0; a < D; ++a) sd += (double)Hz[a];
-            gth[nt] = (double)Lm * sd * I.dSdD;
+            node_theta<D, T>(P, I, tf, trig, idx, Lm, Gz, Hz, gth);
         }
         __syncthreads();
-        if (tb.use_lds) {
-            for (int e = threadIdx.x; e < ext_all; e += blockDim.x) {
-                const T v = tile[e];
-                if (v == T(0)) continue;
-                int l = e / PS;
-                const int f = e - l * PS;
-                long long o = I.node_off;
-                for (int a = D - 1; a >= 0; --a) {
-                    const int la = l % tb.ext[a];
-                    l /= tb.ext[a];
-                    o += (long long)(tb.lo[a] + la) * I.stride[a];
-                }
-                atomicAdd(&mu[o * PS + f], v);
-            }
-        }
-        const int wave = threadIdx.x / 64, wl = threadIdx.x % 64;
-        for (int kk = 0; kk < kThetaSlots; ++kk) {
-            double v = gth[kk];
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            if (wl == 0) red[wave][kk] = v;
-        }
-        __syncthreads();
-        if (threadIdx.x < kThetaSlots) {
-            double v = 0.0;
-            for (int wv = 0; wv < kBlock / 64; ++wv) v += red[wv][threadIdx.x];
-            if (v != 0.0) atomicAdd(&grad[it.inst * kThetaSlots + threadIdx.x], v);
-        }
+        tile.template flush<PS>(I, mu);
+        reduce_theta(red, gth, grad, it.inst);
         __syncthreads();
     }
 }
@@ -1891,7 +2056,7 @@ __global__ void __launch_bounds__(kBlock) k_fold_images(PlanDev P, T *__restrict
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Launchers
+// Launch helpers
 // ---------------------------------------------------------------------------
 
 #define FK_DISPATCH_G(G_, ...)                                   \
@@ -1914,287 +2079,12 @@ __global__ void __launch_bounds__(kBlock) k_fold_images(PlanDev P, T *__restrict
     default: return hipErrorInvalidValue;                        \
     }
 
-static int flat_grid(long long n)
+static inline int flat_grid(long long n)
 {
     long long g = (n + kBlock - 1) / kBlock;
     if (g > 4096) g = 4096;
     if (g < 1) g = 1;
     return (int)g;
-}
-
-hipError_t launch_init_field(const PlanDev &P, bool f32, void *u, hipStream_t s)
-{
-    if (f32)
-        k_init_field<float><<<flat_grid(P.n_nodes), kBlock, 0, s>>>(P.chi, P.n_nodes, (float *)u);
-    else
-        k_init_field<double><<<flat_grid(P.n_nodes), kBlock, 0, s>>>(P.chi, P.n_nodes, (double *)u);
-    return hipGetLastError();
-}
-
-hipError_t launch_slopes(const PlanDev &P, bool f32, int n, const void *u, void *packed,
-                         hipStream_t s)
-{
-    FK_DISPATCH_D(P.d,
-        if (f32) k_slopes<float, D><<<P.slope_grid, kBlock, 0, s>>>(P, n, 0, P.n_slope_work, (const float *)u, (float *)packed);
-        else k_slopes<double, D><<<P.slope_grid, kBlock, 0, s>>>(P, n, 0, P.n_slope_work, (const double *)u, (double *)packed));
-    return hipGetLastError();
-}
-
-hipError_t launch_tables(const PlanDev &P, int n, hipStream_t s)
-{
-    if (P.n_table_work == 0) return hipSuccess;
-    const int g = P.n_table_work >= 8 ? (P.n_table_work + 7) / 8 * 8 : P.n_table_work;
-    FK_DISPATCH_D(P.d,
-        k_slopes<double, D><<<g, kBlock, 0, s>>>(P, n, 0, P.n_table_work, nullptr, nullptr));
-    return hipGetLastError();
-}
-
-template <typename T, int D, int G, int NQ>
-static void step_fused_launch(const PlanDev &P, int n, const void *packed, void *u_out,
-                              hipStream_t s)
-{
-    k_step_fused<T, D, G, NQ><<<P.act_grid, kBlock, 0, s>>>(
-        P, n, P.inst, P.act_work, P.active, P.trig, P.coords, (const T *)packed, (T *)u_out);
-}
-
-template <typename T, int D>
-static hipError_t step_fused_dispatch(const PlanDev &P, int n, const void *packed, void *u_out,
-                                      hipStream_t s)
-{
-    const int nq = (P.n_quad + P.group - 1) / P.group;
-    switch (P.group) {
-    case 4: step_fused_launch<T, D, 4, 1>(P, n, packed, u_out, s); break;
-    case 8: step_fused_launch<T, D, 8, 1>(P, n, packed, u_out, s); break;
-    case 16: step_fused_launch<T, D, 16, 1>(P, n, packed, u_out, s); break;
-    case 32: step_fused_launch<T, D, 32, 1>(P, n, packed, u_out, s); break;
-    case 64:
-        if (nq <= 1) step_fused_launch<T, D, 64, 1>(P, n, packed, u_out, s);
-        else if (nq <= 2) step_fused_launch<T, D, 64, 2>(P, n, packed, u_out, s);
-        else if (nq <= 4) step_fused_launch<T, D, 64, 4>(P, n, packed, u_out, s);
-        else return hipErrorInvalidValue;
-        break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <typename T, int D, int QS>
-static void step_node_launch(const PlanDev &P, int n, const void *packed, void *u_out,
-                             hipStream_t s)
-{
-    constexpr int GS = (QS <= 2) ? 2 : (QS <= 4) ? 4 : (QS <= 8) ? 8 : 16;
-#define FK_NODE(G_, AFF_, grid_, nw_, wl_)                                                     \
-    k_step_node<T, D, QS, G_, AFF_><<<grid_, kBlock, 0, s>>>(                                  \
-        P, n, nw_, P.inst, wl_, P.fw_nodes, P.trig, P.coords, (const T *)packed, (T *)u_out)
-    if (P.n_fw_work > 0) {
-        if (P.step_kind == 2) {
-            if (P.all_affine) FK_NODE(GS, true, P.fw_split_grid, P.n_fw_split_work, P.fw_split_work);
-            else FK_NODE(GS, false, P.fw_split_grid, P.n_fw_split_work, P.fw_split_work);
-        } else {
-            if (P.all_affine) FK_NODE(1, true, P.fw_grid, P.n_fw_work, P.fw_work);
-            else FK_NODE(1, false, P.fw_grid, P.n_fw_work, P.fw_work);
-        }
-    }
-#undef FK_NODE
-    // separable nodes, one launch per box class
-#define FK_BOX(c_, L_)                                                                         \
-    if (P.n_box_work[c_] > 0) {                                                                \
-        if (P.all_affine)                                                                      \
-            k_step_box<T, D, QS, L_, true><<<P.box_grid[c_], kBlock, 0, s>>>(                  \
-                P, n, P.n_box_work[c_], P.inst, P.box_work + P.box_work_off[c_], P.box_nodes,  \
-                P.trig, P.coords, (const T *)packed, (T *)u_out);                              \
-        else                                                                                   \
-            k_step_box<T, D, QS, L_, false><<<P.box_grid[c_], kBlock, 0, s>>>(                 \
-                P, n, P.n_box_work[c_], P.inst, P.box_work + P.box_work_off[c_], P.box_nodes,  \
-                P.trig, P.coords, (const T *)packed, (T *)u_out);                              \
-    }
-    FK_BOX(0, 3) FK_BOX(1, 4) FK_BOX(2, 5) FK_BOX(3, 6) FK_BOX(4, 8)
-#undef FK_BOX
-}
-
-// Q* values with a compiled thread-per-node specialisation.
-template <typename T, int D>
-static bool step_node_dispatch(const PlanDev &P, int n, const void *packed, void *u_out,
-                               hipStream_t s)
-{
-#define FK_QS(v) case v: step_node_launch<T, D, v>(P, n, packed, u_out, s); return true;
-    if constexpr (D == 1) {
-        switch (P.qs) { FK_QS(2) FK_QS(3) FK_QS(4) FK_QS(5) FK_QS(6) FK_QS(7) FK_QS(8)
-                        FK_QS(10) FK_QS(12) FK_QS(16) default: return false; }
-    } else if constexpr (D == 2) {
-        switch (P.qs) { FK_QS(2) FK_QS(3) FK_QS(4) FK_QS(5) FK_QS(6) FK_QS(7) FK_QS(8)
-                        default: return false; }
-    } else {
-        switch (P.qs) { FK_QS(2) FK_QS(3) FK_QS(4) FK_QS(5) FK_QS(6) default: return false; }
-    }
-#undef FK_QS
-}
-
-bool step_node_compiled(int d, int qs)
-{
-    if (d == 1) return (qs >= 2 && qs <= 8) || qs == 10 || qs == 12 || qs == 16;
-    if (d == 2) return qs >= 2 && qs <= 8;
-    if (d == 3) return qs >= 2 && qs <= 6;
-    return false;
-}
-
-hipError_t launch_step_fused(const PlanDev &P, bool f32, int n, const void *packed, void *u_out,
-                             hipStream_t s)
-{
-    if (P.step_kind != 1) {
-        bool ok = false;
-        FK_DISPATCH_D(P.d,
-            ok = f32 ? step_node_dispatch<float, D>(P, n, packed, u_out, s)
-                     : step_node_dispatch<double, D>(P, n, packed, u_out, s));
-        if (ok) return hipGetLastError();
-    }
-    FK_DISPATCH_D(P.d,
-        return f32 ? step_fused_dispatch<float, D>(P, n, packed, u_out, s)
-                   : step_fused_dispatch<double, D>(P, n, packed, u_out, s));
-    return hipSuccess;
-}
-
-hipError_t launch_assemble_ell(const PlanDev &P, bool f32, int n, int *cols, void *vals,
-                               void *exit_mass, hipStream_t s)
-{
-    const size_t lds = (size_t)(kBlock / P.group) * P.ell_width * (f32 ? 4 : 8);
-    FK_DISPATCH_D(P.d, FK_DISPATCH_G(P.group,
-        if (f32) k_assemble_ell<float, D, G><<<P.act_grid, kBlock, lds, s>>>(P, n, cols, (float *)vals, (float *)exit_mass);
-        else k_assemble_ell<double, D, G><<<P.act_grid, kBlock, lds, s>>>(P, n, cols, (double *)vals, (double *)exit_mass)));
-    return hipGetLastError();
-}
-
-hipError_t launch_ell_apply(const PlanDev &P, bool f32, const int *cols, const void *vals,
-                            const void *exit_mass, const void *packed, void *u_out, hipStream_t s)
-{
-    FK_DISPATCH_D(P.d,
-        if (f32) k_ell_apply<float, D><<<P.row_grid, kBlock, 0, s>>>(P, cols, (const float *)vals, (const float *)exit_mass, (const float *)packed, (float *)u_out);
-        else k_ell_apply<double, D><<<P.row_grid, kBlock, 0, s>>>(P, cols, (const double *)vals, (const double *)exit_mass, (const double *)packed, (double *)u_out));
-    return hipGetLastError();
-}
-
-hipError_t launch_export_ell(const PlanDev &P, bool f32, const int *cols_in, const void *vals_in,
-                             int *cols_out, void *vals_out, hipStream_t s)
-{
-    const int g = flat_grid(P.n_active * (long long)P.ell_width);
-    FK_DISPATCH_D(P.d,
-        if (f32) k_export_ell<float, D><<<g, kBlock, 0, s>>>(P, cols_in, (const float *)vals_in, cols_out, (float *)vals_out);
-        else k_export_ell<double, D><<<g, kBlock, 0, s>>>(P, cols_in, (const double *)vals_in, cols_out, (double *)vals_out));
-    return hipGetLastError();
-}
-
-hipError_t launch_export_cells(const PlanDev &P, int inst, int n, int *cells,
-                               unsigned char *exit_flags, hipStream_t s)
-{
-    FK_DISPATCH_D(P.d,
-        k_export_cells<D><<<4096, kBlock, 0, s>>>(P, inst, n, cells, exit_flags));
-    return hipGetLastError();
-}
-
-hipError_t launch_clear_flags(const PlanDev &P, hipStream_t s)
-{
-    k_clear_flags<<<1, 1, 0, s>>>(P.flags);
-    return hipGetLastError();
-}
-
-hipError_t launch_zero(void *p, size_t bytes, hipStream_t s)
-{
-    const long long n = (long long)(bytes / 4);
-    k_zero<<<flat_grid(n), kBlock, 0, s>>>((unsigned int *)p, n);
-    return hipGetLastError();
-}
-
-template <typename T, int D, int QS>
-static void adjoint_node_launch(const PlanDev &P, int n, const void *packed, const void *lam,
-                                void *mu, double *grad, hipStream_t s)
-{
-    const size_t lds = (size_t)P.tile_elems * sizeof(T);
-    if (P.n_fw_work > 0) {
-        if (P.all_affine)
-            k_adjoint_node<T, D, QS, true><<<P.fw_grid, kBlock, lds, s>>>(
-                P, n, P.n_fw_work, P.inst, P.fw_work, P.fw_tiles, P.fw_nodes, P.trig, P.coords,
-                (const T *)packed, (const T *)lam, (T *)mu, grad);
-        else
-            k_adjoint_node<T, D, QS, false><<<P.fw_grid, kBlock, lds, s>>>(
-                P, n, P.n_fw_work, P.inst, P.fw_work, P.fw_tiles, P.fw_nodes, P.trig, P.coords,
-                (const T *)packed, (const T *)lam, (T *)mu, grad);
-    }
-#define FK_ABOX(c_, L_)                                                                        \
-    if (P.n_box_work[c_] > 0) {                                                                \
-        if (P.all_affine)                                                                      \
-            k_adjoint_box<T, D, QS, L_, true><<<P.box_grid[c_], kBlock, lds, s>>>(             \
-                P, n, P.n_box_work[c_], P.inst, P.box_work + P.box_work_off[c_],               \
-                P.box_tiles + P.box_work_off[c_], P.box_nodes, P.trig, P.coords,               \
-                (const T *)packed, (const T *)lam, (T *)mu, grad);                             \
-        else                                                                                   \
-            k_adjoint_box<T, D, QS, L_, false><<<P.box_grid[c_], kBlock, lds, s>>>(            \
-                P, n, P.n_box_work[c_], P.inst, P.box_work + P.box_work_off[c_],               \
-                P.box_tiles + P.box_work_off[c_], P.box_nodes, P.trig, P.coords,               \
-                (const T *)packed, (const T *)lam, (T *)mu, grad);                             \
-    }
-    FK_ABOX(0, 3) FK_ABOX(1, 4) FK_ABOX(2, 5) FK_ABOX(3, 6) FK_ABOX(4, 8)
-#undef FK_ABOX
-}
-
-template <typename T, int D>
-static bool adjoint_node_dispatch(const PlanDev &P, int n, const void *packed, const void *lam,
-                                  void *mu, double *grad, hipStream_t s)
-{
-#define FK_QS(v) case v: adjoint_node_launch<T, D, v>(P, n, packed, lam, mu, grad, s); return true;
-    if constexpr (D == 1) {
-        switch (P.qs) { FK_QS(2) FK_QS(3) FK_QS(4) FK_QS(5) FK_QS(6) FK_QS(7) FK_QS(8)
-                        FK_QS(10) FK_QS(12) FK_QS(16) default: return false; }
-    } else if constexpr (D == 2) {
-        switch (P.qs) { FK_QS(2) FK_QS(3) FK_QS(4) FK_QS(5) FK_QS(6) FK_QS(7) FK_QS(8)
-                        default: return false; }
-    } else {
-        switch (P.qs) { FK_QS(2) FK_QS(3) FK_QS(4) FK_QS(5) FK_QS(6) default: return false; }
-    }
-#undef FK_QS
-}
-
-hipError_t launch_adjoint_step(const PlanDev &P, bool f32, int n, const void *packed,
-                               const void *lam, void *mu, double *grad, hipStream_t s)
-{
-    if (P.step_kind != 1) {
-        bool ok = false;
-        FK_DISPATCH_D(P.d,
-            ok = f32 ? adjoint_node_dispatch<float, D>(P, n, packed, lam, mu, grad, s)
-                     : adjoint_node_dispatch<double, D>(P, n, packed, lam, mu, grad, s));
-        if (ok) return hipGetLastError();
-    }
-    FK_DISPATCH_D(P.d, FK_DISPATCH_G(P.group,
-        if (f32) k_adjoint_step<float, D, G><<<P.act_grid, kBlock, 0, s>>>(P, n, (const float *)packed, (const float *)lam, (float *)mu, grad);
-        else k_adjoint_step<double, D, G><<<P.act_grid, kBlock, 0, s>>>(P, n, (const double *)packed, (const double *)lam, (double *)mu, grad)));
-    return hipGetLastError();
-}
-
-hipError_t launch_adjoint_slopes_T(const PlanDev &P, bool f32, const void *u, const void *mu,
-                                   void *lam_next, hipStream_t s)
-{
-    FK_DISPATCH_D(P.d,
-        if (f32) {
-            k_mu_value<float, D><<<flat_grid(P.n_nodes), kBlock, 0, s>>>(P, (const float *)mu, (float *)lam_next);
-            k_adjoint_slopes_T<float, D><<<P.node_grid, kBlock, 0, s>>>(P, (const float *)u, (const float *)mu, (float *)lam_next);
-            k_fold_images<float, D><<<P.node_grid, kBlock, 0, s>>>(P, (float *)lam_next);
-        } else {
-            k_mu_value<double, D><<<flat_grid(P.n_nodes), kBlock, 0, s>>>(P, (const double *)mu, (double *)lam_next);
-            k_adjoint_slopes_T<double, D><<<P.node_grid, kBlock, 0, s>>>(P, (const double *)u, (const double *)mu, (double *)lam_next);
-            k_fold_images<double, D><<<P.node_grid, kBlock, 0, s>>>(P, (double *)lam_next);
-        });
-    return hipGetLastError();
-}
-
-hipError_t launch_adjoint_init(const PlanDev &P, bool f32, const void *lam0, void *lam,
-                               hipStream_t s)
-{
-    hipError_t e = hipMemcpyAsync(lam, lam0, (size_t)P.n_nodes * (f32 ? 4 : 8),
-                                  hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return e;
-    FK_DISPATCH_D(P.d,
-        if (f32) k_fold_images<float, D><<<P.node_grid, kBlock, 0, s>>>(P, (float *)lam);
-        else k_fold_images<double, D><<<P.node_grid, kBlock, 0, s>>>(P, (double *)lam));
-    return hipGetLastError();
 }
 
 }  // namespace fk

@@ -172,6 +172,9 @@ struct fk_plan {
     int ell_box[3] = {1, 1, 1};
     int ell_width = 0;
     long long ell_total = 0;
+    // measurement: when prof is set, fk_adjoint records a HIP event after
+    // every kernel group (kind >= 0) or before one (kind -1)
+    std::vector<std::pair<hipEvent_t, int>> *prof = nullptr;
     // workspace
     std::map<std::string, Region> reg;
     size_t ws_bytes = 0;
@@ -180,6 +183,10 @@ struct fk_plan {
     // graph cache
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec = nullptr;
+    // checkpoints of u stored by the latest full fk_forward (enqueued on
+    // ckpt_stream); fk_adjoint on that stream reuses them
+    bool ckpt_valid = false;
+    hipStream_t ckpt_stream = nullptr;
     std::string gkey;
     int n_ckpt = 0;
 
@@ -457,7 +464,9 @@ fk_status build_plan(fk_plan *p)
             const double reach = drift_bound(pr, a) * pr.dt + I.S * amax;
             const double cells = std::ceil(reach / hmin) + 2.0;
             const int dil = cells > 1e9 ? (1 << 30) : (int)cells;
-            dils[a] = std::min(dil, pr.ax[a].n);
+            // a landing cell lies within ceil(reach / h) cells of its node, and
+            // its upper corner one further: the adjoint tile's halo
+            dils[a] = std::min(dil - 1, pr.ax[a].n);
             if (pr.ax[a].periodic || na == 0) {
                 blo[a] = 0;
                 bhi[a] = pr.ax[a].n - 1;
@@ -562,10 +571,17 @@ fk_status build_plan(fk_plan *p)
         const int sk = p->opt.step_kernel;
         const bool large = p->n_active >= 256LL * 4 * 64 * 2;
         const bool node_ok = fk::step_node_compiled(p->d, p->qs);
+        bool affine = true;
+        for (const fk::DevInst &I : p->inst)
+            for (int a = 0; a < p->d; ++a) affine = affine && I.affine[a];
         if (sk == 2 || !node_ok) p->step_kind = 1;
         else if (sk == 3 || (sk == 0 && !large)) p->step_kind = 2;
         else p->step_kind = 0;
-        p->use_box = node_ok && (sk == 4 || (sk == 0 && large));
+        // the separable form by default in 3D only: there a node's Q*^3
+        // points gather 8 corners each, against L^3 records of its footprint;
+        // in 2D (Q*^2 points x 4 corners vs L^2) the per-point gather is faster
+        p->use_box = node_ok && affine && fk::box_compiled(p->d, p->qs) &&
+                     (sk == 4 || (sk == 0 && large && p->d == 3));
         const int gs = std::max(2, group_of(p->qs));
         std::vector<std::vector<fk::WorkItem>> bw(fk::kBoxClasses);
         // node lists in patch order (16x16 in 2D, 4x8x8 in 3D, 256 in 1D):
@@ -636,9 +652,11 @@ fk_status build_plan(fk_plan *p)
             p->n_box_work[c2] = (int)bw[c2].size();
             p->box_work.insert(p->box_work.end(), bw[c2].begin(), bw[c2].end());
         }
-        // adjoint LDS tiles: node box of each work item widened by the reach
-        const int PS = p->d == 1 ? 2 : 4;
-        const size_t elt_b = p->f32 ? 4 : 8;
+        // adjoint LDS tiles: node box of each work item widened by the reach,
+        // d + 1 field planes, innermost axis padded to a pitch that puts the
+        // rows of a wave's patch (16 nodes in 2D, 8 in 3D) on distinct banks
+        const int NF = p->d + 1;
+        const size_t elt_b = 8;   // tiles accumulate in FP64 in both precisions
         const size_t budget = 60 * 1024;   // plus static LDS, within 64 KB per workgroup
         auto tile_of = [&](const fk::WorkItem &it, const std::vector<int> &list) {
             const fk_problem &pr = p->probs[it.inst];
@@ -655,7 +673,7 @@ fk_status build_plan(fk_plan *p)
             fk::TileBox tb;
             std::memset(&tb, 0, sizeof(tb));
             bool ok = it.count > 0;
-            size_t elems = PS;
+            size_t elems = NF;
             for (int a = 0; a < pr.d; ++a) {
                 const int dil = inst_dils[it.inst][a];
                 int lo = mn[a] - dil, hi = mx[a] + dil;
@@ -664,9 +682,21 @@ fk_status build_plan(fk_plan *p)
                 hi = std::min(hi, pr.ax[a].n - 1);
                 tb.lo[a] = lo;
                 tb.ext[a] = std::max(hi - lo + 1, 1);
-                elems *= (size_t)tb.ext[a];
+                if (a < pr.d - 1) elems *= (size_t)tb.ext[a];
             }
             for (int a = pr.d; a < 3; ++a) tb.ext[a] = 1;
+            // pitch of the innermost axis: in 2D and 3D, the next length that is
+            // 16 (2D) or 8 (3D) modulo 32 words, unless that breaks the budget
+            const int last = tb.ext[pr.d - 1];
+            int pitch = last;
+            if (pr.d >= 2) {
+                const int want = pr.d == 2 ? 16 : 8;
+                int padded = last;
+                while (padded % 32 != want) ++padded;
+                if (elems * (size_t)padded * elt_b <= budget) pitch = padded;
+            }
+            tb.pad = pitch;
+            elems *= (size_t)pitch;
             if (elems * elt_b > budget) ok = false;
             tb.use_lds = ok ? 1 : 0;
             if (ok) p->tile_elems = std::max<int>(p->tile_elems, (int)elems);
@@ -708,7 +738,7 @@ fk_status build_plan(fk_plan *p)
                     return fail(FK_ERR_UNSUPPORTED, "ELL form needs non-periodic axes");
         for (int a = 0; a < p->d; ++a) p->ell_box[a] = box[a];
         const long long W = ell_wmax;
-        if (W * (long long)(kBlock / p->G) * (p->f32 ? 4 : 8) > 64 * 1024)
+        if (W * (long long)(kBlock / p->G) * 8 > 64 * 1024)   // FP64 row boxes in LDS
             return fail(FK_ERR_UNSUPPORTED, "ELL row box too large for LDS (%lld entries)", W);
         p->ell_width = (int)W;
         p->ell_total = ell_total;
@@ -914,11 +944,11 @@ fk_status enqueue_pass(fk_plan *p, const void *u_start, int start, const int *sn
 }
 
 fk_status run_pass(fk_plan *p, const void *u_start, int start, const int *snaps, int n_snap,
-                   void *u_out, hipStream_t s)
+                   void *u_out, hipStream_t s, bool store_ckpt)
 {
-    if (!p->opt.use_graph) return enqueue_pass(p, u_start, start, snaps, n_snap, u_out, s, false);
+    if (!p->opt.use_graph) return enqueue_pass(p, u_start, start, snaps, n_snap, u_out, s, store_ckpt);
     char key[256];
-    snprintf(key, sizeof(key), "%p|%d|%p|", u_start, start, u_out);
+    snprintf(key, sizeof(key), "%p|%d|%p|%d|", u_start, start, u_out, store_ckpt ? 1 : 0);
     std::string k = key;
     for (int i = 0; i < n_snap; ++i) k += std::to_string(snaps[i]) + ",";
     if (!p->gexec || k != p->gkey) {
@@ -929,7 +959,7 @@ fk_status run_pass(fk_plan *p, const void *u_start, int start, const int *snaps,
         if (!p->cap_stream) FK_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
         hipGraph_t graph = nullptr;
         FK_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-        fk_status st = enqueue_pass(p, u_start, start, snaps, n_snap, u_out, p->cap_stream, false);
+        fk_status st = enqueue_pass(p, u_start, start, snaps, n_snap, u_out, p->cap_stream, store_ckpt);
         hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
         if (st != FK_OK) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -1072,6 +1102,7 @@ fk_status fk_plan_set_workspace(fk_plan *p, void *dev_ptr, size_t bytes, void *s
         p->gkey.clear();
     }
     p->ws = (unsigned char *)dev_ptr;
+    p->ckpt_valid = false;
     fill_dev(p);
     auto up = [&](const char *name, const void *src, size_t n) -> fk_status {
         if (n) FK_HIP(hipMemcpyAsync(p->at(name), src, n, hipMemcpyHostToDevice, s));
@@ -1108,7 +1139,13 @@ fk_status fk_forward(fk_plan *p, const int *snap_steps, int n_snap, void *u_out,
 {
     FK_TRY(need_ws(p));
     FK_TRY(check_snaps(p, snap_steps, n_snap, p->N, u_out));
-    return run_pass(p, nullptr, p->N, snap_steps, n_snap, u_out, (hipStream_t)stream);
+    // a plan built for the adjoint stores its checkpoints on the way
+    const bool store = p->opt.ckpt_every > 0;
+    p->ckpt_valid = false;
+    FK_TRY(run_pass(p, nullptr, p->N, snap_steps, n_snap, u_out, (hipStream_t)stream, store));
+    p->ckpt_valid = store;
+    p->ckpt_stream = (hipStream_t)stream;
+    return FK_OK;
 }
 
 fk_status fk_forward_from(fk_plan *p, const void *u_start, int start_step, const int *snap_steps,
@@ -1118,7 +1155,7 @@ fk_status fk_forward_from(fk_plan *p, const void *u_start, int start_step, const
     if (!u_start) return fail(FK_ERR_ARG, "null start state");
     if (start_step < 0 || start_step > p->N) return fail(FK_ERR_ARG, "start_step outside [0, N]");
     FK_TRY(check_snaps(p, snap_steps, n_snap, start_step, u_out));
-    return run_pass(p, u_start, start_step, snap_steps, n_snap, u_out, (hipStream_t)stream);
+    return run_pass(p, u_start, start_step, snap_steps, n_snap, u_out, (hipStream_t)stream, false);
 }
 
 fk_status fk_step(fk_plan *p, int n, const void *u_next, void *u_out, void *stream)
@@ -1174,6 +1211,16 @@ fk_status fk_check_flags(fk_plan *p, void *stream, int *flags)
     return FK_OK;
 }
 
+static fk_status prof_mark(fk_plan *p, int kind, hipStream_t s)
+{
+    if (!p->prof) return FK_OK;
+    hipEvent_t e;
+    FK_HIP(hipEventCreate(&e));
+    FK_HIP(hipEventRecord(e, s));
+    p->prof->push_back({e, kind});
+    return FK_OK;
+}
+
 fk_status fk_adjoint(fk_plan *p, const void *lam0, double *grad, void *lamN, void *stream)
 {
     FK_TRY(need_ws(p));
@@ -1182,8 +1229,14 @@ fk_status fk_adjoint(fk_plan *p, const void *lam0, double *grad, void *lamN, voi
     hipStream_t s = (hipStream_t)stream;
     const size_t fb = elt(p) * (size_t)p->n_nodes;
     const int K = p->opt.ckpt_every;
-    // 1. forward pass storing checkpoints
-    FK_TRY(enqueue_pass(p, nullptr, p->N, nullptr, 0, nullptr, s, true));
+    // 1. forward pass storing checkpoints, unless the latest fk_forward on this
+    //    stream stored them already
+    if (!(p->ckpt_valid && p->ckpt_stream == s)) {
+        p->ckpt_valid = false;
+        FK_TRY(enqueue_pass(p, nullptr, p->N, nullptr, 0, nullptr, s, true));
+        p->ckpt_valid = true;
+        p->ckpt_stream = s;
+    }
     // 2. reverse sweep, segment by segment from step 0 upward
     void *la = p->at("lamA"), *lb = p->at("lamB"), *mu = p->at("mu");
     double *g = (double *)p->at("grad");
@@ -1202,14 +1255,20 @@ fk_status fk_adjoint(fk_plan *p, const void *lam0, double *grad, void *lamN, voi
         for (int m = n1 - 1; m >= n0 + 1; --m) {
             void *dst = seg + (size_t)(m - n0 - 1) * fb;
             FK_LAUNCH(fk::launch_init_field(p->dev, p->f32, dst, s));
+            FK_TRY(prof_mark(p, -1, s));
             FK_TRY(enqueue_step(p, m, seg + (size_t)(m - n0) * fb, dst, s));
+            FK_TRY(prof_mark(p, 3, s));
         }
         for (int n = n0; n < n1; ++n) {
             const void *v = seg + (size_t)(n - n0) * fb;   // u^{n+1}
+            FK_TRY(prof_mark(p, -1, s));
             FK_LAUNCH(fk::launch_slopes(p->dev, p->f32, n, v, packed, s));
             FK_LAUNCH(fk::launch_zero(mu, fb * rec_stride(p->d), s));
+            FK_TRY(prof_mark(p, 0, s));
             FK_LAUNCH(fk::launch_adjoint_step(p->dev, p->f32, n, packed, la, mu, g, s));
+            FK_TRY(prof_mark(p, 1, s));
             FK_LAUNCH(fk::launch_adjoint_slopes_T(p->dev, p->f32, v, mu, lb, s));
+            FK_TRY(prof_mark(p, 2, s));
             std::swap(la, lb);
         }
     }
@@ -1272,6 +1331,39 @@ fk_status fk_profile_pass(fk_plan *p, double *ms, int *counts, void *stream)
         counts[k] = cnt[k];
     }
     return FK_OK;
+}
+
+fk_status fk_profile_adjoint(fk_plan *p, const void *lam0, double *grad, double *ms,
+                             int *counts, void *stream)
+{
+    FK_TRY(need_ws(p));
+    if (!ms || !counts) return fail(FK_ERR_ARG, "null output");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<std::pair<hipEvent_t, int>> ev;
+    p->prof = &ev;
+    const fk_status st = fk_adjoint(p, lam0, grad, nullptr, stream);
+    p->prof = nullptr;
+    fk_status rs = st;
+    if (st == FK_OK && hipStreamSynchronize(s) != hipSuccess) rs = fail(FK_ERR_HIP, "stream sync");
+    const int nk = 4;
+    double tot[nk] = {0, 0, 0, 0};
+    int cnt[nk] = {0, 0, 0, 0};
+    for (size_t i = 1; rs == FK_OK && i < ev.size(); ++i) {
+        if (ev[i].second < 0) continue;
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, ev[i - 1].first, ev[i].first) != hipSuccess) {
+            rs = fail(FK_ERR_HIP, "event timing");
+            break;
+        }
+        tot[ev[i].second] += t;
+        cnt[ev[i].second] += 1;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e.first);
+    for (int k = 0; k < nk; ++k) {
+        ms[k] = cnt[k] ? tot[k] / cnt[k] : 0.0;
+        counts[k] = cnt[k];
+    }
+    return rs;
 }
 
 }  // extern "C"

@@ -1,5 +1,6 @@
 // fk_internal.h -- device-side plan records and kernel launchers shared by the
-// host runtime (fk_host.cpp) and the gfx950 kernels (fk_kernels.hip).
+// host runtime (fk_host.cpp) and the gfx950 kernels (fk_device.h, instantiated
+// by fk_launch.hip and fk_node_inst.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -124,7 +125,7 @@ struct PlanDev {
     int ell_grid;
 };
 
-// Kernel launchers (fk_kernels.hip).  T is double or float; all return the
+// Kernel launchers (fk_launch.hip).  T is double or float; all return the
 // HIP error of the launch.
 hipError_t launch_init_field(const PlanDev &P, bool f32, void *u, hipStream_t s);
 hipError_t launch_slopes(const PlanDev &P, bool f32, int n, const void *u, void *packed,
@@ -133,6 +134,23 @@ hipError_t launch_tables(const PlanDev &P, int n, hipStream_t s);
 hipError_t launch_step_fused(const PlanDev &P, bool f32, int n, const void *packed,
                              void *u_out, hipStream_t s);
 bool step_node_compiled(int d, int qs);
+// the separable-box form: d >= 2, affine axes, a compiled Q*
+bool box_compiled(int d, int qs);
+
+// Thread-per-node and separable-box launchers, one per (precision, dimension)
+// (fk_node_inst.hip).  Each returns false when the plan's Q* (or its mix of
+// box work and axis kinds) has no compiled specialisation.
+#define FK_NODE_ENTRY(name) \
+    bool name(const PlanDev &P, int n, const void *packed, void *u_out, hipStream_t s);
+#define FK_ADJ_ENTRY(name)                                                                  \
+    bool name(const PlanDev &P, int n, const void *packed, const void *lam, void *mu,       \
+              double *grad, hipStream_t s);
+FK_NODE_ENTRY(step_node_f32_d1) FK_NODE_ENTRY(step_node_f32_d2) FK_NODE_ENTRY(step_node_f32_d3)
+FK_NODE_ENTRY(step_node_f64_d1) FK_NODE_ENTRY(step_node_f64_d2) FK_NODE_ENTRY(step_node_f64_d3)
+FK_ADJ_ENTRY(adjoint_node_f32_d1) FK_ADJ_ENTRY(adjoint_node_f32_d2) FK_ADJ_ENTRY(adjoint_node_f32_d3)
+FK_ADJ_ENTRY(adjoint_node_f64_d1) FK_ADJ_ENTRY(adjoint_node_f64_d2) FK_ADJ_ENTRY(adjoint_node_f64_d3)
+#undef FK_NODE_ENTRY
+#undef FK_ADJ_ENTRY
 hipError_t launch_assemble_ell(const PlanDev &P, bool f32, int n, int *cols, void *vals,
                                void *exit_mass, hipStream_t s);
 hipError_t launch_ell_apply(const PlanDev &P, bool f32, const int *cols, const void *vals,

@@ -1,0 +1,200 @@
+// fk_launch.hip -- launchers of the slope pass, the lane-group step and
+// adjoint (any Q*), the assembled (ELL) form, exports and utility fills.  The
+// thread-per-node and separable-box launchers live in the fk_node_inst.hip
+// instances; launch_step_fused and launch_adjoint_step pick one of them when
+// the plan's Q* has a compiled specialisation and fall back to the lane-group
+// kernels otherwise.
+#include "fk_device.h"
+
+namespace fk {
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_init_field(const PlanDev &P, bool f32, void *u, hipStream_t s)
+{
+    if (f32)
+        k_init_field<float><<<flat_grid(P.n_nodes), kBlock, 0, s>>>(P.chi, P.n_nodes, (float *)u);
+    else
+        k_init_field<double><<<flat_grid(P.n_nodes), kBlock, 0, s>>>(P.chi, P.n_nodes, (double *)u);
+    return hipGetLastError();
+}
+
+hipError_t launch_slopes(const PlanDev &P, bool f32, int n, const void *u, void *packed,
+                         hipStream_t s)
+{
+    FK_DISPATCH_D(P.d,
+        if (f32) k_slopes<float, D><<<P.slope_grid, kBlock, 0, s>>>(P, n, 0, P.n_slope_work, (const float *)u, (float *)packed);
+        else k_slopes<double, D><<<P.slope_grid, kBlock, 0, s>>>(P, n, 0, P.n_slope_work, (const double *)u, (double *)packed));
+    return hipGetLastError();
+}
+
+hipError_t launch_tables(const PlanDev &P, int n, hipStream_t s)
+{
+    if (P.n_table_work == 0) return hipSuccess;
+    const int g = P.n_table_work >= 8 ? (P.n_table_work + 7) / 8 * 8 : P.n_table_work;
+    FK_DISPATCH_D(P.d,
+        k_slopes<double, D><<<g, kBlock, 0, s>>>(P, n, 0, P.n_table_work, nullptr, nullptr));
+    return hipGetLastError();
+}
+
+template <typename T, int D, int G, int NQ>
+static void step_fused_launch(const PlanDev &P, int n, const void *packed, void *u_out,
+                              hipStream_t s)
+{
+    k_step_fused<T, D, G, NQ><<<P.act_grid, kBlock, 0, s>>>(
+        P, n, P.inst, P.act_work, P.active, P.trig, P.coords, (const T *)packed, (T *)u_out);
+}
+
+template <typename T, int D>
+static hipError_t step_fused_dispatch(const PlanDev &P, int n, const void *packed, void *u_out,
+                                      hipStream_t s)
+{
+    const int nq = (P.n_quad + P.group - 1) / P.group;
+    switch (P.group) {
+    case 4: step_fused_launch<T, D, 4, 1>(P, n, packed, u_out, s); break;
+    case 8: step_fused_launch<T, D, 8, 1>(P, n, packed, u_out, s); break;
+    case 16: step_fused_launch<T, D, 16, 1>(P, n, packed, u_out, s); break;
+    case 32: step_fused_launch<T, D, 32, 1>(P, n, packed, u_out, s); break;
+    case 64:
+        if (nq <= 1) step_fused_launch<T, D, 64, 1>(P, n, packed, u_out, s);
+        else if (nq <= 2) step_fused_launch<T, D, 64, 2>(P, n, packed, u_out, s);
+        else if (nq <= 4) step_fused_launch<T, D, 64, 4>(P, n, packed, u_out, s);
+        else return hipErrorInvalidValue;
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+bool step_node_compiled(int d, int qs)
+{
+    if (d == 1) return (qs >= 2 && qs <= 8) || qs == 10 || qs == 12 || qs == 16;
+    if (d == 2) return qs >= 2 && qs <= 8;
+    if (d == 3) return qs >= 2 && qs <= 6;
+    return false;
+}
+
+bool box_compiled(int d, int qs)
+{
+    return d >= 2 && step_node_compiled(d, qs);
+}
+
+hipError_t launch_step_fused(const PlanDev &P, bool f32, int n, const void *packed, void *u_out,
+                             hipStream_t s)
+{
+    if (P.step_kind != 1) {
+        bool ok = false;
+        switch (P.d) {
+        case 1: ok = f32 ? step_node_f32_d1(P, n, packed, u_out, s) : step_node_f64_d1(P, n, packed, u_out, s); break;
+        case 2: ok = f32 ? step_node_f32_d2(P, n, packed, u_out, s) : step_node_f64_d2(P, n, packed, u_out, s); break;
+        case 3: ok = f32 ? step_node_f32_d3(P, n, packed, u_out, s) : step_node_f64_d3(P, n, packed, u_out, s); break;
+        default: return hipErrorInvalidValue;
+        }
+        if (ok) return hipGetLastError();
+    }
+    FK_DISPATCH_D(P.d,
+        return f32 ? step_fused_dispatch<float, D>(P, n, packed, u_out, s)
+                   : step_fused_dispatch<double, D>(P, n, packed, u_out, s));
+    return hipSuccess;
+}
+
+hipError_t launch_assemble_ell(const PlanDev &P, bool f32, int n, int *cols, void *vals,
+                               void *exit_mass, hipStream_t s)
+{
+    const size_t lds = (size_t)(kBlock / P.group) * P.ell_width * sizeof(double);   // FP64 row boxes
+    FK_DISPATCH_D(P.d, FK_DISPATCH_G(P.group,
+        if (f32) k_assemble_ell<float, D, G><<<P.act_grid, kBlock, lds, s>>>(P, n, cols, (float *)vals, (float *)exit_mass);
+        else k_assemble_ell<double, D, G><<<P.act_grid, kBlock, lds, s>>>(P, n, cols, (double *)vals, (double *)exit_mass)));
+    return hipGetLastError();
+}
+
+hipError_t launch_ell_apply(const PlanDev &P, bool f32, const int *cols, const void *vals,
+                            const void *exit_mass, const void *packed, void *u_out, hipStream_t s)
+{
+    FK_DISPATCH_D(P.d,
+        if (f32) k_ell_apply<float, D><<<P.row_grid, kBlock, 0, s>>>(P, cols, (const float *)vals, (const float *)exit_mass, (const float *)packed, (float *)u_out);
+        else k_ell_apply<double, D><<<P.row_grid, kBlock, 0, s>>>(P, cols, (const double *)vals, (const double *)exit_mass, (const double *)packed, (double *)u_out));
+    return hipGetLastError();
+}
+
+hipError_t launch_export_ell(const PlanDev &P, bool f32, const int *cols_in, const void *vals_in,
+                             int *cols_out, void *vals_out, hipStream_t s)
+{
+    const int g = flat_grid(P.n_active * (long long)P.ell_width);
+    FK_DISPATCH_D(P.d,
+        if (f32) k_export_ell<float, D><<<g, kBlock, 0, s>>>(P, cols_in, (const float *)vals_in, cols_out, (float *)vals_out);
+        else k_export_ell<double, D><<<g, kBlock, 0, s>>>(P, cols_in, (const double *)vals_in, cols_out, (double *)vals_out));
+    return hipGetLastError();
+}
+
+hipError_t launch_export_cells(const PlanDev &P, int inst, int n, int *cells,
+                               unsigned char *exit_flags, hipStream_t s)
+{
+    FK_DISPATCH_D(P.d,
+        k_export_cells<D><<<4096, kBlock, 0, s>>>(P, inst, n, cells, exit_flags));
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_flags(const PlanDev &P, hipStream_t s)
+{
+    k_clear_flags<<<1, 1, 0, s>>>(P.flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s)
+{
+    const long long n = (long long)(bytes / 4);
+    k_zero<<<flat_grid(n), kBlock, 0, s>>>((unsigned int *)p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step(const PlanDev &P, bool f32, int n, const void *packed,
+                               const void *lam, void *mu, double *grad, hipStream_t s)
+{
+    if (P.step_kind != 1) {
+        bool ok = false;
+        switch (P.d) {
+        case 1: ok = f32 ? adjoint_node_f32_d1(P, n, packed, lam, mu, grad, s) : adjoint_node_f64_d1(P, n, packed, lam, mu, grad, s); break;
+        case 2: ok = f32 ? adjoint_node_f32_d2(P, n, packed, lam, mu, grad, s) : adjoint_node_f64_d2(P, n, packed, lam, mu, grad, s); break;
+        case 3: ok = f32 ? adjoint_node_f32_d3(P, n, packed, lam, mu, grad, s) : adjoint_node_f64_d3(P, n, packed, lam, mu, grad, s); break;
+        default: return hipErrorInvalidValue;
+        }
+        if (ok) return hipGetLastError();
+    }
+    FK_DISPATCH_D(P.d, FK_DISPATCH_G(P.group,
+        if (f32) k_adjoint_step<float, D, G><<<P.act_grid, kBlock, 0, s>>>(P, n, (const float *)packed, (const float *)lam, (float *)mu, grad);
+        else k_adjoint_step<double, D, G><<<P.act_grid, kBlock, 0, s>>>(P, n, (const double *)packed, (const double *)lam, (double *)mu, grad)));
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_slopes_T(const PlanDev &P, bool f32, const void *u, const void *mu,
+                                   void *lam_next, hipStream_t s)
+{
+    FK_DISPATCH_D(P.d,
+        if (f32) {
+            k_mu_value<float, D><<<flat_grid(P.n_nodes), kBlock, 0, s>>>(P, (const float *)mu, (float *)lam_next);
+            k_adjoint_slopes_T<float, D><<<P.node_grid, kBlock, 0, s>>>(P, (const float *)u, (const float *)mu, (float *)lam_next);
+            k_fold_images<float, D><<<P.node_grid, kBlock, 0, s>>>(P, (float *)lam_next);
+        } else {
+            k_mu_value<double, D><<<flat_grid(P.n_nodes), kBlock, 0, s>>>(P, (const double *)mu, (double *)lam_next);
+            k_adjoint_slopes_T<double, D><<<P.node_grid, kBlock, 0, s>>>(P, (const double *)u, (const double *)mu, (double *)lam_next);
+            k_fold_images<double, D><<<P.node_grid, kBlock, 0, s>>>(P, (double *)lam_next);
+        });
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_init(const PlanDev &P, bool f32, const void *lam0, void *lam,
+                               hipStream_t s)
+{
+    hipError_t e = hipMemcpyAsync(lam, lam0, (size_t)P.n_nodes * (f32 ? 4 : 8),
+                                  hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    FK_DISPATCH_D(P.d,
+        if (f32) k_fold_images<float, D><<<P.node_grid, kBlock, 0, s>>>(P, (float *)lam);
+        else k_fold_images<double, D><<<P.node_grid, kBlock, 0, s>>>(P, (double *)lam));
+    return hipGetLastError();
+}
+
+}  // namespace fk

@@ -29,7 +29,7 @@ MAX_THETA = 8
 EXPORTED = ["fk_last_error", "fk_version", "fk_gh_rule", "fk_plan_create", "fk_plan_destroy",
             "fk_plan_get_info", "fk_plan_layout", "fk_plan_set_workspace", "fk_forward",
             "fk_forward_from", "fk_step", "fk_export_cells", "fk_export_ell",
-            "fk_check_flags", "fk_adjoint", "fk_profile_pass"]
+            "fk_check_flags", "fk_adjoint", "fk_profile_pass", "fk_profile_adjoint"]
 
 
 class FkError(RuntimeError):
@@ -96,6 +96,7 @@ def load(path: str = LIB_PATH):
         "fk_check_flags": (ctypes.c_int, [vp, vp, ip]),
         "fk_adjoint": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "fk_profile_pass": (ctypes.c_int, [vp, dp, ip, vp]),
+        "fk_profile_adjoint": (ctypes.c_int, [vp, vp, vp, dp, ip, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -312,6 +313,21 @@ class Plan:
         _check(load().fk_adjoint(self._h, ctypes.c_void_p(_ptr(lam0)), ctypes.c_void_p(_ptr(grad)),
                                  ctypes.c_void_p(_ptr(lamN)), ctypes.c_void_p(_stream(stream))))
         return grad[:, : self.n_theta], lamN
+
+    def profile_adjoint(self, lam0, stream=None):
+        """Mean per-step durations (ms) of the adjoint's kernel groups (slope
+        pass + clear, transposed step, transposed slopes + fold, recomputed
+        forward step) over one fk_adjoint call, timed with HIP events."""
+        import torch
+        lam0 = lam0.to(self.device, self.dtype).contiguous()
+        grad = torch.zeros((len(self.problems), MAX_THETA), dtype=torch.float64, device=self.device)
+        ms = (ctypes.c_double * 4)()
+        cnt = (ctypes.c_int * 4)()
+        _check(load().fk_profile_adjoint(self._h, ctypes.c_void_p(_ptr(lam0)),
+                                         ctypes.c_void_p(_ptr(grad)), ms, cnt,
+                                         ctypes.c_void_p(_stream(stream))))
+        names = ("slopes", "adjoint_step", "slopes_T", "recompute_step")
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(names)}
 
 
 def solve(problems, snaps: Sequence[int] = (0,), **plan_kw):

@@ -98,3 +98,32 @@ def test_autograd_function_mean_over_disc():
     lam0 = (oracle.node_class(prob) == 0) / float(mask.sum())
     g_ref, _ = oracle.adjoint(prob.replace(coef=(1.0, 0.1, 6.0), D=3e-3), lam0)
     assert _rel(theta.grad.numpy()[0], g_ref) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_adjoint_reuses_forward_checkpoints(prec):
+    """fk_forward on a plan built for the adjoint stores the checkpoints; an
+    adjoint on the same stream then skips its own forward pass.  Both routes,
+    and an adjoint on another stream, give the same gradients up to the order
+    of the atomic sums (the scatter and the gradient reduction add in
+    scheduling order)."""
+    tol = 1e-13 if prec == "f64" else 1e-5
+    prob = W.cell2d(nx=65, ny=33, n_steps=21, dt=2e-3, D=2e-3)
+    lam0 = torch.from_numpy(_lam0(prob).reshape(-1)).cuda()
+    plan = Plan(prob, precision=prec, ckpt_every=4, use_graph=True)
+    g_alone, l_alone = plan.adjoint(lam0)
+    torch.cuda.synchronize()
+    g_alone, l_alone = g_alone.cpu().numpy(), l_alone.cpu().numpy()
+    plan.forward([0])
+    g_reuse, l_reuse = plan.adjoint(lam0)
+    torch.cuda.synchronize()
+    assert _rel(g_reuse.cpu().numpy(), g_alone) <= tol
+    assert _rel(l_reuse.cpu().numpy(), l_alone) <= tol
+    side = torch.cuda.Stream()
+    plan.forward([0])
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        g_side, _ = plan.adjoint(lam0, stream=side)
+    torch.cuda.synchronize()
+    assert _rel(g_side.cpu().numpy(), g_alone) <= tol
+    plan.close()

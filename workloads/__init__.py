@@ -190,6 +190,29 @@ def paper2d(n1: int = 129, n2: int = 33, Pe: float = 10.0, eps: float = 0.15,
     return dict(n1=n1, n2=n2, Pe=Pe, eps=eps, omega=omega, n=2, T=0.05)
 
 
+def region_mean_weights(prob: "Problem") -> np.ndarray:
+    """Objective weights for J = mean of u^0 over the target region: 1/m on
+    the m nodes strictly inside the disc/ball (squared distance below r^2),
+    0 elsewhere; for a box region, on every node off the non-periodic faces.
+    Shape prob.shape.  This is an input (dJ/du^0), not part of the scheme."""
+    grids = np.meshgrid(*[ax.nodes for ax in prob.axes], indexing="ij")
+    if prob.region_kind == "ball":
+        d2 = np.zeros(prob.shape)
+        for a, g in enumerate(grids):
+            d2 = d2 + (g - prob.center[a]) ** 2
+        mask = d2 < prob.radius ** 2
+    else:
+        mask = np.ones(prob.shape, dtype=bool)
+        for a, ax in enumerate(prob.axes):
+            if not ax.periodic:
+                idx = [slice(None)] * prob.d
+                for end in (0, -1):
+                    idx[a] = end
+                    mask[tuple(idx)] = False
+    m = mask.astype(np.float64)
+    return m / max(m.sum(), 1.0)
+
+
 def random_field(shape: Sequence[int], seed: int, lo: float = 0.0,
                  hi: float = 1.0) -> np.ndarray:
     """Seeded uniform random field (test states for single-step checks)."""
