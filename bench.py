@@ -36,7 +36,8 @@ import workloads as W  # noqa: E402
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (published)
 PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64 (published)
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E (published)
-CKPT = 64
+CKPT_LIST = (1, 4, 16, 64)   # checkpoint intervals tried, smallest first
+CKPT_MEM_FRACTION = 0.5       # of free HBM the plan's workspace may take
 
 
 def step_kernel_flops(d: int, qs: int):
@@ -163,7 +164,19 @@ def main():
     log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)  # noqa: E731
     log(f"workload cell2d_batch64: {len(probs)} instances, N={N}, FP32 apply, forward + adjoint")
 
-    plan = Plan(probs, precision="f32", use_graph=True, ckpt_every=CKPT)
+    # the smallest checkpoint interval whose storage fits half of free HBM
+    # (every step stored: the adjoint recomputes nothing)
+    free, _ = torch.cuda.mem_get_info()
+    ckpt = CKPT_LIST[-1]
+    for k in CKPT_LIST:
+        probe = Plan(probs, precision="f32", use_graph=True, ckpt_every=k, allocate=False)
+        need = int(probe.info.workspace_bytes)
+        probe.close()
+        if need <= CKPT_MEM_FRACTION * free:
+            ckpt = k
+            break
+    log(f"checkpoint every {ckpt} step(s)")
+    plan = Plan(probs, precision="f32", use_graph=True, ckpt_every=ckpt)
     Ja = sum(plan.active_count)
     lam0 = disc_mean_weights(probs, plan.dtype, plan.device)
 
@@ -226,7 +239,9 @@ def main():
                                "(128m+1)x(64m+1) m~U{1..8}, disc exit r=0.3, 8x8 Gauss-Hermite, "
                                "dt=1e-3, 1000 steps, one plan; step = backward pass (captured HIP "
                                "graph) + adjoint of the disc-mean exit probability w.r.t. "
-                               "(A, eps, omega, D), checkpoint every 64 steps",
+                               "(A, eps, omega, D); u checkpointed every ckpt_every steps (the "
+                               "smallest of 1, 4, 16, 64 whose storage fits half of free HBM)",
+                   "ckpt_every": ckpt,
                    "instances": len(probs), "active_nodes": Ja, "time_steps": N,
                    "precision": "FP32 weights and accumulation, FP64 landing points and cells"},
         "forward_only": {"ms_per_pass": ms_fwd, "gp_steps_per_s": Ja * N / (ms_fwd * 1e-3)},
@@ -242,7 +257,7 @@ def main():
         off = 0
         errs, gerr = [], []
         for i, p in enumerate(probs):
-            pl = Plan(p, precision="f64", use_graph=False, ckpt_every=CKPT)
+            pl = Plan(p, precision="f64", use_graph=False, ckpt_every=64)
             lam_i = disc_mean_weights([p], pl.dtype, pl.device)
             torch.cuda.synchronize()
             t, (o, g) = event_time(lambda: (pl.forward([0]), pl.adjoint(lam_i)[0]), 1, stream)

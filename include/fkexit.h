@@ -116,11 +116,13 @@ typedef struct {
                         3 = Q* lanes per node over the outermost axis;
                         4 = separable box form for nodes whose landing points
                         cannot reach a ball boundary (footprint up to 8 nodes
-                        per axis), one thread per node for the others.  1, 3
-                        and 4 exist for d=1: gh_q 2..8,10,12,16; d=2: 2..8;
-                        d=3: 2..6 (FK_ERR_UNSUPPORTED otherwise).  auto picks 4
-                        for plans with many active nodes, 3 for small ones, 2
-                        when the others are not compiled for gh_q */
+                        per axis; d >= 2 on affine axes), one thread per node
+                        for the others.  1, 3 and 4 exist for d=1: gh_q
+                        2..8,10,12,16; d=2: 2..8; d=3: 2..6
+                        (FK_ERR_UNSUPPORTED otherwise).  auto picks 4 for 3D
+                        plans with many active nodes, 1 for other large plans,
+                        3 for small ones, 2 when the others are not compiled
+                        for gh_q; fk_tune measures them instead */
     int reserved[2];
 } fk_options;
 
@@ -138,6 +140,15 @@ typedef struct {
 } fk_plan_info;
 
 typedef struct fk_plan fk_plan;
+
+/* Result of fk_tune: the fastest step layout and the measured mean duration
+ * of one backward step (slope pass + step pass) per layout, in milliseconds
+ * (0 where the layout was not timed: not compiled for the plan, or the same
+ * lists as one already timed). */
+typedef struct {
+    int step_kernel;          /* value for fk_options.step_kernel */
+    double ms_per_step[5];    /* indexed by step_kernel 0..4 (0 unused) */
+} fk_tune_result;
 
 /* Message of the last error on this thread ("" if none). */
 const char *fk_last_error(void);
@@ -216,6 +227,18 @@ fk_status fk_check_flags(fk_plan *p, void *stream, int *flags);
  * any other stream, or a workspace change, makes fk_adjoint recompute them. */
 fk_status fk_adjoint(fk_plan *p, const void *lam0, double *grad, void *lamN,
                      void *stream);
+
+/* Autotuner for batched plans: builds a trial plan for each step layout
+ * (fk_options.step_kernel 1..4) of the problems with n_steps replaced by
+ * trial_steps (the cost of a step does not depend on n), runs its backward
+ * pass twice on stream with the caller's other options, and returns the
+ * layout with the shortest second run in out (host).  workspace (device,
+ * 256-byte aligned, caller-owned, contents destroyed) must hold the largest
+ * trial plan: the workspace_bytes of a plan over the full problems suffices.
+ * Synchronises stream.  Errors: FK_ERR_ARG (bad arguments), FK_ERR_WORKSPACE
+ * (workspace too small for a trial plan), plan-creation and HIP errors. */
+fk_status fk_tune(const fk_problem *probs, int n_inst, const fk_options *opt, int trial_steps,
+                  void *workspace, size_t workspace_bytes, void *stream, fk_tune_result *out);
 
 /* Measurement hook: runs one backward pass from chi without a graph on
  * stream, with HIP events around every kernel launch, and returns the mean

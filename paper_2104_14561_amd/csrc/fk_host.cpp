@@ -787,7 +787,7 @@ fk_status build_plan(fk_plan *p)
         add_region(p, "mu", fb * rec_stride(p->d));
         add_region(p, "grad", sizeof(double) * fk::kThetaSlots * p->n_inst);
         add_region(p, "ckpt", fb * p->n_ckpt);
-        add_region(p, "seg", fb * std::min(K, p->N));
+        add_region(p, "seg", fb * std::max(1, std::min(K, p->N) - 1));   // recomputed fields
     }
     return FK_OK;
 }
@@ -1249,18 +1249,21 @@ fk_status fk_adjoint(fk_plan *p, const void *lam0, double *grad, void *lamN, voi
     for (int sg = 0; sg < nseg; ++sg) {
         const int n0 = sg * K, n1 = std::min(n0 + K, p->N);
         const int top_slot = (n1 == p->N) ? p->n_ckpt - 1 : n1 / K;
-        // seg[j] = u^{n0 + 1 + j}, j = 0 .. n1 - n0 - 1
-        FK_HIP(hipMemcpyAsync(seg + (size_t)(n1 - n0 - 1) * fb, ck + (size_t)top_slot * fb, fb,
-                              hipMemcpyDeviceToDevice, s));
+        // u^{m} for m in (n0, n1]: the top from its checkpoint slot, the rest
+        // recomputed into seg[m - n0 - 1]
+        const unsigned char *top = ck + (size_t)top_slot * fb;
+        auto field = [&](int m) -> const void * {
+            return m == n1 ? (const void *)top : (const void *)(seg + (size_t)(m - n0 - 1) * fb);
+        };
         for (int m = n1 - 1; m >= n0 + 1; --m) {
             void *dst = seg + (size_t)(m - n0 - 1) * fb;
             FK_LAUNCH(fk::launch_init_field(p->dev, p->f32, dst, s));
             FK_TRY(prof_mark(p, -1, s));
-            FK_TRY(enqueue_step(p, m, seg + (size_t)(m - n0) * fb, dst, s));
+            FK_TRY(enqueue_step(p, m, field(m + 1), dst, s));
             FK_TRY(prof_mark(p, 3, s));
         }
         for (int n = n0; n < n1; ++n) {
-            const void *v = seg + (size_t)(n - n0) * fb;   // u^{n+1}
+            const void *v = field(n + 1);   // u^{n+1}
             FK_TRY(prof_mark(p, -1, s));
             FK_LAUNCH(fk::launch_slopes(p->dev, p->f32, n, v, packed, s));
             FK_LAUNCH(fk::launch_zero(mu, fb * rec_stride(p->d), s));
@@ -1330,6 +1333,70 @@ fk_status fk_profile_pass(fk_plan *p, double *ms, int *counts, void *stream)
         ms[k] = cnt[k] ? tot[k] / cnt[k] : 0.0;
         counts[k] = cnt[k];
     }
+    return FK_OK;
+}
+
+fk_status fk_tune(const fk_problem *probs, int n_inst, const fk_options *opt, int trial_steps,
+                  void *workspace, size_t workspace_bytes, void *stream, fk_tune_result *out)
+{
+    if (!probs || n_inst < 1 || !out) return fail(FK_ERR_ARG, "null problems or result");
+    if (trial_steps < 1) return fail(FK_ERR_ARG, "trial_steps must be >= 1");
+    if (!workspace) return fail(FK_ERR_ARG, "null workspace");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<fk_problem> trial(probs, probs + n_inst);
+    for (fk_problem &pr : trial) pr.n_steps = std::min(pr.n_steps, trial_steps);
+    fk_options base{};
+    if (opt) base = *opt;
+    base.ckpt_every = 0;
+    std::memset(out, 0, sizeof(*out));
+    double best = 1e300;
+    std::vector<std::pair<int, int>> seen;   // (step_kind, use_box) already timed
+    for (int sk = 1; sk <= 4; ++sk) {
+        fk_options o = base;
+        o.step_kernel = sk;
+        fk_plan *p = nullptr;
+        if (fk_plan_create(trial.data(), n_inst, &o, &p) != FK_OK) {
+            g_err.clear();   // layout not compiled for this plan: skip it
+            continue;
+        }
+        const std::pair<int, int> key{p->step_kind, p->use_box ? 1 : 0};
+        bool dup = false;
+        for (const auto &k : seen) dup = dup || k == key;
+        if (dup) {
+            fk_plan_destroy(p);
+            continue;
+        }
+        seen.push_back(key);
+        if (p->ws_bytes > workspace_bytes) {
+            const size_t need = p->ws_bytes;
+            fk_plan_destroy(p);
+            return fail(FK_ERR_WORKSPACE, "trial plan needs %zu workspace bytes, %zu given", need,
+                        workspace_bytes);
+        }
+        fk_status st = fk_plan_set_workspace(p, workspace, workspace_bytes, stream);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        float ms = 0.f;
+        if (st == FK_OK) st = fk_forward(p, nullptr, 0, nullptr, stream);   // warm-up / capture
+        if (st == FK_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+            st = fail(FK_ERR_HIP, "event create");
+        if (st == FK_OK && hipEventRecord(e0, s) != hipSuccess) st = fail(FK_ERR_HIP, "event record");
+        if (st == FK_OK) st = fk_forward(p, nullptr, 0, nullptr, stream);
+        if (st == FK_OK && hipEventRecord(e1, s) != hipSuccess) st = fail(FK_ERR_HIP, "event record");
+        if (st == FK_OK && hipEventSynchronize(e1) != hipSuccess) st = fail(FK_ERR_HIP, "event sync");
+        if (st == FK_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            st = fail(FK_ERR_HIP, "event timing");
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        const int steps = p->N;
+        fk_plan_destroy(p);
+        if (st != FK_OK) return st;
+        out->ms_per_step[sk] = ms / steps;
+        if (out->ms_per_step[sk] < best) {
+            best = out->ms_per_step[sk];
+            out->step_kernel = sk;
+        }
+    }
+    if (out->step_kernel == 0) return fail(FK_ERR_UNSUPPORTED, "no step layout could be built");
     return FK_OK;
 }
 

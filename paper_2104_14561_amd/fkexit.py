@@ -29,7 +29,7 @@ MAX_THETA = 8
 EXPORTED = ["fk_last_error", "fk_version", "fk_gh_rule", "fk_plan_create", "fk_plan_destroy",
             "fk_plan_get_info", "fk_plan_layout", "fk_plan_set_workspace", "fk_forward",
             "fk_forward_from", "fk_step", "fk_export_cells", "fk_export_ell",
-            "fk_check_flags", "fk_adjoint", "fk_profile_pass", "fk_profile_adjoint"]
+            "fk_check_flags", "fk_adjoint", "fk_profile_pass", "fk_profile_adjoint", "fk_tune"]
 
 
 class FkError(RuntimeError):
@@ -62,6 +62,10 @@ class _Info(ctypes.Structure):
                 ("n_quad", ctypes.c_int), ("n_steps", ctypes.c_int), ("n_theta", ctypes.c_int),
                 ("n_nodes", ctypes.c_int64), ("n_active", ctypes.c_int64),
                 ("ell_width", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t)]
+
+
+class _TuneResult(ctypes.Structure):
+    _fields_ = [("step_kernel", ctypes.c_int), ("ms_per_step", ctypes.c_double * 5)]
 
 
 _lib = None
@@ -97,6 +101,9 @@ def load(path: str = LIB_PATH):
         "fk_adjoint": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "fk_profile_pass": (ctypes.c_int, [vp, dp, ip, vp]),
         "fk_profile_adjoint": (ctypes.c_int, [vp, vp, vp, dp, ip, vp]),
+        "fk_tune": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_int, ctypes.POINTER(_Options),
+                                   ctypes.c_int, vp, ctypes.c_size_t, vp,
+                                   ctypes.POINTER(_TuneResult)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -165,16 +172,25 @@ class Plan:
     precision: "f64" or "f32" (FP64 landing points and cells, FP32 weights,
     gathers, accumulation and fields); form: "fused" or "ell"; use_graph:
     capture the N-step loop once and replay it; ckpt_every: adjoint checkpoint
-    interval (0 = no adjoint).
+    interval (0 = no adjoint).  step_kernel: "auto", "node", "group", "split",
+    "box", or "tune" (fk_tune times the layouts on this device first and the
+    plan takes the fastest; the choice and timings are in .tuned).
+    allocate=False builds the plan on the host only (for its info: workspace
+    size, node counts); calls need a workspace.
     """
 
     def __init__(self, problems, precision: str = "f64", form: str = "fused",
                  use_graph: bool = False, ckpt_every: int = 0, device: str = "cuda",
-                 step_kernel: str = "auto"):
+                 step_kernel: str = "auto", allocate: bool = True):
         import torch
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
         self.problems = list(problems)
+        self.tuned = None
+        if step_kernel == "tune":
+            self.tuned = tune(self.problems, precision=precision, form=form,
+                              use_graph=use_graph, device=device)
+            step_kernel = self.tuned["step_kernel"]
         lib = load()
         arr, keep = _marshal(self.problems)
         opt = _Options()
@@ -199,6 +215,9 @@ class Plan:
         self.node_offset = [int(v) for v in off]
         self.active_count = [int(v) for v in cnt]
         self.device = torch.device(device)
+        self.workspace = None
+        if not allocate:
+            return
         nbytes = max(int(info.workspace_bytes), 256)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = _ptr(self.workspace)
@@ -328,6 +347,35 @@ class Plan:
                                          ctypes.c_void_p(_stream(stream))))
         names = ("slopes", "adjoint_step", "slopes_T", "recompute_step")
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(names)}
+
+
+def tune(problems, precision: str = "f64", form: str = "fused", use_graph: bool = False,
+         trial_steps: int = 16, device: str = "cuda", stream=None):
+    """fk_tune: time every step layout on a trial_steps-step copy of the
+    problems and return {"step_kernel": name, "ms_per_step": {name: ms}}."""
+    import torch
+    if not isinstance(problems, (list, tuple)):
+        problems = [problems]
+    probe = Plan(problems, precision=precision, form=form, use_graph=use_graph, device=device,
+                 allocate=False)
+    nbytes = int(probe.info.workspace_bytes) * 5 // 4 + (1 << 20)
+    probe.close()
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=torch.device(device))
+    aligned = (_ptr(ws) + 255) // 256 * 256
+    arr, keep = _marshal(list(problems))
+    opt = _Options()
+    opt.precision = PREC[precision]
+    opt.form = FORM[form]
+    opt.use_graph = int(bool(use_graph))
+    res = _TuneResult()
+    _check(load().fk_tune(arr, len(problems), ctypes.byref(opt), int(trial_steps),
+                          ctypes.c_void_p(aligned), nbytes, ctypes.c_void_p(_stream(stream)),
+                          ctypes.byref(res)))
+    del keep, ws
+    names = {v: k for k, v in STEP_KERNEL.items()}
+    return {"step_kernel": names[res.step_kernel],
+            "ms_per_step": {names[k]: float(res.ms_per_step[k]) for k in range(1, 5)
+                            if res.ms_per_step[k] > 0}}
 
 
 def solve(problems, snaps: Sequence[int] = (0,), **plan_kw):

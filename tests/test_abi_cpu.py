@@ -170,3 +170,21 @@ def test_workspace_too_small_rejected(lib):
     assert lib.fk_plan_set_workspace(h, ctypes.c_void_p((1 << 20) + 8), info.workspace_bytes,
                                      None) == -1
     lib.fk_plan_destroy(h)
+
+
+def test_tune_rejects_bad_arguments(lib):
+    """fk_tune validates its arguments on the host before touching a device."""
+    arr, keep = fkexit._marshal([W.bm1d()])
+    res = fkexit._TuneResult()
+    opt = fkexit._Options()
+    # no problems
+    assert lib.fk_tune(None, 0, ctypes.byref(opt), 4, None, 0, None, ctypes.byref(res)) == -1
+    # no result
+    assert lib.fk_tune(arr, 1, ctypes.byref(opt), 4, ctypes.c_void_p(256), 1 << 20, None, None) == -1
+    # trial_steps < 1
+    assert lib.fk_tune(arr, 1, ctypes.byref(opt), 0, ctypes.c_void_p(256), 1 << 20, None,
+                       ctypes.byref(res)) == -1
+    # no workspace
+    assert lib.fk_tune(arr, 1, ctypes.byref(opt), 4, None, 0, None, ctypes.byref(res)) == -1
+    assert "workspace" in lib.fk_last_error().decode()
+    del keep

@@ -266,3 +266,22 @@ def _cell2d_ref():
     if "cell2d" not in _REF:
         _REF["cell2d"] = oracle.solve(W.cell2d(), snaps=[1000, 500, 0])
     return _REF["cell2d"]
+
+
+def test_autotuned_plan_matches_oracle():
+    """fk_tune times the step layouts on this device; the plan built with its
+    choice stays within the parity bar."""
+    from paper_2104_14561_amd import tune
+    probs = W.cell2d_batch(n_inst=3, n_steps=12, max_m=2)
+    res = tune(probs, precision="f64", use_graph=True, trial_steps=4)
+    print(res)
+    assert res["step_kernel"] in ("node", "group", "split", "box")
+    assert all(v > 0 for v in res["ms_per_step"].values())
+    assert res["ms_per_step"][res["step_kernel"]] == min(res["ms_per_step"].values())
+    plan = Plan(probs, precision="f64", use_graph=True, step_kernel="tune")
+    assert plan.tuned is not None
+    out = plan.forward([0])
+    torch.cuda.synchronize()
+    for p, g in zip(probs, plan.split(out)):
+        assert _maxerr(g.cpu().numpy(), oracle.solve(p, snaps=[0])) <= 1e-12
+    plan.close()
