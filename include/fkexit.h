@@ -251,7 +251,7 @@ fk_status fk_profile_pass(fk_plan *p, double *ms, int *counts, void *stream);
 /* Measurement hook for the adjoint: runs fk_adjoint(p, lam0, grad, NULL,
  * stream) with HIP events around every kernel group of the reverse sweep and
  * returns the mean duration in milliseconds per step of each group in ms[4]
- * (host): [0] slope pass of u^{n+1} and the clearing of mu, [1] transposed
+ * (host): [0] slope pass of u^{n+1}, [1] transposed
  * step (the scatter of A_n^T lam^n and the theta-gradient), [2] transposed
  * slope pass with the image fold, [3] forward step recomputed inside a
  * checkpoint segment; counts[4] (host) receives the number of steps timed.

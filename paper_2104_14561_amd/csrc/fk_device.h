@@ -1959,14 +1959,16 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_box(
 // lam_next must hold mu_u on entry.
 template <typename T, int D>
 __global__ void __launch_bounds__(kBlock) k_adjoint_slopes_T(PlanDev P, const T *__restrict__ u,
-                                                             const T *__restrict__ mu,
-                                                             T *__restrict__ lam_next)
+                                                             T *__restrict__ mu,
+                                                             T *__restrict__ lam_next,
+                                                             const WorkItem *__restrict__ items,
+                                                             int first, int n_items)
 {
     constexpr int PS = RecStride<D>::value;
-    const WorkRange wr = work_range(0, P.n_node_work);
+    const WorkRange wr = work_range(first, n_items);
     for (int w = wr.begin; w < wr.end; w += wr.step) {
-        const WorkItem it = P.node_work[w];
-        if ((int)threadIdx.x >= it.count) continue;
+        const WorkItem it = items[w];
+        if ((int)threadIdx.x >= it.count || it.kind != 0) continue;
         const DevInst &I = P.inst[it.inst];
         const int node = it.first + threadIdx.x;
         int idx[3];
@@ -1974,8 +1976,10 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_slopes_T(PlanDev P, const T 
         const T *ui = u + I.node_off;
         T *li = lam_next + I.node_off;
         for (int a = 0; a < D; ++a) {
-            const T m = mu[(I.node_off + node) * PS + 1 + a];
+            T *mp = &mu[(I.node_off + node) * PS + 1 + a];
+            const T m = *mp;
             if (m == T(0)) continue;
+            *mp = T(0);   // mu is clear again for the next step
             const int na = I.n[a];
             const double *x = P.coords + I.coord_off[a];
             const int i = idx[a];
@@ -2014,27 +2018,37 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_slopes_T(PlanDev P, const T 
     }
 }
 
-// lam <- mu_u (field 0 of the records).
+// lam <- mu_u (field 0 of the records) over the nodes of a work list (node
+// runs), clearing mu_u for the next step.
 template <typename T, int D>
-__global__ void __launch_bounds__(kBlock) k_mu_value(PlanDev P, const T *__restrict__ mu,
-                                                     T *__restrict__ lam)
+__global__ void __launch_bounds__(kBlock) k_mu_value(PlanDev P, T *__restrict__ mu,
+                                                     T *__restrict__ lam,
+                                                     const WorkItem *__restrict__ items,
+                                                     int first, int n_items)
 {
     constexpr int PS = RecStride<D>::value;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < P.n_nodes;
-         i += (long long)gridDim.x * blockDim.x)
-        lam[i] = mu[i * PS];
+    const WorkRange wr = work_range(first, n_items);
+    for (int w = wr.begin; w < wr.end; w += wr.step) {
+        const WorkItem it = items[w];
+        if ((int)threadIdx.x >= it.count || it.kind != 0) continue;
+        const long long g = P.inst[it.inst].node_off + it.first + threadIdx.x;
+        lam[g] = mu[g * PS];
+        mu[g * PS] = T(0);
+    }
 }
 
 // Exit nodes carry no sensitivity; a periodic image passes its cotangent to
 // the node it copies.  cls: 0 active, 1 exit, 2 image of an active node,
 // 3 image of an exit node.
 template <typename T, int D>
-__global__ void __launch_bounds__(kBlock) k_fold_images(PlanDev P, T *__restrict__ lam)
+__global__ void __launch_bounds__(kBlock) k_fold_images(PlanDev P, T *__restrict__ lam,
+                                                        const WorkItem *__restrict__ items,
+                                                        int first, int n_items)
 {
-    const WorkRange wr = work_range(0, P.n_node_work);
+    const WorkRange wr = work_range(first, n_items);
     for (int w = wr.begin; w < wr.end; w += wr.step) {
-        const WorkItem it = P.node_work[w];
-        if ((int)threadIdx.x >= it.count) continue;
+        const WorkItem it = items[w];
+        if ((int)threadIdx.x >= it.count || it.kind != 0) continue;
         const DevInst &I = P.inst[it.inst];
         const int node = it.first + threadIdx.x;
         const long long g = I.node_off + node;

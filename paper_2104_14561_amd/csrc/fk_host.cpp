@@ -1245,6 +1245,10 @@ fk_status fk_adjoint(fk_plan *p, const void *lam0, double *grad, void *lamN, voi
     void *packed = p->at("packed");
     FK_LAUNCH(fk::launch_zero(g, sizeof(double) * fk::kThetaSlots * p->n_inst, s));
     FK_LAUNCH(fk::launch_adjoint_init(p->dev, p->f32, lam0, la, s));
+    // the per-step passes touch only the nodes a step can reach and leave mu
+    // clear behind them: clear mu and the second lam buffer once
+    FK_LAUNCH(fk::launch_zero(mu, fb * rec_stride(p->d), s));
+    FK_LAUNCH(fk::launch_zero(lb, fb, s));
     const int nseg = (p->N - 1) / K + 1;
     for (int sg = 0; sg < nseg; ++sg) {
         const int n0 = sg * K, n1 = std::min(n0 + K, p->N);
@@ -1266,7 +1270,6 @@ fk_status fk_adjoint(fk_plan *p, const void *lam0, double *grad, void *lamN, voi
             const void *v = field(n + 1);   // u^{n+1}
             FK_TRY(prof_mark(p, -1, s));
             FK_LAUNCH(fk::launch_slopes(p->dev, p->f32, n, v, packed, s));
-            FK_LAUNCH(fk::launch_zero(mu, fb * rec_stride(p->d), s));
             FK_TRY(prof_mark(p, 0, s));
             FK_LAUNCH(fk::launch_adjoint_step(p->dev, p->f32, n, packed, la, mu, g, s));
             FK_TRY(prof_mark(p, 1, s));

@@ -165,8 +165,8 @@ hipError_t launch_clear_flags(const PlanDev &P, hipStream_t s);
 // Adjoint launchers.
 hipError_t launch_adjoint_step(const PlanDev &P, bool f32, int n, const void *packed,
                                const void *lam, void *mu, double *grad, hipStream_t s);
-hipError_t launch_adjoint_slopes_T(const PlanDev &P, bool f32, const void *u,
-                                   const void *mu, void *lam_next, hipStream_t s);
+hipError_t launch_adjoint_slopes_T(const PlanDev &P, bool f32, const void *u, void *mu,
+                                   void *lam_next, hipStream_t s);
 hipError_t launch_adjoint_init(const PlanDev &P, bool f32, const void *lam0, void *lam,
                                hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);

@@ -169,18 +169,24 @@ hipError_t launch_adjoint_step(const PlanDev &P, bool f32, int n, const void *pa
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_slopes_T(const PlanDev &P, bool f32, const void *u, const void *mu,
+hipError_t launch_adjoint_slopes_T(const PlanDev &P, bool f32, const void *u, void *mu,
                                    void *lam_next, hipStream_t s)
 {
+    // every node an adjoint step can touch lies in the slope pass' node runs
+    // (the active region widened by the reach and the slope stencil)
+    const WorkItem *runs = P.slope_work;
+    const int r0 = P.n_table_work, nr = P.n_slope_work - P.n_table_work;
+    if (nr <= 0) return hipSuccess;
+    const int g = P.slope_grid;
     FK_DISPATCH_D(P.d,
         if (f32) {
-            k_mu_value<float, D><<<flat_grid(P.n_nodes), kBlock, 0, s>>>(P, (const float *)mu, (float *)lam_next);
-            k_adjoint_slopes_T<float, D><<<P.node_grid, kBlock, 0, s>>>(P, (const float *)u, (const float *)mu, (float *)lam_next);
-            k_fold_images<float, D><<<P.node_grid, kBlock, 0, s>>>(P, (float *)lam_next);
+            k_mu_value<float, D><<<g, kBlock, 0, s>>>(P, (float *)mu, (float *)lam_next, runs, r0, nr);
+            k_adjoint_slopes_T<float, D><<<g, kBlock, 0, s>>>(P, (const float *)u, (float *)mu, (float *)lam_next, runs, r0, nr);
+            k_fold_images<float, D><<<g, kBlock, 0, s>>>(P, (float *)lam_next, runs, r0, nr);
         } else {
-            k_mu_value<double, D><<<flat_grid(P.n_nodes), kBlock, 0, s>>>(P, (const double *)mu, (double *)lam_next);
-            k_adjoint_slopes_T<double, D><<<P.node_grid, kBlock, 0, s>>>(P, (const double *)u, (const double *)mu, (double *)lam_next);
-            k_fold_images<double, D><<<P.node_grid, kBlock, 0, s>>>(P, (double *)lam_next);
+            k_mu_value<double, D><<<g, kBlock, 0, s>>>(P, (double *)mu, (double *)lam_next, runs, r0, nr);
+            k_adjoint_slopes_T<double, D><<<g, kBlock, 0, s>>>(P, (const double *)u, (double *)mu, (double *)lam_next, runs, r0, nr);
+            k_fold_images<double, D><<<g, kBlock, 0, s>>>(P, (double *)lam_next, runs, r0, nr);
         });
     return hipGetLastError();
 }
@@ -192,8 +198,8 @@ hipError_t launch_adjoint_init(const PlanDev &P, bool f32, const void *lam0, voi
                                   hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
     FK_DISPATCH_D(P.d,
-        if (f32) k_fold_images<float, D><<<P.node_grid, kBlock, 0, s>>>(P, (float *)lam);
-        else k_fold_images<double, D><<<P.node_grid, kBlock, 0, s>>>(P, (double *)lam));
+        if (f32) k_fold_images<float, D><<<P.node_grid, kBlock, 0, s>>>(P, (float *)lam, P.node_work, 0, P.n_node_work);
+        else k_fold_images<double, D><<<P.node_grid, kBlock, 0, s>>>(P, (double *)lam, P.node_work, 0, P.n_node_work));
     return hipGetLastError();
 }
 
