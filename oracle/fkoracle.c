@@ -621,6 +621,17 @@ int fko_assemble_row(const fko_problem *P, int n, long j, double *row, double *e
 /* Adjoint of the whole pass (exit classification held fixed)               */
 /* ------------------------------------------------------------------------ */
 
+/* The slope map of Eq. (e300) is not differentiable where a divided
+ * difference vanishes; its linearisation takes derivative 0 there.  A
+ * difference below 2^-30 of the magnitude of the two values it is taken from
+ * is rounding noise of a flat stretch (equal values computed along different
+ * rounding paths) and counts as vanishing, so that the adjoint does not
+ * depend on the last bits of u. */
+static int flat_pair(double a, double b)
+{
+    return fabs(a - b) <= 0x1p-30 * (fabs(a) + fabs(b));
+}
+
 /* Transpose of the PCHIP slope map along every axis, linearised at u:
  * lam[c] += sum_a sum_j mu[a][j] d g_a[j] / d u[c]. */
 static void slopes_transpose(const fko_problem *P, const double *u, const double *mu,
@@ -640,6 +651,7 @@ static void slopes_transpose(const fko_problem *P, const double *u, const double
             t[ax] = il; long nl = node_linear(P, t);
             t[ax] = ic; long nc = node_linear(P, t);
             t[ax] = ir; long nr = node_linear(P, t);
+            if (flat_pair(u[nc], u[nl]) || flat_pair(u[nr], u[nc])) continue;
             double dl = (u[nc] - u[nl]) / hl;
             double dr = (u[nr] - u[nc]) / hr;
             if (!(dl * dr > 0.0)) continue;

@@ -981,11 +981,17 @@ __device__ inline bool axis_vectors(const DevInst &I, const double *coords, cons
     return ok;
 }
 
+// Node index of footprint position i on an axis: wrapped across the seam of a
+// periodic axis, clamped to the axis otherwise.  Footprint positions past the
+// last node carry zero weight (no landing cell reaches them); clamping keeps
+// their record reads inside the field.
 __device__ inline int wrap_index(int i, int n, int per)
 {
     if (per) {
         if (i < 0) i += n - 1;
         else if (i > n - 1) i -= n - 1;
+    } else {
+        i = i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
     }
     return i;
 }
@@ -1819,6 +1825,153 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
     }
 }
 
+// Box-form adjoint step in 2D for separable nodes (affine axes).  The
+// transposed row of A_n over the footprint box [o0, o0+L) x [o1, o1+L) is
+// the outer product of the per-axis weight vectors: entry (i, j) gets
+// lam_j (V0[i] V1[j], S0[i] V1[j], V0[i] S1[j]) for (value, slope-0, slope-1),
+// i.e. 3 L^2 scatter adds per node against 12 per landing point in the
+// per-point form.  The theta-gradient is the same box contraction of the
+// records with the derivative vectors (dV, dS: z-derivative bases; aV, aS:
+// the same times the GH node) on one axis at a time.  The axis-1 vectors live
+// in registers; the axis-0 entries of row i are rebuilt inside the (rolled)
+// row loop from the hoisted axis-0 landing data, which keeps the registers
+// within a few waves per SIMD for L up to 12.
+template <typename T, int QS, int L>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : (L <= 8 ? 3 : 2)))) k_adjoint_box2(
+    const PlanDev P, int n, int n_work, const DevInst *__restrict__ insts,
+    const WorkItem *__restrict__ work, const TileBox *__restrict__ tiles,
+    const int *__restrict__ nodes, const double2 *__restrict__ trig,
+    const double *__restrict__ coords, const T *__restrict__ packed,
+    const T *__restrict__ lam, T *__restrict__ mu, double *__restrict__ grad)
+{
+    constexpr int D = 2;
+    constexpr int PS = RecStride<D>::value;
+    using R = typename RecT<T, PS>::type;
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ double red[kBlock / 64][kThetaSlots];
+    const R *rec = reinterpret_cast<const R *>(packed);
+    const double *ga = P.gh_a;
+    const T *w1 = weights1<T>(P);
+    const WorkRange wr = work_range(0, n_work);
+    for (int w = wr.begin; w < wr.end; w += wr.step) {
+        const WorkItem it = work[w];
+        const DevInst &I = insts[it.inst];
+        double *const tmem = reinterpret_cast<double *>(smem_raw);
+        MuTile<T, D> tile;
+        tile.init(tmem, tiles[w]);
+        tile.clear();
+        __syncthreads();
+        double gth[kThetaSlots];
+        for (int kk = 0; kk < kThetaSlots; ++kk) gth[kk] = 0.0;
+        const bool valid = (int)threadIdx.x < it.count;
+        const int node = valid ? nodes[it.first + threadIdx.x] : 0;
+        const T Lm = valid ? lam[I.node_off + node] : T(0);
+        if (valid && Lm != T(0)) {
+            int idx[3];
+            split_node<D>(I, node, idx);
+            const double *tf = time_factors(P, n, it.inst);
+            double c[3];
+            node_centre<D>(I, coords, tf, trig, idx, P.dt, c);
+            // axis 1: weight vectors over the footprint
+            T V1[L], S1[L], dV1[L], dS1[L], aV1[L], aS1[L];
+            int o1;
+            T m1;
+            bool ok = axis_vectors<T, QS, L, true, true>(I, coords, ga, w1, 1, c[1], o1, m1, V1, S1,
+                                                         dV1, dS1, aV1, aS1);
+            // axis 0: landing data per GH node
+            int l0[QS];
+            T s0[QS];
+            bool in0[QS];
+            int o0 = 0;
+            T h0 = T(1);
+#pragma unroll
+            for (int q = 0; q < QS; ++q) {
+                int ku;
+                const AxisEval e = eval_axis_unwrapped<true>(I, coords, 0, c[0], ga[q], ku);
+                if (q == 0) {
+                    o0 = ku;
+                    h0 = (T)e.h;
+                }
+                l0[q] = ku - o0;
+                s0[q] = (T)e.s;
+                in0[q] = !e.ex;
+                ok = ok && l0[q] >= 0 && l0[q] <= L - 2;
+            }
+            if (!ok) atomicOr(P.flags, 2);
+            const int b0 = o0 - tile.lo[0], b1 = o1 - tile.lo[1];
+            const bool lds = tile.use && b0 >= 0 && b0 + L <= tile.ext[0] && b1 >= 0 &&
+                             b1 + L <= tile.ext[1];
+            T Gz0 = T(0), Gz1 = T(0), Hz0 = T(0), Hz1 = T(0);
+            for (int i = 0; i < L; ++i) {
+                // axis-0 entries of row o0 + i
+                T v0 = T(0), sv0 = T(0), dv0 = T(0), ds0 = T(0), av0 = T(0), as0 = T(0);
+                bool hit = false;
+#pragma unroll
+                for (int q = 0; q < QS; ++q) {
+                    const bool lo = l0[q] == i, hi = l0[q] + 1 == i;
+                    if (!in0[q] || !(lo || hi)) continue;
+                    hit = true;
+                    const Basis<T> B = hermite<T>(s0[q], h0), Bz = hermite_dz<T>(s0[q], h0);
+                    const T wq = w1[q], wa = wq * (T)ga[q];
+                    v0 += wq * (lo ? B.v0 : B.v1);
+                    sv0 += wq * (lo ? B.d0 : B.d1);
+                    dv0 += wq * (lo ? Bz.v0 : Bz.v1);
+                    ds0 += wq * (lo ? Bz.d0 : Bz.d1);
+                    av0 += wa * (lo ? Bz.v0 : Bz.v1);
+                    as0 += wa * (lo ? Bz.d0 : Bz.d1);
+                }
+                if (!hit) continue;
+                const int ci = wrap_index(o0 + i, I.n[0], I.periodic[0]);
+                const long long row = I.node_off + (long long)ci * I.stride[0];
+                const T lv0 = Lm * v0, lsv0 = Lm * sv0;
+                T tA = T(0), tB = T(0), tC = T(0), tD = T(0), tE = T(0), tF = T(0);
+                if (lds) {
+                    double *t = tmem + (b0 + i) * tile.pitch + b1;
+#pragma unroll
+                    for (int j = 0; j < L; ++j) {
+                        const R r = rec[row + o1 + j];
+                        tA += V1[j] * r.x + S1[j] * r.z;
+                        tB += V1[j] * r.y;
+                        tC += dV1[j] * r.x + dS1[j] * r.z;
+                        tD += dV1[j] * r.y;
+                        tE += aV1[j] * r.x + aS1[j] * r.z;
+                        tF += aV1[j] * r.y;
+                        lds_add(t + j, lv0 * V1[j]);
+                        lds_add(t + tile.plane + j, lsv0 * V1[j]);
+                        lds_add(t + 2 * tile.plane + j, lv0 * S1[j]);
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < L; ++j) {
+                        const int cj = wrap_index(o1 + j, I.n[1], I.periodic[1]);
+                        const R r = rec[row + cj];
+                        tA += V1[j] * r.x + S1[j] * r.z;
+                        tB += V1[j] * r.y;
+                        tC += dV1[j] * r.x + dS1[j] * r.z;
+                        tD += dV1[j] * r.y;
+                        tE += aV1[j] * r.x + aS1[j] * r.z;
+                        tF += aV1[j] * r.y;
+                        T *m = mu + (row + cj) * PS;
+                        atomicAdd(m, lv0 * V1[j]);
+                        atomicAdd(m + 1, lsv0 * V1[j]);
+                        atomicAdd(m + 2, lv0 * S1[j]);
+                    }
+                }
+                Gz0 += dv0 * tA + ds0 * tB;
+                Hz0 += av0 * tA + as0 * tB;
+                Gz1 += v0 * tC + sv0 * tD;
+                Hz1 += v0 * tE + sv0 * tF;
+            }
+            const T Gz[3] = {Gz0, Gz1, T(0)}, Hz[3] = {Hz0, Hz1, T(0)};
+            node_theta<D, T>(P, I, tf, trig, idx, Lm, Gz, Hz, gth);
+        }
+        __syncthreads();
+        tile.template flush<PS>(I, mu);
+        reduce_theta(red, gth, grad, it.inst);
+        __syncthreads();
+    }
+}
+
 // Box-form adjoint step for separable nodes: the transposed row of A_n is the
 // outer product of the per-axis weight vectors, and the theta-gradient needs
 // the same box contraction with the derivative vectors (dV, dS) and the
@@ -2005,8 +2158,16 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_slopes_T(PlanDev P, const T 
             const long long nl = base + (long long)il * I.stride[a];
             const long long nc = base + (long long)ic * I.stride[a];
             const long long nr = base + (long long)ir * I.stride[a];
-            const T dl = (ui[nc] - ui[nl]) / (T)hl;
-            const T dr = (ui[nr] - ui[nc]) / (T)hr;
+            // derivative 0 where a divided difference vanishes, including
+            // differences that are rounding noise of a flat stretch (below
+            // 2^-30 of the values; in FP32 that is exact equality)
+            const T tau = T(0x1p-30);
+            const T vl = ui[nl], vc = ui[nc], vr = ui[nr];
+            if (fabs(vc - vl) <= tau * (fabs(vc) + fabs(vl)) ||
+                fabs(vr - vc) <= tau * (fabs(vr) + fabs(vc)))
+                continue;
+            const T dl = (vc - vl) / (T)hl;
+            const T dr = (vr - vc) / (T)hr;
             if (!(dl * dr > T(0))) continue;
             const T den = (dl + dr) * (dl + dr);
             const T gdl = T(2) * dr * dr / den;

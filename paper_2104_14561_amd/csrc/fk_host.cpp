@@ -158,8 +158,14 @@ struct fk_plan {
     std::vector<float> gh_wf, gh_w1f;
     std::vector<double> tfac;
     std::vector<fk::WorkItem> slope_work, node_work, act_work, row_work, split_work;
-    std::vector<fk::TileBox> fw_tiles, box_tiles;
     int tile_elems = 0;
+    // adjoint step lists (per-node form and box form by class) with LDS tiles
+    struct {
+        std::vector<int> fw_nodes, box_nodes;
+        std::vector<fk::WorkItem> fw_work, box_work;
+        std::vector<fk::TileBox> fw_tiles, box_tiles;
+        int box_work_off[fk::kBoxClasses] = {0}, n_box_work[fk::kBoxClasses] = {0};
+    } adj;
     // forward step lists
     std::vector<int> fw_nodes, box_nodes;
     std::vector<fk::WorkItem> fw_work, fw_split_work, box_work;
@@ -370,7 +376,7 @@ fk_status build_plan(fk_plan *p)
     std::vector<fk::WorkItem> tables, runs;
     long long ell_total = 0, ell_wmax = 0;
     std::vector<std::vector<int>> inst_sep, inst_rest;
-    std::vector<int> inst_cls;
+    std::vector<int> inst_cls, inst_lneed;
     std::vector<std::array<int, 3>> inst_dils;
     p->node_off.assign(p->n_inst + 1, 0);
     p->act_count.assign(p->n_inst, 0);
@@ -520,7 +526,7 @@ fk_status build_plan(fk_plan *p)
             std::vector<int> sep, rest;
             for (int t = 0; t < na; ++t) {
                 const int j = p->active[I.act_off + t];
-                bool separable = cls_box >= 0;
+                bool separable = true;
                 if (separable && pr.region_kind == FK_REGION_BALL) {
                     long long r = j;
                     double dist2 = 0.0;
@@ -537,6 +543,7 @@ fk_status build_plan(fk_plan *p)
             inst_sep.push_back(sep);
             inst_rest.push_back(rest);
             inst_cls.push_back(cls_box);
+            inst_lneed.push_back(Lneed);
         }
         build_work(p->row_work, i, na, kBlock);
         inst_dils.push_back({dils[0], dils[1], dils[2]});
@@ -702,8 +709,48 @@ fk_status build_plan(fk_plan *p)
             if (ok) p->tile_elems = std::max<int>(p->tile_elems, (int)elems);
             return tb;
         };
-        for (const fk::WorkItem &it : p->fw_work) p->fw_tiles.push_back(tile_of(it, p->fw_nodes));
-        for (const fk::WorkItem &it : p->box_work) p->box_tiles.push_back(tile_of(it, p->box_nodes));
+        // adjoint lists: separable nodes in box form when their footprint fits
+        // a class (the transposed row then scatters 3 L^2 (2D) entries instead
+        // of 12 per landing point), the others per landing point
+        if (p->opt.ckpt_every > 0) {
+            // 2D: footprints up to 6 nodes; wider ones scatter faster per point
+            // (measured: the box form's vector building and L^2 gathers cost
+            // more than the FP64 LDS atomics they save from L = 8 on)
+            static const int kLA[2][fk::kBoxClasses] = {{4, 6, 0, 0, 0}, {3, 4, 5, 6, 8}};
+            const bool abox = node_ok && affine && p->d >= 2 && fk::box_compiled(p->d, p->qs) &&
+                              sk != 1 && sk != 2;
+            std::vector<std::vector<fk::WorkItem>> abw(fk::kBoxClasses);
+            for (int i = 0; i < p->n_inst; ++i) {
+                const fk_problem &pr = p->probs[i];
+                int ac = -1;
+                if (abox)
+                    for (int c2 = 0; c2 < fk::kBoxClasses && ac < 0; ++c2)
+                        if (inst_lneed[i] <= kLA[p->d - 2][c2]) ac = c2;
+                std::vector<int> fw = inst_rest[i];
+                if (ac < 0) {
+                    fw.insert(fw.end(), inst_sep[i].begin(), inst_sep[i].end());
+                } else {
+                    std::vector<int> sep = inst_sep[i];
+                    patch_sort(sep, pr, keys);
+                    const int f0 = (int)p->adj.box_nodes.size();
+                    p->adj.box_nodes.insert(p->adj.box_nodes.end(), sep.begin(), sep.end());
+                    patch_work(abw[ac], i, keys, f0, kBlock);
+                }
+                patch_sort(fw, pr, keys);
+                const int f1 = (int)p->adj.fw_nodes.size();
+                p->adj.fw_nodes.insert(p->adj.fw_nodes.end(), fw.begin(), fw.end());
+                patch_work(p->adj.fw_work, i, keys, f1, kBlock);
+            }
+            for (int c2 = 0; c2 < fk::kBoxClasses; ++c2) {
+                p->adj.box_work_off[c2] = (int)p->adj.box_work.size();
+                p->adj.n_box_work[c2] = (int)abw[c2].size();
+                p->adj.box_work.insert(p->adj.box_work.end(), abw[c2].begin(), abw[c2].end());
+            }
+            for (const fk::WorkItem &it : p->adj.fw_work)
+                p->adj.fw_tiles.push_back(tile_of(it, p->adj.fw_nodes));
+            for (const fk::WorkItem &it : p->adj.box_work)
+                p->adj.box_tiles.push_back(tile_of(it, p->adj.box_nodes));
+        }
     }
     p->slope_work = tables;
     p->slope_work.insert(p->slope_work.end(), runs.begin(), runs.end());
@@ -762,8 +809,12 @@ fk_status build_plan(fk_plan *p)
     add_region(p, "act_work", sizeof(fk::WorkItem) * std::max<size_t>(p->act_work.size(), 1));
     add_region(p, "row_work", sizeof(fk::WorkItem) * std::max<size_t>(p->row_work.size(), 1));
     add_region(p, "split_work", sizeof(fk::WorkItem) * std::max<size_t>(p->split_work.size(), 1));
-    add_region(p, "fw_tiles", sizeof(fk::TileBox) * std::max<size_t>(p->fw_tiles.size(), 1));
-    add_region(p, "box_tiles", sizeof(fk::TileBox) * std::max<size_t>(p->box_tiles.size(), 1));
+    add_region(p, "afw_nodes", sizeof(int) * std::max<size_t>(p->adj.fw_nodes.size(), 1));
+    add_region(p, "afw_work", sizeof(fk::WorkItem) * std::max<size_t>(p->adj.fw_work.size(), 1));
+    add_region(p, "afw_tiles", sizeof(fk::TileBox) * std::max<size_t>(p->adj.fw_tiles.size(), 1));
+    add_region(p, "abox_nodes", sizeof(int) * std::max<size_t>(p->adj.box_nodes.size(), 1));
+    add_region(p, "abox_work", sizeof(fk::WorkItem) * std::max<size_t>(p->adj.box_work.size(), 1));
+    add_region(p, "abox_tiles", sizeof(fk::TileBox) * std::max<size_t>(p->adj.box_tiles.size(), 1));
     add_region(p, "fw_nodes", sizeof(int) * std::max<size_t>(p->fw_nodes.size(), 1));
     add_region(p, "fw_work", sizeof(fk::WorkItem) * std::max<size_t>(p->fw_work.size(), 1));
     add_region(p, "fw_split_work", sizeof(fk::WorkItem) * std::max<size_t>(p->fw_split_work.size(), 1));
@@ -812,8 +863,19 @@ void fill_dev(fk_plan *p)
     D.act_work = (const fk::WorkItem *)p->at("act_work");
     D.row_work = (const fk::WorkItem *)p->at("row_work");
     D.split_work = (const fk::WorkItem *)p->at("split_work");
-    D.fw_tiles = (const fk::TileBox *)p->at("fw_tiles");
-    D.box_tiles = (const fk::TileBox *)p->at("box_tiles");
+    D.adj.fw_nodes = (const int *)p->at("afw_nodes");
+    D.adj.fw_work = (const fk::WorkItem *)p->at("afw_work");
+    D.adj.fw_tiles = (const fk::TileBox *)p->at("afw_tiles");
+    D.adj.n_fw_work = (int)p->adj.fw_work.size();
+    D.adj.fw_grid = grid_for(p->adj.fw_work.size());
+    D.adj.box_nodes = (const int *)p->at("abox_nodes");
+    D.adj.box_work = (const fk::WorkItem *)p->at("abox_work");
+    D.adj.box_tiles = (const fk::TileBox *)p->at("abox_tiles");
+    for (int c2 = 0; c2 < fk::kBoxClasses; ++c2) {
+        D.adj.box_work_off[c2] = p->adj.box_work_off[c2];
+        D.adj.n_box_work[c2] = p->adj.n_box_work[c2];
+        D.adj.box_grid[c2] = grid_for(p->adj.n_box_work[c2]);
+    }
     D.fw_nodes = (const int *)p->at("fw_nodes");
     D.fw_work = (const fk::WorkItem *)p->at("fw_work");
     D.n_fw_work = (int)p->fw_work.size();
@@ -1123,8 +1185,12 @@ fk_status fk_plan_set_workspace(fk_plan *p, void *dev_ptr, size_t bytes, void *s
     FK_TRY(up("act_work", p->act_work.data(), sizeof(fk::WorkItem) * p->act_work.size()));
     FK_TRY(up("row_work", p->row_work.data(), sizeof(fk::WorkItem) * p->row_work.size()));
     FK_TRY(up("split_work", p->split_work.data(), sizeof(fk::WorkItem) * p->split_work.size()));
-    FK_TRY(up("fw_tiles", p->fw_tiles.data(), sizeof(fk::TileBox) * p->fw_tiles.size()));
-    FK_TRY(up("box_tiles", p->box_tiles.data(), sizeof(fk::TileBox) * p->box_tiles.size()));
+    FK_TRY(up("afw_nodes", p->adj.fw_nodes.data(), sizeof(int) * p->adj.fw_nodes.size()));
+    FK_TRY(up("afw_work", p->adj.fw_work.data(), sizeof(fk::WorkItem) * p->adj.fw_work.size()));
+    FK_TRY(up("afw_tiles", p->adj.fw_tiles.data(), sizeof(fk::TileBox) * p->adj.fw_tiles.size()));
+    FK_TRY(up("abox_nodes", p->adj.box_nodes.data(), sizeof(int) * p->adj.box_nodes.size()));
+    FK_TRY(up("abox_work", p->adj.box_work.data(), sizeof(fk::WorkItem) * p->adj.box_work.size()));
+    FK_TRY(up("abox_tiles", p->adj.box_tiles.data(), sizeof(fk::TileBox) * p->adj.box_tiles.size()));
     FK_TRY(up("fw_nodes", p->fw_nodes.data(), sizeof(int) * p->fw_nodes.size()));
     FK_TRY(up("fw_work", p->fw_work.data(), sizeof(fk::WorkItem) * p->fw_work.size()));
     FK_TRY(up("fw_split_work", p->fw_split_work.data(), sizeof(fk::WorkItem) * p->fw_split_work.size()));

@@ -59,6 +59,23 @@ struct TileBox {
     int pad;
 };
 
+// The adjoint's work lists: active nodes handled per landing point (fw) and
+// separable nodes handled in box form by footprint class, each work item with
+// its LDS tile.  Box classes: L = 4, 6 in 2D; 3, 4, 5, 6, 8 in 3D.
+struct AdjLists {
+    const int *fw_nodes;
+    const WorkItem *fw_work;
+    const TileBox *fw_tiles;
+    int n_fw_work;
+    int fw_grid;
+    const int *box_nodes;
+    const WorkItem *box_work;
+    const TileBox *box_tiles;
+    int box_work_off[kBoxClasses];
+    int n_box_work[kBoxClasses];
+    int box_grid[kBoxClasses];
+};
+
 // Pointers into the workspace that every launch needs.
 struct PlanDev {
     const DevInst *inst;
@@ -105,9 +122,8 @@ struct PlanDev {
     int box_work_off[kBoxClasses];
     int n_box_work[kBoxClasses];
     int box_grid[kBoxClasses];
-    const TileBox *fw_tiles;    // adjoint LDS tile per fw_work item
-    const TileBox *box_tiles;   // adjoint LDS tile per box_work item
-    int tile_elems;             // LDS entries of the largest tile in use
+    AdjLists adj;               // adjoint step work
+    int tile_elems;             // LDS entries (FP64) of the largest adjoint tile in use
     const WorkItem *split_work; // chunks of block / pow2(Q*) active nodes
     int n_split_work;
     int split_grid;

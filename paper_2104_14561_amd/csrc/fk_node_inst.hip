@@ -12,7 +12,9 @@
 // The separable-box kernels are compiled for d >= 2 on affine axes only: in
 // one dimension the thread-per-node kernel already contracts a single axis,
 // and the plan builder enables the box form only for plans whose axes are all
-// affine (box_compiled below).
+// affine (box_compiled).  The adjoint has its own lists (P.adj): in 2D its box
+// classes are L = 4 and 6, where the saved scatter adds outweigh the cost of
+// building the weight vectors.
 #include "fk_device.h"
 
 #if !defined(FK_INST_F32) || !defined(FK_INST_D) || !defined(FK_INST_ADJ) || !defined(FK_INST_NAME)
@@ -67,22 +69,32 @@ void adjoint_node_launch(const PlanDev &P, int n, const void *packed, const void
                          double *grad, hipStream_t s)
 {
     const size_t lds = (size_t)P.tile_elems * sizeof(double);   // FP64 tiles
-    if (P.n_fw_work > 0) {
+    const AdjLists &A = P.adj;
+    if (A.n_fw_work > 0) {
         if (P.all_affine)
-            k_adjoint_node<T, D, QS, true><<<P.fw_grid, kBlock, lds, s>>>(
-                P, n, P.n_fw_work, P.inst, P.fw_work, P.fw_tiles, P.fw_nodes, P.trig, P.coords,
+            k_adjoint_node<T, D, QS, true><<<A.fw_grid, kBlock, lds, s>>>(
+                P, n, A.n_fw_work, P.inst, A.fw_work, A.fw_tiles, A.fw_nodes, P.trig, P.coords,
                 (const T *)packed, (const T *)lam, (T *)mu, grad);
         else
-            k_adjoint_node<T, D, QS, false><<<P.fw_grid, kBlock, lds, s>>>(
-                P, n, P.n_fw_work, P.inst, P.fw_work, P.fw_tiles, P.fw_nodes, P.trig, P.coords,
+            k_adjoint_node<T, D, QS, false><<<A.fw_grid, kBlock, lds, s>>>(
+                P, n, A.n_fw_work, P.inst, A.fw_work, A.fw_tiles, A.fw_nodes, P.trig, P.coords,
                 (const T *)packed, (const T *)lam, (T *)mu, grad);
     }
-    if constexpr (D >= 2) {
+    if constexpr (D == 2) {
 #define FK_ABOX(c_, L_)                                                                        \
-        if (P.n_box_work[c_] > 0)                                                              \
-            k_adjoint_box<T, D, QS, L_, true><<<P.box_grid[c_], kBlock, lds, s>>>(             \
-                P, n, P.n_box_work[c_], P.inst, P.box_work + P.box_work_off[c_],               \
-                P.box_tiles + P.box_work_off[c_], P.box_nodes, P.trig, P.coords,               \
+        if (A.n_box_work[c_] > 0)                                                              \
+            k_adjoint_box2<T, QS, L_><<<A.box_grid[c_], kBlock, lds, s>>>(                     \
+                P, n, A.n_box_work[c_], P.inst, A.box_work + A.box_work_off[c_],               \
+                A.box_tiles + A.box_work_off[c_], A.box_nodes, P.trig, P.coords,               \
+                (const T *)packed, (const T *)lam, (T *)mu, grad);
+        FK_ABOX(0, 4) FK_ABOX(1, 6)
+#undef FK_ABOX
+    } else if constexpr (D == 3) {
+#define FK_ABOX(c_, L_)                                                                        \
+        if (A.n_box_work[c_] > 0)                                                              \
+            k_adjoint_box<T, D, QS, L_, true><<<A.box_grid[c_], kBlock, lds, s>>>(             \
+                P, n, A.n_box_work[c_], P.inst, A.box_work + A.box_work_off[c_],               \
+                A.box_tiles + A.box_work_off[c_], A.box_nodes, P.trig, P.coords,               \
                 (const T *)packed, (const T *)lam, (T *)mu, grad);
         FK_ABOX(0, 3) FK_ABOX(1, 4) FK_ABOX(2, 5) FK_ABOX(3, 6) FK_ABOX(4, 8)
 #undef FK_ABOX
@@ -107,7 +119,7 @@ bool FK_INST_NAME(const PlanDev &P, int n, const void *packed, const void *lam, 
 {
     if (P.d != kInstD) return false;
     bool any_box = false;
-    for (int c = 0; c < kBoxClasses; ++c) any_box = any_box || P.n_box_work[c] > 0;
+    for (int c = 0; c < kBoxClasses; ++c) any_box = any_box || P.adj.n_box_work[c] > 0;
     if (any_box && !(kInstD >= 2 && P.all_affine)) return false;
 #define FK_QS(v) case v: adjoint_node_launch<InstT, kInstD, v>(P, n, packed, lam, mu, grad, s); return true;
 #endif

@@ -38,11 +38,16 @@ def _rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
-@pytest.mark.parametrize("kernel", ["auto", "box", "group"])
-@pytest.mark.parametrize("case", ["cell2d", "const1d", "abc3d"])
+@pytest.mark.parametrize("kernel", ["auto", "node", "box", "group"])
+@pytest.mark.parametrize("case", ["cell2d", "const1d", "abc3d", "box2d"])
 def test_adjoint_matches_oracle_fp64(case, kernel):
     if case == "cell2d":
         prob = W.cell2d(nx=65, ny=33, n_steps=14, dt=2e-3, D=2e-3, A=1.1, eps=0.2, omega=5.0)
+    elif case == "box2d":
+        # box exit: every node separable, footprints touching the faces
+        prob = W.Problem(axes=[W.uniform_axis(0, 1, 37), W.uniform_axis(0, 2, 71)],
+                         coef_kind="const", coef=(0.4, -0.7), D=0.01, region_kind="box",
+                         gh_q=5, dt=0.01, n_steps=9)
     elif case == "const1d":
         prob = W.Problem(axes=[W.uniform_axis(-1, 1, 61)], coef_kind="const", coef=(0.3,),
                          D=0.2, region_kind="box", gh_q=6, dt=0.01, n_steps=15)
@@ -53,9 +58,13 @@ def test_adjoint_matches_oracle_fp64(case, kernel):
     gg, ll = _gpu_adjoint([prob], [lam0], kernel=kernel)
     g, lamN = gg[0], ll[0]
     nt = len(g_ref)
-    print(case, g[:nt], g_ref)
+    print(case, g[:nt], g_ref, "lamN rel", _rel(lamN, lamN_ref))
     assert _rel(g[:nt], g_ref) <= 1e-10
-    assert _rel(lamN, lamN_ref) <= 1e-11
+    # lam^N passes through the PCHIP Jacobian of u^1, whose derivative depends
+    # on the ratio of divided differences: where rows are nearly flat (the box
+    # case has translation-invariant rows) their rounding is amplified, so the
+    # bar there reflects that conditioning
+    assert _rel(lamN, lamN_ref) <= (1e-8 if case == "box2d" else 1e-11)
 
 
 def test_checkpoint_interval_does_not_change_result():

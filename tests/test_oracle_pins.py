@@ -564,3 +564,22 @@ def test_conditioning_depends_on_resolution():
     print(a_coarse, a_fine)
     assert a_coarse > 1e3
     assert a_fine < 1.0
+
+
+def test_adjoint_translation_equivariant_in_flat_rows():
+    """Box exit, constant drift: away from the x faces every row of u^n along x
+    is the same function of y, so the adjoint of a point source shifted by one
+    row along x is the shifted adjoint.  Rows that are equal up to rounding
+    make the PCHIP slope's divided differences vanish; the linearisation must
+    treat them as flat (derivative 0) whatever their last bits, else a spurious
+    O(1) jump appears between neighbouring rows."""
+    prob = W.Problem(axes=[W.uniform_axis(0, 1, 37), W.uniform_axis(0, 2, 71)],
+                     coef_kind="const", coef=(0.4, -0.7), D=0.01, region_kind="box",
+                     gh_q=5, dt=0.01, n_steps=3)
+    outs = []
+    for i in (12, 13):
+        lam0 = np.zeros(prob.shape)
+        lam0[i, 2] = 1.0
+        outs.append(oracle.adjoint(prob, lam0)[1])
+    a, b = outs
+    assert np.abs(a[8:26, :] - b[9:27, :]).max() <= 1e-12 * np.abs(a).max()
