@@ -87,17 +87,20 @@ def alu_roofline(flops, n_nodes: int, ms_kernel: float, kernel: str, precision: 
 
 
 def ell_roofline(plan, ms_apply: float):
-    """Algorithmic bytes of one ELL product: per row W (col int32 + value)
-    pairs, the exit mass, the gathered record entry per pair, the row's own
-    record value and the output value."""
+    """Algorithmic bytes of one ELL product: every stored (col int32, value)
+    pair once, per row the exit mass, its own record value and the output
+    value, and the node records the gathers read, each once (d+1 entries
+    padded to the record stride, all nodes of the plan)."""
     s = 4 if plan.precision == "f32" else 8
-    W_ = int(plan.info.ell_width)
+    entries = int(plan.info.ell_entries)
     rows = int(plan.info.n_active)
-    bytes_ = rows * (W_ * (4 + s) + s + W_ * s + s + s)
+    ps = 2 if plan.problems[0].d == 1 else 4
+    bytes_ = entries * (4 + s) + rows * 3 * s + plan.n_nodes * ps * s
     achieved = bytes_ / (ms_apply * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None, "kernel": "k_ell_apply",
-            "launch_ms": round(ms_apply, 5), "bytes_per_launch": bytes_, "ell_width": W_}
+            "launch_ms": round(ms_apply, 5), "bytes_per_launch": bytes_, "ell_entries": entries,
+            "rows": rows}
 
 
 def disc_mean_weights(probs, dtype, device):
@@ -288,6 +291,25 @@ def main():
         log(f"plain FP64: {plain_rate:.4e} gp-steps/s, speedup {value / plain_rate:.2f}, "
             f"u0 diff max {errs.max():.2e} median {np.median(errs):.2e}, "
             f"grad abs diff max {gabs.max():.2e}, rel (norm >= 1e-3) median {np.median(big):.2e}")
+
+        # assembled ELL form on the batch (HBM roofline of the product; a
+        # shortened pass: every step costs the same)
+        n_ell = 50
+        pb = Plan([p.replace(n_steps=n_ell) for p in probs], precision="f32", form="ell",
+                  use_graph=True)
+        pb.forward([0])
+        torch.cuda.synchronize()
+        ms_eb, _ = event_time(lambda: pb.forward([0]), 1, stream)
+        ppb = pb.profile_pass()
+        result["ell_batched"] = {
+            "workload": f"cell2d_batch64, first {n_ell} steps, FP32, A_n assembled each step "
+                        f"(ELL, per-instance width, column-major)",
+            "gp_steps_per_s": Ja * n_ell / (ms_eb * 1e-3),
+            "kernels_ms": {k: v[0] for k, v in ppb.items() if v[1]},
+            "roofline_ell_apply": ell_roofline(pb, ppb["ell_apply"][0])}
+        pb.close()
+        log(f"ELL batched: {result['ell_batched']['gp_steps_per_s']:.4e} gp-steps/s, apply "
+            f"{result['ell_batched']['roofline_ell_apply']['achieved']} GB/s")
 
         # assembled ELL form on the single 513x257 instance (HBM roofline)
         single = W.cell2d()

@@ -135,8 +135,9 @@ typedef struct {
     int n_theta;            /* theta per instance (drift params + D) */
     int64_t n_nodes;        /* nodes of all instances */
     int64_t n_active;       /* active nodes of all instances */
-    int64_t ell_width;      /* ELL row width (FK_FORM_ELL), else 0 */
+    int64_t ell_width;      /* ELL row width (FK_FORM_ELL), else 0; the widest instance */
     size_t workspace_bytes;
+    int64_t ell_entries;    /* stored ELL entries, sum over instances of width x active rows */
 } fk_plan_info;
 
 typedef struct fk_plan fk_plan;

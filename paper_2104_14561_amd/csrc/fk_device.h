@@ -1272,6 +1272,8 @@ __global__ void __launch_bounds__(kBlock) k_ell_apply(PlanDev P, const int *__re
         T acc = exit_mass[row] * (T(1) - uref);
         const int *cr = cols + I.ell_off + r;
         const T *vr = vals + I.ell_off + r;
+        // several independent (col, value, gather) chains in flight per lane
+#pragma unroll 4
         for (int k = 0; k < W; ++k) {
             const int col = cr[k * rows];
             const T x = packed[col];

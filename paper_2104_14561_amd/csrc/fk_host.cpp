@@ -1136,6 +1136,7 @@ fk_status fk_plan_get_info(const fk_plan *p, fk_plan_info *info)
     info->n_nodes = p->n_nodes;
     info->n_active = p->n_active;
     info->ell_width = p->ell_width;
+    info->ell_entries = p->opt.form == FK_FORM_ELL ? p->ell_total : 0;
     info->workspace_bytes = p->ws_bytes;
     return FK_OK;
 }

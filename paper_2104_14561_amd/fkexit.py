@@ -61,7 +61,8 @@ class _Info(ctypes.Structure):
     _fields_ = [("n_inst", ctypes.c_int), ("d", ctypes.c_int), ("gh_q", ctypes.c_int),
                 ("n_quad", ctypes.c_int), ("n_steps", ctypes.c_int), ("n_theta", ctypes.c_int),
                 ("n_nodes", ctypes.c_int64), ("n_active", ctypes.c_int64),
-                ("ell_width", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t)]
+                ("ell_width", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t),
+                ("ell_entries", ctypes.c_int64)]
 
 
 class _TuneResult(ctypes.Structure):
