@@ -87,15 +87,16 @@ def alu_roofline(flops, n_nodes: int, ms_kernel: float, kernel: str, precision: 
 
 
 def ell_roofline(plan, ms_apply: float):
-    """Algorithmic bytes of one ELL product: every stored (col int32, value)
-    pair once, per row the exit mass, its own record value and the output
-    value, and the node records the gathers read, each once (d+1 entries
-    padded to the record stride, all nodes of the plan)."""
+    """Algorithmic bytes of one product of the stored operator: every stored
+    value once (the rows are dense node boxes, their columns implicit in the
+    box origin), per row the origin (3 int32), the exit mass, its own record
+    value and the output value, and the node records the gathers read, each
+    once (d+1 entries padded to the record stride, all nodes of the plan)."""
     s = 4 if plan.precision == "f32" else 8
     entries = int(plan.info.ell_entries)
     rows = int(plan.info.n_active)
     ps = 2 if plan.problems[0].d == 1 else 4
-    bytes_ = entries * (4 + s) + rows * 3 * s + plan.n_nodes * ps * s
+    bytes_ = entries * s + rows * (12 + 3 * s) + plan.n_nodes * ps * s
     achieved = bytes_ / (ms_apply * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None, "kernel": "k_ell_apply",
@@ -303,7 +304,7 @@ def main():
         ppb = pb.profile_pass()
         result["ell_batched"] = {
             "workload": f"cell2d_batch64, first {n_ell} steps, FP32, A_n assembled each step "
-                        f"(ELL, per-instance width, column-major)",
+                        f"(one dense node box per row, per-instance width, field-planar)",
             "gp_steps_per_s": Ja * n_ell / (ms_eb * 1e-3),
             "kernels_ms": {k: v[0] for k, v in ppb.items() if v[1]},
             "roofline_ell_apply": ell_roofline(pb, ppb["ell_apply"][0])}

@@ -80,8 +80,11 @@ enum { FK_PREC_F64 = 0, FK_PREC_F32 = 1 };
 
 /* FK_FORM_FUSED: matrix-free step (landing, weights and contraction in one
  * kernel).  FK_FORM_ELL: the step operator A_n = Q Psi^n (Eq. (e36)) is
- * assembled each step into ELL storage and then applied as a sparse
- * matrix-vector product, the paper's own GPU formulation (Section 3.2.1). */
+ * assembled each step into ELL-like storage and then applied as a sparse
+ * matrix-vector product, the paper's own GPU formulation (Section 3.2.1).
+ * Internally each row is stored as the dense box of nodes its landing cells
+ * can cover (columns implicit in the box origin); fk_export_ell writes the
+ * plain (column, value) layout. */
 enum { FK_FORM_FUSED = 0, FK_FORM_ELL = 1 };
 
 typedef struct {

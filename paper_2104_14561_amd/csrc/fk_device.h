@@ -1143,15 +1143,19 @@ __device__ inline void lds_add(double *p, double v)
 }
 
 // ---------------------------------------------------------------------------
-// Assembled form (the paper's GPU formulation, Section 3.2.1): A_n stored in
-// ELL, each row the dense box of nodes covered by its landing points times
-// (d+1) fields.  The lane group of a row builds it in LDS with shared atomics,
-// then writes it column-major (coalesced for the row-per-thread product).
-// The stored row is the plain operator (u^n_j = exit_mass + A_j [u; g]); the
-// product evaluates it in the same offset form as the fused pass.
+// Assembled form (the paper's GPU formulation, Section 3.2.1): A_n stored as
+// one dense box per row -- the L_0 x .. x L_{d-1} nodes its landing cells can
+// cover (origin: the cell of the smallest landing coordinate on each axis)
+// times (d+1) fields -- stored column-major within an instance (entry k of
+// all rows, then entry k+1), with the box origin per row.  The columns are
+// implicit in the box, so the product streams values only.  The lane group of
+// a row builds the box in LDS (FP64 adds); the workgroup writes its rows'
+// boxes together, entry by entry.  The stored row is the plain operator
+// (u^n_j = exit_mass + A_j [u; g]); the product evaluates it in the same offset
+// form as the fused pass.
 // ---------------------------------------------------------------------------
 template <typename T, int D, int G>
-__global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n, int *__restrict__ cols,
+__global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n, int *__restrict__ org,
                                                          T *__restrict__ vals,
                                                          T *__restrict__ exit_mass)
 {
@@ -1224,60 +1228,88 @@ __global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n, int *
         }
         em = group_sum<G>(em);
         __syncthreads();
-        if (valid) {
+        if (valid && lane == 0) {
+            for (int a = 0; a < 3; ++a) org[row * 3 + a] = a < D ? origin[a] : 0;
+            exit_mass[row] = em;
+        }
+        // the workgroup's rows are consecutive: write entry k of all of them
+        // together (column-major within the instance: k * rows + r), value f
+        // of box node l at k = f * nbox + l
+        {
+            const int nrow = it.count;
+            const int nbox = W / (D + 1);
             const long long rows = I.n_act;
-            const long long r = row - I.act_off;
-            for (int k = lane; k < W; k += G) {
-                const int f = k % (D + 1);
-                int l = k / (D + 1);
-                long long nd = I.node_off;
-                for (int a = D - 1; a >= 0; --a) {
-                    const int la = l % I.ell_box[a];
-                    l /= I.ell_box[a];
-                    int ia = origin[a] + la;
-                    if (ia > I.n[a] - 1) ia = I.n[a] - 1;   // padding stays in range
-                    nd += (long long)ia * I.stride[a];
-                }
-                cols[I.ell_off + k * rows + r] = (int)(nd * PS + f);
-                vals[I.ell_off + k * rows + r] = (T)mybox[k];
+            const long long r0 = it.first;
+            for (int e = threadIdx.x; e < nrow * W; e += blockDim.x) {
+                const int k = e / nrow, rr = e - k * nrow;
+                const int f = k / nbox, l = k - f * nbox;
+                vals[I.ell_off + (long long)k * rows + r0 + rr] =
+                    (T)box[(long long)rr * P.ell_width + l * (D + 1) + f];
             }
-            if (lane == 0) exit_mass[row] = em;
         }
         __syncthreads();
     }
 }
 
-// Row-per-thread ELL product
-//   u^n[row] = uref + exit_mass[row] (1 - uref) + sum_k val (x[col] - uref [value cols])
-// i.e. exit_mass + A [u; g] written in offset form about uref = u^{n+1}[row].
+// Box-row product, one row per lane: the row walks its box nodes in order
+// (coordinates advanced incrementally), gathering one node record per box
+// node and its (d+1) values, which sit column-major across the rows of the
+// instance so that every value load of a wave is contiguous:
+//   u^n[row] = uref + exit_mass[row] (1 - uref) + sum_box (v_u (u - uref) + sum_a v_a g_a),
+// i.e. exit_mass + A [u; g] in offset form about uref = u^{n+1}[row].
 template <typename T, int D>
-__global__ void __launch_bounds__(kBlock) k_ell_apply(PlanDev P, const int *__restrict__ cols,
+__global__ void __launch_bounds__(kBlock) k_ell_apply(PlanDev P, const int *__restrict__ org,
                                                       const T *__restrict__ vals,
                                                       const T *__restrict__ exit_mass,
                                                       const T *__restrict__ packed,
                                                       T *__restrict__ u_out)
 {
     constexpr int PS = RecStride<D>::value;
+    using R = typename RecT<T, PS>::type;
+    const R *rec = reinterpret_cast<const R *>(packed);
     const WorkRange wr = work_range(0, P.n_row_work);
     for (int w = wr.begin; w < wr.end; w += wr.step) {
         const WorkItem it = P.row_work[w];
         if ((int)threadIdx.x >= it.count) continue;
         const DevInst &I = P.inst[it.inst];
         const int W = I.ell_w;
+        const int nbox = W / (D + 1);
         const long long rows = I.n_act;
         const long long r = it.first + threadIdx.x;
         const long long row = I.act_off + r;
         const int node = P.active[row];
-        const T uref = packed[(I.node_off + node) * PS];
+        const T uref = rec[I.node_off + node].x;
+        int o[3] = {0, 0, 0};
+        for (int a = 0; a < D; ++a) o[a] = org[row * 3 + a];
+        const T *v0 = vals + I.ell_off + r;
+        const long long fs = (long long)nbox * rows;   // stride between field planes
         T acc = exit_mass[row] * (T(1) - uref);
-        const int *cr = cols + I.ell_off + r;
-        const T *vr = vals + I.ell_off + r;
-        // several independent (col, value, gather) chains in flight per lane
+        int bi[3] = {0, 0, 0};
+        // independent gathers of several box nodes in flight per lane
 #pragma unroll 4
-        for (int k = 0; k < W; ++k) {
-            const int col = cr[k * rows];
-            const T x = packed[col];
-            acc += vr[k * rows] * ((col % PS) == 0 ? x - uref : x);
+        for (int l = 0; l < nbox; ++l) {
+            long long nd = I.node_off;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                int ia = o[a] + bi[a];
+                if (ia > I.n[a] - 1) ia = I.n[a] - 1;   // zero-valued padding stays in range
+                nd += (long long)ia * I.stride[a];
+            }
+            const R rc = rec[nd];
+            const T *v = v0 + (long long)l * rows;
+            if constexpr (D == 1) {
+                acc += v[0] * (rc.x - uref) + v[fs] * rc.y;
+            } else if constexpr (D == 2) {
+                acc += v[0] * (rc.x - uref) + v[fs] * rc.y + v[2 * fs] * rc.z;
+            } else {
+                acc += v[0] * (rc.x - uref) + v[fs] * rc.y + v[2 * fs] * rc.z + v[3 * fs] * rc.w;
+            }
+            // next box node (last axis fastest)
+#pragma unroll
+            for (int a = D - 1; a >= 0; --a) {
+                if (++bi[a] < I.ell_box[a]) break;
+                bi[a] = 0;
+            }
         }
         int idx[3];
         split_node<D>(I, node, idx);
@@ -1291,11 +1323,10 @@ __global__ void __launch_bounds__(kBlock) k_ell_apply(PlanDev P, const int *__re
 // width), column-major over all active rows, columns (d+1) node + field,
 // padding entries value 0 (column of the row's own node value).
 template <typename T, int D>
-__global__ void __launch_bounds__(kBlock) k_export_ell(PlanDev P, const int *cols_in,
+__global__ void __launch_bounds__(kBlock) k_export_ell(PlanDev P, const int *org_in,
                                                        const T *vals_in, int *cols_out,
                                                        T *vals_out)
 {
-    constexpr int PS = RecStride<D>::value;
     const long long na = P.n_active;
     const long long total = na * (long long)P.ell_width;
     for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
@@ -1311,8 +1342,18 @@ __global__ void __launch_bounds__(kBlock) k_export_ell(PlanDev P, const int *col
         const DevInst &I = P.inst[lo];
         const long long r = row - I.act_off;
         if (k < I.ell_w) {
-            const int c = cols_in[I.ell_off + (long long)k * I.n_act + r];
-            cols_out[t] = (c / PS) * (D + 1) + (c % PS);
+            const int nbox = I.ell_w / (D + 1);
+            const int f = k / nbox;
+            int rest = k - f * nbox;
+            long long nd = I.node_off;
+            for (int a = D - 1; a >= 0; --a) {
+                const int la = rest % I.ell_box[a];
+                rest /= I.ell_box[a];
+                int ia = org_in[row * 3 + a] + la;
+                if (ia > I.n[a] - 1) ia = I.n[a] - 1;
+                nd += (long long)ia * I.stride[a];
+            }
+            cols_out[t] = (int)(nd * (D + 1) + f);
             vals_out[t] = vals_in[I.ell_off + (long long)k * I.n_act + r];
         } else {
             cols_out[t] = (int)((I.node_off + P.active[row]) * (D + 1));

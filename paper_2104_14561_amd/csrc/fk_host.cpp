@@ -826,7 +826,7 @@ fk_status build_plan(fk_plan *p)
     add_region(p, "uB", fb);
     add_region(p, "packed", fb * rec_stride(p->d));
     if (p->opt.form == FK_FORM_ELL) {
-        add_region(p, "ell_cols", sizeof(int) * (size_t)std::max<long long>(p->ell_total, 1));
+        add_region(p, "ell_org", sizeof(int) * 3 * (size_t)std::max<long long>(p->n_active, 1));
         add_region(p, "ell_vals", elt(p) * (size_t)std::max<long long>(p->ell_total, 1));
         add_region(p, "ell_em", elt(p) * (size_t)std::max<long long>(p->n_active, 1));
     }
@@ -950,7 +950,7 @@ fk_status enqueue_step(fk_plan *p, int n, const void *u_next, void *u_out, hipSt
     void *packed = p->at("packed");
     FK_LAUNCH(fk::launch_slopes(p->dev, p->f32, n, u_next, packed, s));
     if (p->opt.form == FK_FORM_ELL) {
-        int *cols = (int *)p->at("ell_cols");
+        int *cols = (int *)p->at("ell_org");
         void *vals = p->at("ell_vals"), *em = p->at("ell_em");
         FK_LAUNCH(fk::launch_assemble_ell(p->dev, p->f32, n, cols, vals, em, s));
         FK_LAUNCH(fk::launch_ell_apply(p->dev, p->f32, cols, vals, em, packed, u_out, s));
@@ -1254,7 +1254,7 @@ fk_status fk_export_ell(fk_plan *p, int n, int *cols, void *vals, void *exit_mas
     if (n < 0 || n >= p->N) return fail(FK_ERR_ARG, "step outside [0, N-1]");
     if (!cols || !vals || !exit_mass) return fail(FK_ERR_ARG, "null output");
     hipStream_t s = (hipStream_t)stream;
-    int *icols = (int *)p->at("ell_cols");
+    int *icols = (int *)p->at("ell_org");
     void *ivals = p->at("ell_vals"), *iem = p->at("ell_em");
     FK_LAUNCH(fk::launch_tables(p->dev, n, s));
     FK_LAUNCH(fk::launch_assemble_ell(p->dev, p->f32, n, icols, ivals, iem, s));
@@ -1376,7 +1376,7 @@ fk_status fk_profile_pass(fk_plan *p, double *ms, int *counts, void *stream)
         FK_LAUNCH(fk::launch_slopes(p->dev, p->f32, n, cur, packed, s));
         FK_TRY(rec(0));
         if (p->opt.form == FK_FORM_ELL) {
-            int *cols = (int *)p->at("ell_cols");
+            int *cols = (int *)p->at("ell_org");
             void *vals = p->at("ell_vals"), *em = p->at("ell_em");
             FK_LAUNCH(fk::launch_assemble_ell(p->dev, p->f32, n, cols, vals, em, s));
             FK_TRY(rec(2));

@@ -167,12 +167,12 @@ FK_ADJ_ENTRY(adjoint_node_f32_d1) FK_ADJ_ENTRY(adjoint_node_f32_d2) FK_ADJ_ENTRY
 FK_ADJ_ENTRY(adjoint_node_f64_d1) FK_ADJ_ENTRY(adjoint_node_f64_d2) FK_ADJ_ENTRY(adjoint_node_f64_d3)
 #undef FK_NODE_ENTRY
 #undef FK_ADJ_ENTRY
-hipError_t launch_assemble_ell(const PlanDev &P, bool f32, int n, int *cols, void *vals,
+hipError_t launch_assemble_ell(const PlanDev &P, bool f32, int n, int *org, void *vals,
                                void *exit_mass, hipStream_t s);
-hipError_t launch_ell_apply(const PlanDev &P, bool f32, const int *cols, const void *vals,
+hipError_t launch_ell_apply(const PlanDev &P, bool f32, const int *org, const void *vals,
                             const void *exit_mass, const void *packed, void *u_out,
                             hipStream_t s);
-hipError_t launch_export_ell(const PlanDev &P, bool f32, const int *cols_in, const void *vals_in,
+hipError_t launch_export_ell(const PlanDev &P, bool f32, const int *org_in, const void *vals_in,
                              int *cols_out, void *vals_out, hipStream_t s);
 hipError_t launch_export_cells(const PlanDev &P, int inst, int n, int *cells,
                                unsigned char *exit_flags, hipStream_t s);

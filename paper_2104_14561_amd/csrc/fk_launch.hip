@@ -100,32 +100,32 @@ hipError_t launch_step_fused(const PlanDev &P, bool f32, int n, const void *pack
     return hipSuccess;
 }
 
-hipError_t launch_assemble_ell(const PlanDev &P, bool f32, int n, int *cols, void *vals,
+hipError_t launch_assemble_ell(const PlanDev &P, bool f32, int n, int *org, void *vals,
                                void *exit_mass, hipStream_t s)
 {
     const size_t lds = (size_t)(kBlock / P.group) * P.ell_width * sizeof(double);   // FP64 row boxes
     FK_DISPATCH_D(P.d, FK_DISPATCH_G(P.group,
-        if (f32) k_assemble_ell<float, D, G><<<P.act_grid, kBlock, lds, s>>>(P, n, cols, (float *)vals, (float *)exit_mass);
-        else k_assemble_ell<double, D, G><<<P.act_grid, kBlock, lds, s>>>(P, n, cols, (double *)vals, (double *)exit_mass)));
+        if (f32) k_assemble_ell<float, D, G><<<P.act_grid, kBlock, lds, s>>>(P, n, org, (float *)vals, (float *)exit_mass);
+        else k_assemble_ell<double, D, G><<<P.act_grid, kBlock, lds, s>>>(P, n, org, (double *)vals, (double *)exit_mass)));
     return hipGetLastError();
 }
 
-hipError_t launch_ell_apply(const PlanDev &P, bool f32, const int *cols, const void *vals,
+hipError_t launch_ell_apply(const PlanDev &P, bool f32, const int *org, const void *vals,
                             const void *exit_mass, const void *packed, void *u_out, hipStream_t s)
 {
     FK_DISPATCH_D(P.d,
-        if (f32) k_ell_apply<float, D><<<P.row_grid, kBlock, 0, s>>>(P, cols, (const float *)vals, (const float *)exit_mass, (const float *)packed, (float *)u_out);
-        else k_ell_apply<double, D><<<P.row_grid, kBlock, 0, s>>>(P, cols, (const double *)vals, (const double *)exit_mass, (const double *)packed, (double *)u_out));
+        if (f32) k_ell_apply<float, D><<<P.row_grid, kBlock, 0, s>>>(P, org, (const float *)vals, (const float *)exit_mass, (const float *)packed, (float *)u_out);
+        else k_ell_apply<double, D><<<P.row_grid, kBlock, 0, s>>>(P, org, (const double *)vals, (const double *)exit_mass, (const double *)packed, (double *)u_out));
     return hipGetLastError();
 }
 
-hipError_t launch_export_ell(const PlanDev &P, bool f32, const int *cols_in, const void *vals_in,
+hipError_t launch_export_ell(const PlanDev &P, bool f32, const int *org_in, const void *vals_in,
                              int *cols_out, void *vals_out, hipStream_t s)
 {
     const int g = flat_grid(P.n_active * (long long)P.ell_width);
     FK_DISPATCH_D(P.d,
-        if (f32) k_export_ell<float, D><<<g, kBlock, 0, s>>>(P, cols_in, (const float *)vals_in, cols_out, (float *)vals_out);
-        else k_export_ell<double, D><<<g, kBlock, 0, s>>>(P, cols_in, (const double *)vals_in, cols_out, (double *)vals_out));
+        if (f32) k_export_ell<float, D><<<g, kBlock, 0, s>>>(P, org_in, (const float *)vals_in, cols_out, (float *)vals_out);
+        else k_export_ell<double, D><<<g, kBlock, 0, s>>>(P, org_in, (const double *)vals_in, cols_out, (double *)vals_out));
     return hipGetLastError();
 }
 
