@@ -771,6 +771,7 @@ __global__ void __launch_bounds__(kBlock) k_step_node(
         const WorkItem it = work[w];
         if (G == 1 && slot >= it.count) continue;
         const bool valid = slot < it.count;
+        const bool interior = it.kind == 1;   // host: no landing point can exit
         const DevInst &I = insts[it.inst];
         const int node = valid ? nodes[it.first + slot] : nodes[it.first];
         int idx[3];
@@ -812,35 +813,54 @@ __global__ void __launch_bounds__(kBlock) k_step_node(
                 acc += w1[q] * v;
             }
         } else if constexpr (D == 2) {
-            for (int q0 = lane; q0 < QS; q0 += G) {
-                const AxisEval e0 = eval_axis_t<AFF>(I, coords, 0, c[0], ga[q0]);
-                const T w0 = w1[q0];
-                if (e0.ex) {
-                    emass += w0 * wsum;
-                    continue;
-                }
-                const Basis<T> X = hermite<T>(e0.s, e0.h);
-                const long long row = I.node_off + (long long)e0.k * I.stride[0];
-                const long long s0 = I.stride[0];
-                T part = T(0), pex = T(0);
+            // records of the instance, indexed with 32-bit offsets
+            const R *ri = rec + I.node_off;
+            const int s0 = I.stride[0];
+            // landing point (q0, q1) of a cell row: the tensor Hermite value
+            auto point = [&](int row, const Basis<T> &X, int q1) -> T {
+                const int b = row + kin[q1];
+                const R p00 = ri[b], p01 = ri[b + 1], p10 = ri[b + s0], p11 = ri[b + s0 + 1];
+                const T A0 = (p00.x - uref) * X.v0 + (p10.x - uref) * X.v1 + p00.y * X.d0 + p10.y * X.d1;
+                const T A1 = (p01.x - uref) * X.v0 + (p11.x - uref) * X.v1 + p01.y * X.d0 + p11.y * X.d1;
+                const T C0 = p00.z * X.v0 + p10.z * X.v1;
+                const T C1 = p01.z * X.v0 + p11.z * X.v1;
+                return w1[q1] * (bin[q1][0] * A0 + bin[q1][1] * A1 + bin[q1][2] * C0 + bin[q1][3] * C1);
+            };
+            if (interior) {
+                // no landing point of this work item can exit: no exit tests
+                for (int q0 = lane; q0 < QS; q0 += G) {
+                    const AxisEval e0 = eval_axis_t<AFF>(I, coords, 0, c[0], ga[q0]);
+                    const Basis<T> X = hermite<T>(e0.s, e0.h);
+                    const int row = e0.k * s0;
+                    T part = T(0);
 #pragma unroll
-                for (int q1 = 0; q1 < QS; ++q1) {
-                    bool ex = exin[q1];
-                    if (ball) ex = ex || ball_exit2(e0.dz2, din[q1], r2);
-                    if (ex) {
-                        pex += w1[q1];
+                    for (int q1 = 0; q1 < QS; ++q1) part += point(row, X, q1);
+                    acc += w1[q0] * part;
+                }
+            } else {
+                for (int q0 = lane; q0 < QS; q0 += G) {
+                    const AxisEval e0 = eval_axis_t<AFF>(I, coords, 0, c[0], ga[q0]);
+                    const T w0 = w1[q0];
+                    if (e0.ex) {
+                        emass += w0 * wsum;
                         continue;
                     }
-                    const long long b = row + kin[q1];
-                    const R p00 = rec[b], p01 = rec[b + 1], p10 = rec[b + s0], p11 = rec[b + s0 + 1];
-                    const T A0 = (p00.x - uref) * X.v0 + (p10.x - uref) * X.v1 + p00.y * X.d0 + p10.y * X.d1;
-                    const T A1 = (p01.x - uref) * X.v0 + (p11.x - uref) * X.v1 + p01.y * X.d0 + p11.y * X.d1;
-                    const T C0 = p00.z * X.v0 + p10.z * X.v1;
-                    const T C1 = p01.z * X.v0 + p11.z * X.v1;
-                    part += w1[q1] * (bin[q1][0] * A0 + bin[q1][1] * A1 + bin[q1][2] * C0 + bin[q1][3] * C1);
+                    const Basis<T> X = hermite<T>(e0.s, e0.h);
+                    const int row = e0.k * s0;
+                    T part = T(0), pex = T(0);
+#pragma unroll
+                    for (int q1 = 0; q1 < QS; ++q1) {
+                        bool ex = exin[q1];
+                        if (ball) ex = ex || ball_exit2(e0.dz2, din[q1], r2);
+                        if (ex) {
+                            pex += w1[q1];
+                            continue;
+                        }
+                        part += point(row, X, q1);
+                    }
+                    acc += w0 * part;
+                    emass += w0 * pex;
                 }
-                acc += w0 * part;
-                emass += w0 * pex;
             }
         } else {
             for (int q0 = lane; q0 < QS; q0 += G) {

@@ -377,6 +377,7 @@ fk_status build_plan(fk_plan *p)
     long long ell_total = 0, ell_wmax = 0;
     std::vector<std::vector<int>> inst_sep, inst_rest;
     std::vector<int> inst_cls, inst_lneed;
+    std::vector<std::vector<unsigned char>> inst_inner;   // per node: no landing point can exit
     std::vector<std::array<int, 3>> inst_dils;
     p->node_off.assign(p->n_inst + 1, 0);
     p->act_count.assign(p->n_inst, 0);
@@ -524,22 +525,37 @@ fk_status build_plan(fk_plan *p)
             for (int c2 = 0; c2 < fk::kBoxClasses; ++c2)
                 if (Lneed <= kL[c2]) { cls_box = c2; break; }
             std::vector<int> sep, rest;
+            std::vector<unsigned char> inner(J, 0);
+            double reach_a[3] = {0, 0, 0};
+            for (int a = 0; a < pr.d; ++a) reach_a[a] = drift_bound(pr, a) * pr.dt + I.S * amax;
             for (int t = 0; t < na; ++t) {
                 const int j = p->active[I.act_off + t];
                 bool separable = true;
-                if (separable && pr.region_kind == FK_REGION_BALL) {
-                    long long r = j;
-                    double dist2 = 0.0;
-                    for (int a = pr.d - 1; a >= 0; --a) {
-                        const int ia = (int)(r % pr.ax[a].n);
-                        r /= pr.ax[a].n;
-                        const double dx = pr.ax[a].nodes[ia] - pr.center[a];
-                        dist2 += dx * dx;
+                // interior: no landing point can leave the box on a non-periodic
+                // axis (with a relative margin for the rounding of z), nor the ball
+                bool interior = true;
+                long long r = j;
+                double dist2 = 0.0;
+                for (int a = pr.d - 1; a >= 0; --a) {
+                    const int ia = (int)(r % pr.ax[a].n);
+                    r /= pr.ax[a].n;
+                    const double x = pr.ax[a].nodes[ia];
+                    const double dx = x - pr.center[a];
+                    dist2 += dx * dx;
+                    if (!pr.ax[a].periodic) {
+                        const double lo = pr.ax[a].nodes[0], hi = pr.ax[a].nodes[pr.ax[a].n - 1];
+                        const double m = reach_a[a] * (1.0 + 1e-6) + 1e-12 * (hi - lo);
+                        interior = interior && x - m > lo && x + m < hi;
                     }
-                    separable = std::sqrt(dist2) + reach < pr.radius * (1.0 - 1e-9);
                 }
+                if (pr.region_kind == FK_REGION_BALL) {
+                    separable = std::sqrt(dist2) + reach < pr.radius * (1.0 - 1e-9);
+                    interior = interior && separable;
+                }
+                inner[j] = interior ? 1 : 0;
                 (separable ? sep : rest).push_back(j);
             }
+            inst_inner.push_back(std::move(inner));
             inst_sep.push_back(sep);
             inst_rest.push_back(rest);
             inst_cls.push_back(cls_box);
@@ -651,8 +667,20 @@ fk_status build_plan(fk_plan *p)
             patch_sort(fw, pr, keys);
             const int f1 = (int)p->fw_nodes.size();
             p->fw_nodes.insert(p->fw_nodes.end(), fw.begin(), fw.end());
+            const size_t w0 = p->fw_work.size(), ws0 = p->fw_split_work.size();
             patch_work(p->fw_work, i, keys, f1, kBlock);
             patch_work(p->fw_split_work, i, keys, f1, kBlock / gs);
+            // kind 1: no landing point of any node of the item can exit
+            auto mark = [&](std::vector<fk::WorkItem> &v, size_t from) {
+                for (size_t t = from; t < v.size(); ++t) {
+                    bool all = true;
+                    for (int u = 0; u < v[t].count && all; ++u)
+                        all = inst_inner[i][p->fw_nodes[v[t].first + u]] != 0;
+                    v[t].kind = all ? 1 : 0;
+                }
+            };
+            mark(p->fw_work, w0);
+            mark(p->fw_split_work, ws0);
         }
         for (int c2 = 0; c2 < fk::kBoxClasses; ++c2) {
             p->box_work_off[c2] = (int)p->box_work.size();
