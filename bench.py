@@ -36,6 +36,10 @@ import workloads as W  # noqa: E402
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (published)
 PEAK_FP64_TFLOPS = 78.6    # MI355X vector FP64 (published)
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E (published)
+# lane-level FP64 LDS atomic adds per second of the chip: 2048 workgroups x 256
+# lanes of conflict-free ds_add_f64 ran at 1.62-1.95e12 on one MI355X (20-24 CU
+# cycles per wave instruction); the best of those runs
+LDS_F64_ATOMIC_PEAK = 1.95e12
 CKPT_LIST = (1, 4, 16, 64)   # checkpoint intervals tried, smallest first
 CKPT_MEM_FRACTION = 0.5       # of free HBM the plan's workspace may take
 
@@ -104,6 +108,30 @@ def ell_roofline(plan, ms_apply: float):
             "rows": rows}
 
 
+def kernel_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("fk_device.h", "fk_node_inst.hip", "fk_launch.hip", "fk_internal.h", "fk_host.cpp"):
+        with open(os.path.join(ROOT, "paper_2104_14561_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy)
+    from the committed counter runs, while the kernel sources are unchanged."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_cell2d_batch64.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except OSError:
+        return None
+    if t.get("kernel_sources_sha256_16") != kernel_sources_hash() or kernel not in t["kernels"]:
+        return None
+    k = t["kernels"][kernel]
+    return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+
+
 def disc_mean_weights(probs, dtype, device):
     """lam0 = dJ/du^0 for J = mean of u^0 over each instance's disc nodes."""
     import torch
@@ -151,6 +179,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="headline line only")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 1 GiB device-to-device once (a kernel of known traffic "
+                         "that scales the HBM byte counters of a profiled run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -163,6 +194,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     stream = torch.cuda.current_stream()
+    if args.copy_probe:
+        n = 1 << 28   # 2^28 float32 = 1 GiB read + 1 GiB written
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy probe: {n * 4} bytes read, {n * 4} bytes written", file=sys.stderr)
+        del src, dst
+        torch.cuda.empty_cache()
     probs = W.cell2d_batch()
     N = probs[0].n_steps
     log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)  # noqa: E731
@@ -208,16 +249,28 @@ def main():
     d, qs = probs[0].d, probs[0].gh_q
     # per bench step: the fused forward step runs in the forward pass (whose
     # checkpoints the adjoint reuses) and once more per recomputed step of the
-    # adjoint; the transposed step once per step
+    # adjoint; the per-point transposed step once per step
     n_recomp = prof_a["recompute_step"][1]
     t_step_kernel = prof_f["step_fused"][0] * (N + n_recomp)
     t_adj_kernel = prof_a["adjoint_step"][0] * prof_a["adjoint_step"][1]
+    n_point = int(plan.info.adj_point_nodes)
     if t_adj_kernel >= t_step_kernel:
-        roof = alu_roofline(adjoint_kernel_flops(d, qs), Ja, prof_a["adjoint_step"][0],
-                            "k_adjoint_node (transposed step)", plan.precision)
+        roof = alu_roofline(adjoint_kernel_flops(d, qs), n_point, prof_a["adjoint_step"][0],
+                            "k_adjoint_node (transposed step, nodes handled per landing point)",
+                            plan.precision)
+        # its real limit: FP64 LDS atomic adds, 2^d (d+1) per inside landing point
+        adds = n_point * qs ** d * (1 << d) * (d + 1)
+        rate = adds / (prof_a["adjoint_step"][0] * 1e-3)
+        roof["lds_fp64_atomic_adds"] = {
+            "per_launch_upper_bound": adds, "achieved_per_s": rate,
+            "probe_peak_per_s": LDS_F64_ATOMIC_PEAK, "frac": round(rate / LDS_F64_ATOMIC_PEAK, 4),
+            "note": "lane-level ds_add_f64 rate; peak measured with a conflict-free probe kernel"}
+        kname = "void k_adjoint_node<float, 2, 8, true>"
     else:
         roof = alu_roofline(step_kernel_flops(d, qs), Ja, prof_f["step_fused"][0],
                             "k_step_node (fused step)", plan.precision)
+        kname = "void k_step_node<float, 2, 8, 1, true>"
+    roof["traffic"] = measured_traffic(kname)
     roof["share_of_step"] = round(max(t_adj_kernel, t_step_kernel) / ms_step, 4)
     u32 = out32[0].double().cpu()
     g32 = g32.double().cpu().numpy()

@@ -141,6 +141,8 @@ typedef struct {
     int64_t ell_width;      /* ELL row width (FK_FORM_ELL), else 0; the widest instance */
     size_t workspace_bytes;
     int64_t ell_entries;    /* stored ELL entries, sum over instances of width x active rows */
+    int64_t adj_point_nodes;  /* adjoint (ckpt_every > 0): active nodes transposed per landing point */
+    int64_t adj_box_nodes;    /* adjoint: active nodes transposed in separable box form */
 } fk_plan_info;
 
 typedef struct fk_plan fk_plan;
@@ -254,11 +256,13 @@ fk_status fk_profile_pass(fk_plan *p, double *ms, int *counts, void *stream);
 
 /* Measurement hook for the adjoint: runs fk_adjoint(p, lam0, grad, NULL,
  * stream) with HIP events around every kernel group of the reverse sweep and
- * returns the mean duration in milliseconds per step of each group in ms[4]
- * (host): [0] slope pass of u^{n+1}, [1] transposed
- * step (the scatter of A_n^T lam^n and the theta-gradient), [2] transposed
- * slope pass with the image fold, [3] forward step recomputed inside a
- * checkpoint segment; counts[4] (host) receives the number of steps timed.
+ * returns the mean duration in milliseconds per step of each group in ms[5]
+ * (host): [0] slope pass of u^{n+1}, [1] transposed step of the nodes
+ * handled per landing point (the scatter of A_n^T lam^n and the
+ * theta-gradient), [2] transposed slope pass with the image fold, [3] forward
+ * step recomputed inside a checkpoint segment, [4] transposed step of the
+ * nodes handled in separable box form; counts[5] (host) receives the number of
+ * steps timed.
  * Arguments and errors as fk_adjoint.  Synchronises stream. */
 fk_status fk_profile_adjoint(fk_plan *p, const void *lam0, double *grad, double *ms,
                              int *counts, void *stream);

@@ -1165,6 +1165,8 @@ fk_status fk_plan_get_info(const fk_plan *p, fk_plan_info *info)
     info->n_active = p->n_active;
     info->ell_width = p->ell_width;
     info->ell_entries = p->opt.form == FK_FORM_ELL ? p->ell_total : 0;
+    info->adj_point_nodes = (int64_t)p->adj.fw_nodes.size();
+    info->adj_box_nodes = (int64_t)p->adj.box_nodes.size();
     info->workspace_bytes = p->ws_bytes;
     return FK_OK;
 }
@@ -1366,8 +1368,14 @@ fk_status fk_adjoint(fk_plan *p, const void *lam0, double *grad, void *lamN, voi
             FK_TRY(prof_mark(p, -1, s));
             FK_LAUNCH(fk::launch_slopes(p->dev, p->f32, n, v, packed, s));
             FK_TRY(prof_mark(p, 0, s));
-            FK_LAUNCH(fk::launch_adjoint_step(p->dev, p->f32, n, packed, la, mu, g, s));
-            FK_TRY(prof_mark(p, 1, s));
+            if (p->prof) {
+                FK_LAUNCH(fk::launch_adjoint_step(p->dev, p->f32, n, packed, la, mu, g, s, 1));
+                FK_TRY(prof_mark(p, 1, s));
+                FK_LAUNCH(fk::launch_adjoint_step(p->dev, p->f32, n, packed, la, mu, g, s, 2));
+                FK_TRY(prof_mark(p, 4, s));
+            } else {
+                FK_LAUNCH(fk::launch_adjoint_step(p->dev, p->f32, n, packed, la, mu, g, s));
+            }
             FK_LAUNCH(fk::launch_adjoint_slopes_T(p->dev, p->f32, v, mu, lb, s));
             FK_TRY(prof_mark(p, 2, s));
             std::swap(la, lb);
@@ -1510,9 +1518,9 @@ fk_status fk_profile_adjoint(fk_plan *p, const void *lam0, double *grad, double 
     p->prof = nullptr;
     fk_status rs = st;
     if (st == FK_OK && hipStreamSynchronize(s) != hipSuccess) rs = fail(FK_ERR_HIP, "stream sync");
-    const int nk = 4;
-    double tot[nk] = {0, 0, 0, 0};
-    int cnt[nk] = {0, 0, 0, 0};
+    const int nk = 5;
+    double tot[nk] = {0, 0, 0, 0, 0};
+    int cnt[nk] = {0, 0, 0, 0, 0};
     for (size_t i = 1; rs == FK_OK && i < ev.size(); ++i) {
         if (ev[i].second < 0) continue;
         float t = 0.f;

@@ -179,8 +179,11 @@ hipError_t launch_export_cells(const PlanDev &P, int inst, int n, int *cells,
 hipError_t launch_clear_flags(const PlanDev &P, hipStream_t s);
 
 // Adjoint launchers.
+// part 0: the whole transposed step; 1: the per-point work list only (or the
+// lane-group form); 2: the separable-box lists only
 hipError_t launch_adjoint_step(const PlanDev &P, bool f32, int n, const void *packed,
-                               const void *lam, void *mu, double *grad, hipStream_t s);
+                               const void *lam, void *mu, double *grad, hipStream_t s,
+                               int part = 0);
 hipError_t launch_adjoint_slopes_T(const PlanDev &P, bool f32, const void *u, void *mu,
                                    void *lam_next, hipStream_t s);
 hipError_t launch_adjoint_init(const PlanDev &P, bool f32, const void *lam0, void *lam,

@@ -150,10 +150,15 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_step(const PlanDev &P, bool f32, int n, const void *packed,
-                               const void *lam, void *mu, double *grad, hipStream_t s)
+hipError_t launch_adjoint_step(const PlanDev &P0, bool f32, int n, const void *packed,
+                               const void *lam, void *mu, double *grad, hipStream_t s, int part)
 {
-    if (P.step_kind != 1) {
+    if (P0.step_kind != 1) {
+        // part 1: the per-point list only, part 2: the box lists only
+        PlanDev P = P0;
+        if (part == 1)
+            for (int c = 0; c < kBoxClasses; ++c) P.adj.n_box_work[c] = 0;
+        if (part == 2) P.adj.n_fw_work = 0;
         bool ok = false;
         switch (P.d) {
         case 1: ok = f32 ? adjoint_node_f32_d1(P, n, packed, lam, mu, grad, s) : adjoint_node_f64_d1(P, n, packed, lam, mu, grad, s); break;
@@ -163,6 +168,8 @@ hipError_t launch_adjoint_step(const PlanDev &P, bool f32, int n, const void *pa
         }
         if (ok) return hipGetLastError();
     }
+    if (part == 2) return hipSuccess;   // the lane-group form has no separate box part
+    const PlanDev &P = P0;
     FK_DISPATCH_D(P.d, FK_DISPATCH_G(P.group,
         if (f32) k_adjoint_step<float, D, G><<<P.act_grid, kBlock, 0, s>>>(P, n, (const float *)packed, (const float *)lam, (float *)mu, grad);
         else k_adjoint_step<double, D, G><<<P.act_grid, kBlock, 0, s>>>(P, n, (const double *)packed, (const double *)lam, (double *)mu, grad)));

@@ -62,7 +62,8 @@ class _Info(ctypes.Structure):
                 ("n_quad", ctypes.c_int), ("n_steps", ctypes.c_int), ("n_theta", ctypes.c_int),
                 ("n_nodes", ctypes.c_int64), ("n_active", ctypes.c_int64),
                 ("ell_width", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t),
-                ("ell_entries", ctypes.c_int64)]
+                ("ell_entries", ctypes.c_int64), ("adj_point_nodes", ctypes.c_int64),
+                ("adj_box_nodes", ctypes.c_int64)]
 
 
 class _TuneResult(ctypes.Structure):
@@ -336,17 +337,18 @@ class Plan:
 
     def profile_adjoint(self, lam0, stream=None):
         """Mean per-step durations (ms) of the adjoint's kernel groups (slope
-        pass + clear, transposed step, transposed slopes + fold, recomputed
-        forward step) over one fk_adjoint call, timed with HIP events."""
+        pass, transposed step per landing point, transposed slopes + fold,
+        recomputed forward step, transposed step in box form) over one
+        fk_adjoint call, timed with HIP events."""
         import torch
         lam0 = lam0.to(self.device, self.dtype).contiguous()
         grad = torch.zeros((len(self.problems), MAX_THETA), dtype=torch.float64, device=self.device)
-        ms = (ctypes.c_double * 4)()
-        cnt = (ctypes.c_int * 4)()
+        ms = (ctypes.c_double * 5)()
+        cnt = (ctypes.c_int * 5)()
         _check(load().fk_profile_adjoint(self._h, ctypes.c_void_p(_ptr(lam0)),
                                          ctypes.c_void_p(_ptr(grad)), ms, cnt,
                                          ctypes.c_void_p(_stream(stream))))
-        names = ("slopes", "adjoint_step", "slopes_T", "recompute_step")
+        names = ("slopes", "adjoint_step", "slopes_T", "recompute_step", "adjoint_box")
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(names)}
 
 
