@@ -136,3 +136,38 @@ def test_adjoint_reuses_forward_checkpoints(prec):
     torch.cuda.synchronize()
     assert _rel(g_side.cpu().numpy(), g_alone) <= tol
     plan.close()
+
+
+def test_adjoint_matches_central_differences_of_gpu_forward():
+    """Adjoint gradient against central differences (relative step h = 1e-6)
+    of the GPU's own FP64 forward, the eight perturbed problems in one batched
+    plan.  The scheme's J is piecewise smooth in theta: a landing point
+    crossing the exit boundary switches its value to 1.  The oracle's exit
+    records show that no landing point changes side within +-h here, so J is
+    smooth over the difference stencil."""
+    h = 1e-6
+    prob = W.cell2d(nx=49, ny=25, n_steps=12, dt=2e-3, D=2e-3, A=1.1, eps=0.2, omega=5.0)
+    theta = list(prob.coef) + [prob.D]
+    _, rec = oracle.solve(prob, snaps=[0], record_exits=True)
+    lam0 = _lam0(prob, seed=40)
+    probs = []
+    for k in range(len(theta)):
+        for sgn in (1, -1):
+            th = list(theta)
+            th[k] = theta[k] * (1 + sgn * h)
+            p = prob.replace(coef=tuple(th[:-1]), D=th[-1])
+            _, r2 = oracle.solve(p, snaps=[0], record_exits=True)
+            assert np.array_equal(r2, rec), "exit classification changes within the stencil"
+            probs.append(p)
+    (g,), _ = _gpu_adjoint([prob], [lam0], "f64", K=5)
+    plan = Plan(probs, precision="f64", use_graph=True)
+    out = plan.forward([0])
+    J = [float(np.sum(lam0 * u.cpu().numpy())) for u in plan.split(out[0])]
+    plan.close()
+    fd = np.array([(J[2 * k] - J[2 * k + 1]) / (2 * h * abs(theta[k]))
+                   for k in range(len(theta))])
+    print("adjoint", g[:4], "central differences", fd)
+    # the difference quotient's own error: rounding of J (per-node state
+    # rounding ~1e-15, summed against lam0) over 2 h theta_k, plus O(h^2)
+    fd_noise = 1e-15 * np.abs(lam0).sum() / (2 * h * np.abs(theta))
+    assert np.all(np.abs(g[:4] - fd) <= 1e-5 * np.abs(fd) + fd_noise)

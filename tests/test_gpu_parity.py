@@ -245,6 +245,68 @@ def test_nonfinite_state_is_flagged():
 
 
 # ---------------------------------------------------------------------------
+# degenerate inputs and the largest rules
+# ---------------------------------------------------------------------------
+
+def _degenerate(case):
+    b = W.cell2d(nx=33, ny=17, n_steps=6)
+    if case == "empty_instance":
+        # a disc that holds no node: every node exits, u = 1 throughout
+        empty = W.cell2d(nx=33, ny=17, n_steps=6, radius=0.02, center=(0.53, 0.53))
+        return [b, empty, b.replace(D=3e-3)]
+    if case == "D0":        # sigma = 0: the Q landing points of a node coincide
+        return [b.replace(D=0.0)]
+    if case == "q1":        # one GH node at 0: the deterministic characteristic
+        return [b.replace(gh_q=1)]
+    if case == "one_step":
+        return [b.replace(n_steps=1)]
+    if case == "q64_1d":    # the largest rule, Q = 64
+        return [W.bm1d(n=101, gh_q=64, n_steps=10)]
+    if case == "q16_2d":    # Q = 256, the largest tensor rule
+        return [b.replace(gh_q=16, n_steps=3)]
+    if case == "q6_3d":     # Q = 216
+        return [W.abc3d(n=9, n_steps=3, dt=0.05, D=3e-3)]
+    raise ValueError(case)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["empty_instance", "D0", "q1", "one_step", "q64_1d",
+                                  "q16_2d", "q6_3d"])
+def test_degenerate_inputs(case, prec):
+    probs = _degenerate(case)
+    N = probs[0].n_steps
+    snaps = sorted({N, N // 2, 0}, reverse=True)
+    got = _run(probs, prec, snaps, use_graph=True)
+    for p, g in zip(probs, got):
+        ref = oracle.solve(p, snaps=snaps)
+        err = _maxerr(g, ref)
+        print(case, prec, p.gh_q, err)
+        assert err <= TOL[prec]
+        if oracle.active_nodes(p).size == 0:
+            assert np.all(g == 1.0)
+
+
+def test_degenerate_adjoint_with_empty_instance():
+    """An instance without active nodes in a batched adjoint: zero gradient,
+    zero lambda^N (exit nodes carry no cotangent), the others as alone."""
+    probs = _degenerate("empty_instance")
+    rng = np.random.default_rng(7)
+    lams = [rng.uniform(size=p.shape) for p in probs]
+    plan = Plan(probs, precision="f64", ckpt_every=4, use_graph=True)
+    lam = torch.cat([torch.from_numpy(l.reshape(-1)) for l in lams]).cuda()
+    g, lN = plan.adjoint(lam)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    lN = [x.cpu().numpy() for x in plan.split(lN)]
+    plan.close()
+    assert np.all(g[1] == 0.0) and np.all(lN[1] == 0.0)
+    for i in (0, 2):
+        g_ref, l_ref = oracle.adjoint(probs[i], lams[i])
+        assert np.abs(g[i, :len(g_ref)] - g_ref).max() <= 1e-10 * np.abs(g_ref).max()
+        assert np.abs(lN[i] - l_ref).max() <= 1e-11 * np.abs(l_ref).max()
+
+
+# ---------------------------------------------------------------------------
 # full-size workloads
 # ---------------------------------------------------------------------------
 
