@@ -583,3 +583,24 @@ def test_adjoint_translation_equivariant_in_flat_rows():
         outs.append(oracle.adjoint(prob, lam0)[1])
     a, b = outs
     assert np.abs(a[8:26, :] - b[9:27, :]).max() <= 1e-12 * np.abs(a).max()
+
+
+def test_full_size_cell2d_adjoint_fixture_matches_frozen_central_differences():
+    """The stored 2000-step oracle adjoint of the 513x257 cellular flow
+    (tests/golden/make_cell2d_adj.py) against the stored central differences
+    with the exit classification frozen (relative step 1e-6): the adjoint is
+    the derivative of the scheme with exits held fixed.  The differences with
+    exits recomputed are stored beside them; a landing point that changes side
+    within +-h switches its value to 1, so they need not agree."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "cell2d_adj_oracle.json")
+    with open(path) as f:
+        ref = json.load(f)
+    prob = W.cell2d_adj()
+    assert tuple(ref["problem"][k] for k in ("nx", "ny")) == prob.shape
+    assert ref["problem"]["dt"] == prob.dt and ref["problem"]["n_steps"] == prob.n_steps
+    assert ref["problem"]["coef"] == list(prob.coef) and ref["problem"]["D"] == prob.D
+    g, fd = np.array(ref["grad"]), np.array(ref["fd_frozen_exits"])
+    assert np.all(np.abs(g - fd) <= 1e-5 * np.abs(fd) + 1e-12), (g, fd)
+    assert 0.0 < ref["J0"] < 1.0
