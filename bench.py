@@ -357,7 +357,7 @@ def main():
         ppb = pb.profile_pass()
         result["ell_batched"] = {
             "workload": f"cell2d_batch64, first {n_ell} steps, FP32, A_n assembled each step "
-                        f"(one dense node box per row, per-instance width, field-planar)",
+                        f"(one dense node box per row, per-instance width, values in 16-byte blocks of box nodes per field)",
             "gp_steps_per_s": Ja * n_ell / (ms_eb * 1e-3),
             "kernels_ms": {k: v[0] for k, v in ppb.items() if v[1]},
             "roofline_ell_apply": ell_roofline(pb, ppb["ell_apply"][0])}

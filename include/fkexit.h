@@ -83,7 +83,8 @@ enum { FK_PREC_F64 = 0, FK_PREC_F32 = 1 };
  * assembled each step into ELL-like storage and then applied as a sparse
  * matrix-vector product, the paper's own GPU formulation (Section 3.2.1).
  * Internally each row is stored as the dense box of nodes its landing cells
- * can cover (columns implicit in the box origin); fk_export_ell writes the
+ * can cover (columns implicit in the box origin), its values in 16-byte
+ * blocks of consecutive box nodes of one field; fk_export_ell writes the
  * plain (column, value) layout. */
 enum { FK_FORM_FUSED = 0, FK_FORM_ELL = 1 };
 
@@ -140,7 +141,7 @@ typedef struct {
     int64_t n_active;       /* active nodes of all instances */
     int64_t ell_width;      /* ELL row width (FK_FORM_ELL), else 0; the widest instance */
     size_t workspace_bytes;
-    int64_t ell_entries;    /* stored ELL entries, sum over instances of width x active rows */
+    int64_t ell_entries;    /* ELL entries, sum over instances of width x active rows (block padding not counted) */
     int64_t adj_point_nodes;  /* adjoint (ckpt_every > 0): active nodes transposed per landing point */
     int64_t adj_box_nodes;    /* adjoint: active nodes transposed in separable box form */
 } fk_plan_info;

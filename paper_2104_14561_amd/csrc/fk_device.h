@@ -1174,6 +1174,13 @@ __device__ inline void lds_add(double *p, double v)
 // (u^n_j = exit_mass + A_j [u; g]); the product evaluates it in the same offset
 // form as the fused pass.
 // ---------------------------------------------------------------------------
+// 16 bytes of consecutive box nodes of one field of one row
+template <typename T>
+struct alignas(16) EllBlock {
+    static constexpr int K = 16 / sizeof(T);
+    T v[K];
+};
+
 template <typename T, int D, int G>
 __global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n, int *__restrict__ org,
                                                          T *__restrict__ vals,
@@ -1252,19 +1259,24 @@ __global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n, int *
             for (int a = 0; a < 3; ++a) org[row * 3 + a] = a < D ? origin[a] : 0;
             exit_mass[row] = em;
         }
-        // the workgroup's rows are consecutive: write entry k of all of them
-        // together (column-major within the instance: k * rows + r), value f
-        // of box node l at k = f * nbox + l
+        // the workgroup's rows are consecutive: write block b of all of them
+        // together.  Block b = f * (nbp / K) + l / K holds value f of box nodes
+        // l .. l + K - 1 and sits at (b * rows + r) * K within the instance
+        // (blocks of one index are contiguous across rows); padding nodes
+        // (l >= nbox) hold 0
         {
+            constexpr int K = EllBlock<T>::K;
             const int nrow = it.count;
             const int nbox = W / (D + 1);
+            const int bpf = I.ell_nbp / K;   // blocks per field
             const long long rows = I.n_act;
             const long long r0 = it.first;
-            for (int e = threadIdx.x; e < nrow * W; e += blockDim.x) {
-                const int k = e / nrow, rr = e - k * nrow;
-                const int f = k / nbox, l = k - f * nbox;
-                vals[I.ell_off + (long long)k * rows + r0 + rr] =
-                    (T)box[(long long)rr * P.ell_width + l * (D + 1) + f];
+            for (int e = threadIdx.x; e < nrow * (D + 1) * bpf * K; e += blockDim.x) {
+                const int j = e % K, rest = e / K;
+                const int rr = rest % nrow, b = rest / nrow;
+                const int f = b / bpf, l = (b - f * bpf) * K + j;
+                const T v = l < nbox ? (T)box[(long long)rr * P.ell_width + l * (D + 1) + f] : T(0);
+                vals[I.ell_off + ((long long)b * rows + r0 + rr) * K + j] = v;
             }
         }
         __syncthreads();
@@ -1273,8 +1285,9 @@ __global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n, int *
 
 // Box-row product, one row per lane: the row walks its box nodes in order
 // (coordinates advanced incrementally), gathering one node record per box
-// node and its (d+1) values, which sit column-major across the rows of the
-// instance so that every value load of a wave is contiguous:
+// node, and reads its values a 16-byte block (K box nodes of one field) at a
+// time; blocks of one index are contiguous across the rows of the instance,
+// so a wave's block load is 1 KB in one piece:
 //   u^n[row] = uref + exit_mass[row] (1 - uref) + sum_box (v_u (u - uref) + sum_a v_a g_a),
 // i.e. exit_mass + A [u; g] in offset form about uref = u^{n+1}[row].
 template <typename T, int D>
@@ -1292,8 +1305,6 @@ __global__ void __launch_bounds__(kBlock) k_ell_apply(PlanDev P, const int *__re
         const WorkItem it = P.row_work[w];
         if ((int)threadIdx.x >= it.count) continue;
         const DevInst &I = P.inst[it.inst];
-        const int W = I.ell_w;
-        const int nbox = W / (D + 1);
         const long long rows = I.n_act;
         const long long r = it.first + threadIdx.x;
         const long long row = I.act_off + r;
@@ -1301,34 +1312,44 @@ __global__ void __launch_bounds__(kBlock) k_ell_apply(PlanDev P, const int *__re
         const T uref = rec[I.node_off + node].x;
         int o[3] = {0, 0, 0};
         for (int a = 0; a < D; ++a) o[a] = org[row * 3 + a];
-        const T *v0 = vals + I.ell_off + r;
-        const long long fs = (long long)nbox * rows;   // stride between field planes
+        constexpr int K = EllBlock<T>::K;
+        using B = EllBlock<T>;
+        const int bpf = I.ell_nbp / K;
+        const B *v0 = reinterpret_cast<const B *>(vals + I.ell_off) + r;
+        const long long fs = (long long)bpf * rows;   // stride between field planes, in blocks
         T acc = exit_mass[row] * (T(1) - uref);
         int bi[3] = {0, 0, 0};
-        // independent gathers of several box nodes in flight per lane
-#pragma unroll 4
-        for (int l = 0; l < nbox; ++l) {
-            long long nd = I.node_off;
+        for (int lb = 0; lb < bpf; ++lb) {
+            const B *vp = v0 + (long long)lb * rows;
+            B vf[D + 1];
 #pragma unroll
-            for (int a = 0; a < D; ++a) {
-                int ia = o[a] + bi[a];
-                if (ia > I.n[a] - 1) ia = I.n[a] - 1;   // zero-valued padding stays in range
-                nd += (long long)ia * I.stride[a];
-            }
-            const R rc = rec[nd];
-            const T *v = v0 + (long long)l * rows;
-            if constexpr (D == 1) {
-                acc += v[0] * (rc.x - uref) + v[fs] * rc.y;
-            } else if constexpr (D == 2) {
-                acc += v[0] * (rc.x - uref) + v[fs] * rc.y + v[2 * fs] * rc.z;
-            } else {
-                acc += v[0] * (rc.x - uref) + v[fs] * rc.y + v[2 * fs] * rc.z + v[3 * fs] * rc.w;
-            }
-            // next box node (last axis fastest)
+            for (int f = 0; f <= D; ++f) vf[f] = vp[f * fs];
+            // K independent gathers in flight per lane; past the last box node
+            // the coordinates wrap to the origin (padding values are 0)
 #pragma unroll
-            for (int a = D - 1; a >= 0; --a) {
-                if (++bi[a] < I.ell_box[a]) break;
-                bi[a] = 0;
+            for (int j = 0; j < K; ++j) {
+                long long nd = I.node_off;
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    int ia = o[a] + bi[a];
+                    if (ia > I.n[a] - 1) ia = I.n[a] - 1;   // zero-valued box nodes stay in range
+                    nd += (long long)ia * I.stride[a];
+                }
+                const R rc = rec[nd];
+                if constexpr (D == 1) {
+                    acc += vf[0].v[j] * (rc.x - uref) + vf[1].v[j] * rc.y;
+                } else if constexpr (D == 2) {
+                    acc += vf[0].v[j] * (rc.x - uref) + vf[1].v[j] * rc.y + vf[2].v[j] * rc.z;
+                } else {
+                    acc += vf[0].v[j] * (rc.x - uref) + vf[1].v[j] * rc.y + vf[2].v[j] * rc.z +
+                           vf[3].v[j] * rc.w;
+                }
+                // next box node (last axis fastest)
+#pragma unroll
+                for (int a = D - 1; a >= 0; --a) {
+                    if (++bi[a] < I.ell_box[a]) break;
+                    bi[a] = 0;
+                }
             }
         }
         int idx[3];
@@ -1373,8 +1394,11 @@ __global__ void __launch_bounds__(kBlock) k_export_ell(PlanDev P, const int *org
                 if (ia > I.n[a] - 1) ia = I.n[a] - 1;
                 nd += (long long)ia * I.stride[a];
             }
+            constexpr int K = EllBlock<T>::K;
+            const int l = k - f * nbox;
+            const long long blk = (long long)f * (I.ell_nbp / K) + l / K;
             cols_out[t] = (int)(nd * (D + 1) + f);
-            vals_out[t] = vals_in[I.ell_off + (long long)k * I.n_act + r];
+            vals_out[t] = vals_in[I.ell_off + (blk * I.n_act + r) * K + l % K];
         } else {
             cols_out[t] = (int)((I.node_off + P.active[row]) * (D + 1));
             vals_out[t] = T(0);

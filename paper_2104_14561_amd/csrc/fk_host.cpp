@@ -177,7 +177,8 @@ struct fk_plan {
     long long n_nodes = 0, n_active = 0;
     int ell_box[3] = {1, 1, 1};
     int ell_width = 0;
-    long long ell_total = 0;
+    long long ell_total = 0;     // stored values, with block padding
+    long long ell_entries = 0;   // width x active rows, summed over instances
     // measurement: when prof is set, fk_adjoint records a HIP event after
     // every kernel group (kind >= 0) or before one (kind -1)
     std::vector<std::pair<hipEvent_t, int>> *prof = nullptr;
@@ -374,7 +375,7 @@ fk_status build_plan(fk_plan *p)
 
     const int npb = kBlock / p->G;
     std::vector<fk::WorkItem> tables, runs;
-    long long ell_total = 0, ell_wmax = 0;
+    long long ell_total = 0, ell_wmax = 0, ell_rows_w = 0;
     std::vector<std::vector<int>> inst_sep, inst_rest;
     std::vector<int> inst_cls, inst_lneed;
     std::vector<std::vector<unsigned char>> inst_inner;   // per node: no landing point can exit
@@ -581,9 +582,16 @@ fk_status build_plan(fk_plan *p)
                 Wi *= L;
             }
             for (int a = pr.d; a < 3; ++a) p->inst.back().ell_box[a] = 1;
+            // values are stored in 16-byte blocks of consecutive box nodes of
+            // one field (4 in FP32, 2 in FP64); the box is padded to whole blocks
+            const long long KB = p->opt.precision == FK_PREC_F32 ? 4 : 2;
+            const long long nbox = Wi / (pr.d + 1);
+            const long long nbp = (nbox + KB - 1) / KB * KB;
             p->inst.back().ell_w = (int)Wi;
+            p->inst.back().ell_nbp = (int)nbp;
             p->inst.back().ell_off = ell_total;
-            ell_total += Wi * na;
+            ell_total += (pr.d + 1) * nbp * na;
+            ell_rows_w += Wi * na;
             ell_wmax = std::max(ell_wmax, Wi);
         }
     }
@@ -817,6 +825,7 @@ fk_status build_plan(fk_plan *p)
             return fail(FK_ERR_UNSUPPORTED, "ELL row box too large for LDS (%lld entries)", W);
         p->ell_width = (int)W;
         p->ell_total = ell_total;
+        p->ell_entries = ell_rows_w;
     }
 
     // workspace layout
@@ -1164,7 +1173,7 @@ fk_status fk_plan_get_info(const fk_plan *p, fk_plan_info *info)
     info->n_nodes = p->n_nodes;
     info->n_active = p->n_active;
     info->ell_width = p->ell_width;
-    info->ell_entries = p->opt.form == FK_FORM_ELL ? p->ell_total : 0;
+    info->ell_entries = p->opt.form == FK_FORM_ELL ? p->ell_entries : 0;
     info->adj_point_nodes = (int64_t)p->adj.fw_nodes.size();
     info->adj_box_nodes = (int64_t)p->adj.box_nodes.size();
     info->workspace_bytes = p->ws_bytes;

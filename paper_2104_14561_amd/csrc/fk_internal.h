@@ -35,9 +35,12 @@ struct DevInst {
     double r2;
     double S;       // sqrt(2 D) * sqrt(2 dt)
     double dSdD;    // S / (2 D)  (adjoint)
-    // assembled (ELL) form: this instance's row box, width and storage offset
+    // assembled (ELL) form: this instance's row box, width (box nodes x
+    // (d + 1) fields), box nodes per field padded to whole 16-byte blocks,
+    // and storage offset
     int ell_box[kMaxDim];
     int ell_w;
+    int ell_nbp;
     long long ell_off;
 };
 
