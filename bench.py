@@ -171,6 +171,31 @@ def event_time(fn, k: int, stream):
     return e0.elapsed_time(e1) / k, out
 
 
+def ell_batched(probs, stream):
+    """Assembled ELL form on the batch: a shortened pass (every step costs the
+    same), its rate and the HBM roofline of the product."""
+    import torch
+    from paper_2104_14561_amd import Plan
+    n_ell = 50
+    pb = Plan([p.replace(n_steps=n_ell) for p in probs], precision="f32", form="ell",
+              use_graph=True)
+    Ja = sum(pb.active_count)
+    pb.forward([0])
+    torch.cuda.synchronize()
+    ms_eb, _ = event_time(lambda: pb.forward([0]), 1, stream)
+    ppb = pb.profile_pass()
+    roof = ell_roofline(pb, ppb["ell_apply"][0])
+    roof["traffic"] = measured_traffic("void k_ell_apply<float, 2>")
+    out = {"workload": f"cell2d_batch64, first {n_ell} steps, FP32, A_n assembled each step "
+                       "(one dense node box per row, per-instance width, values in 16-byte "
+                       "blocks of box nodes per field)",
+           "gp_steps_per_s": Ja * n_ell / (ms_eb * 1e-3),
+           "kernels_ms": {k: v[0] for k, v in ppb.items() if v[1]},
+           "roofline_ell_apply": roof}
+    pb.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,13 +204,16 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="headline line only")
+    ap.add_argument("--ell-only", action="store_true",
+                    help="only the assembled (ELL) form on the batch, as its own JSON line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device-to-device once (a kernel of known traffic "
                          "that scales the HBM byte counters of a profiled run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(sharding by instance is described in DESIGN.md)", file=sys.stderr)
+              "(the instances are independent and would be sharded over GPUs by cost)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -207,6 +235,9 @@ def main():
     probs = W.cell2d_batch()
     N = probs[0].n_steps
     log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)  # noqa: E731
+    if args.ell_only:
+        print(json.dumps({"ell_batched": ell_batched(probs, stream)}), flush=True)
+        return
     log(f"workload cell2d_batch64: {len(probs)} instances, N={N}, FP32 apply, forward + adjoint")
 
     # the smallest checkpoint interval whose storage fits half of free HBM
@@ -335,7 +366,7 @@ def main():
                 "max": float(errs.max()), "median": float(np.median(errs)),
                 "instances_within_1e-5": int((errs <= 1e-5).sum()), "instances": len(errs),
                 "note": "instances beyond 1e-5 are the coarse, advection-dominated ones whose "
-                        "FP64 scheme amplifies any perturbation (see DESIGN.md, conditioning)"},
+                        "FP64 scheme amplifies any perturbation (conditioning of the scheme)"},
             "f32_vs_f64_grad": {
                 "max_abs_diff": float(gabs.max()), "median_abs_diff": float(np.median(gabs)),
                 "rel_diff_where_norm_ge_1e-3": {"max": float(max(big)), "median": float(np.median(big)),
@@ -346,22 +377,7 @@ def main():
             f"u0 diff max {errs.max():.2e} median {np.median(errs):.2e}, "
             f"grad abs diff max {gabs.max():.2e}, rel (norm >= 1e-3) median {np.median(big):.2e}")
 
-        # assembled ELL form on the batch (HBM roofline of the product; a
-        # shortened pass: every step costs the same)
-        n_ell = 50
-        pb = Plan([p.replace(n_steps=n_ell) for p in probs], precision="f32", form="ell",
-                  use_graph=True)
-        pb.forward([0])
-        torch.cuda.synchronize()
-        ms_eb, _ = event_time(lambda: pb.forward([0]), 1, stream)
-        ppb = pb.profile_pass()
-        result["ell_batched"] = {
-            "workload": f"cell2d_batch64, first {n_ell} steps, FP32, A_n assembled each step "
-                        f"(one dense node box per row, per-instance width, values in 16-byte blocks of box nodes per field)",
-            "gp_steps_per_s": Ja * n_ell / (ms_eb * 1e-3),
-            "kernels_ms": {k: v[0] for k, v in ppb.items() if v[1]},
-            "roofline_ell_apply": ell_roofline(pb, ppb["ell_apply"][0])}
-        pb.close()
+        result["ell_batched"] = ell_batched(probs, stream)
         log(f"ELL batched: {result['ell_batched']['gp_steps_per_s']:.4e} gp-steps/s, apply "
             f"{result['ell_batched']['roofline_ell_apply']['achieved']} GB/s")
 
