@@ -176,6 +176,57 @@ def test_ell_rows_match_oracle_rows():
     plan.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["batch2d", "bm1d", "const3d"])
+def test_ell_form_other_shapes(case, prec):
+    """Assembled form on a batch of uneven grids (per-instance box widths,
+    block padding and storage offsets), in 1D and in 3D."""
+    if case == "batch2d":
+        probs = W.cell2d_batch(n_inst=4, n_steps=10, max_m=3)
+    elif case == "bm1d":
+        probs = [W.bm1d(n=101, n_steps=20, gh_q=7)]
+    else:
+        probs = [W.Problem(axes=[W.uniform_axis(0, 1, 13), W.uniform_axis(0, 1, 11),
+                                 W.uniform_axis(-1, 1, 17)],
+                           coef_kind="const", coef=(0.3, -0.2, 0.1), D=4e-3, region_kind="box",
+                           gh_q=3, dt=0.02, n_steps=6)]
+    N = probs[0].n_steps
+    a = _run(probs, prec, [0, N // 2], form="ell", use_graph=True)
+    b = _run(probs, prec, [0, N // 2], form="fused", use_graph=True)
+    for p, ga, gb in zip(probs, a, b):
+        ref = oracle.solve(p, snaps=[0, N // 2])
+        assert _maxerr(ga, gb) <= (1e-13 if prec == "f64" else 2e-6)
+        assert _maxerr(ga, ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_ell_export_batched_rows_match_oracle(prec):
+    """fk_export_ell over two instances of different box widths: every
+    sampled row of each instance equals the oracle's dense row of A_n."""
+    probs = [W.cell2d(nx=65, ny=33, n_steps=4, D=4e-3, radius=0.4),
+             W.cell2d(nx=97, ny=49, n_steps=4, D=1e-3, radius=0.35)]
+    plan = Plan(probs, precision=prec, form="ell")
+    cols, vals, em = plan.export_ell(2)
+    torch.cuda.synchronize()
+    cols, vals, em = cols.cpu().numpy(), vals.double().cpu().numpy(), em.double().cpu().numpy()
+    tol = 1e-14 if prec == "f64" else 1e-6
+    row0 = 0
+    for i, prob in enumerate(probs):
+        act = oracle.active_nodes(prob)
+        J = prob.n_nodes
+        base = plan.node_offset[i]
+        for r in range(0, len(act), 41):
+            row, emr = oracle.assemble_row(prob, 2, int(act[r]))
+            dense = np.zeros(3 * J)
+            c = cols[:, row0 + r] - 3 * base
+            assert np.all((c >= 0) & (c < 3 * J))
+            np.add.at(dense, c, vals[:, row0 + r])
+            assert np.abs(dense - row.T.reshape(-1)).max() <= tol
+            assert abs(emr - em[row0 + r]) <= tol
+        row0 += len(act)
+    plan.close()
+
+
 def test_graph_replay_matches_eager():
     prob = W.cell2d(nx=97, ny=49, n_steps=40, D=2e-3)
     eager = _run(prob, "f64", [0, 20])[0]
