@@ -1182,7 +1182,10 @@ struct alignas(16) EllBlock {
 };
 
 template <typename T, int D, int G>
-__global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n, int *__restrict__ org,
+__global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n,
+                                                         const WorkItem *__restrict__ work,
+                                                         int n_work, int bstride,
+                                                         int *__restrict__ org,
                                                          T *__restrict__ vals,
                                                          T *__restrict__ exit_mass)
 {
@@ -1192,13 +1195,13 @@ __global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n, int *
     const T *Wq = weights<T>(P);
     const int lane = threadIdx.x % G;
     const int slot = threadIdx.x / G;
-    const WorkRange wr = work_range(0, P.n_act_work);
+    const WorkRange wr = work_range(0, n_work);
     for (int w = wr.begin; w < wr.end; w += wr.step) {
-        const WorkItem it = P.act_work[w];
+        const WorkItem it = work[w];
         const bool valid = slot < it.count;
         const DevInst &I = P.inst[it.inst];
-        const int W = I.ell_w;
-        double *mybox = box + (long long)slot * P.ell_width;
+        const int W = I.ell_w;   // <= bstride, the launch's row-box stride
+        double *mybox = box + (long long)slot * bstride;
         for (int k = lane; k < W; k += G) mybox[k] = 0.0;
         __syncthreads();
         int idx[3] = {0, 0, 0};
@@ -1275,7 +1278,7 @@ __global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n, int *
                 const int j = e % K, rest = e / K;
                 const int rr = rest % nrow, b = rest / nrow;
                 const int f = b / bpf, l = (b - f * bpf) * K + j;
-                const T v = l < nbox ? (T)box[(long long)rr * P.ell_width + l * (D + 1) + f] : T(0);
+                const T v = l < nbox ? (T)box[(long long)rr * bstride + l * (D + 1) + f] : T(0);
                 vals[I.ell_off + ((long long)b * rows + r0 + rr) * K + j] = v;
             }
         }

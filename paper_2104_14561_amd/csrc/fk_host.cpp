@@ -158,6 +158,10 @@ struct fk_plan {
     std::vector<float> gh_wf, gh_w1f;
     std::vector<double> tfac;
     std::vector<fk::WorkItem> slope_work, node_work, act_work, row_work, split_work;
+    std::vector<fk::WorkItem> ell_work;   // act_work by ELL width class
+    int n_ell_cls = 0;
+    int ell_cls_off[fk::kEllClasses] = {}, ell_cls_n[fk::kEllClasses] = {},
+        ell_cls_w[fk::kEllClasses] = {};
     int tile_elems = 0;
     // adjoint step lists (per-node form and box form by class) with LDS tiles
     struct {
@@ -826,6 +830,32 @@ fk_status build_plan(fk_plan *p)
         p->ell_width = (int)W;
         p->ell_total = ell_total;
         p->ell_entries = ell_rows_w;
+        // width classes: bounds 128, 256, ... entries, the last one the widest row
+        int bound[fk::kEllClasses];
+        int nc = 0;
+        for (long long bnd = 128; nc < fk::kEllClasses - 1 && bnd < W; bnd *= 2) bound[nc++] = (int)bnd;
+        bound[nc++] = (int)W;
+        std::vector<std::vector<fk::WorkItem>> by(nc);
+        for (const fk::WorkItem &it : p->act_work) {
+            const int w = p->inst[it.inst].ell_w;
+            int c = 0;
+            while (bound[c] < w) ++c;
+            by[c].push_back(it);
+        }
+        p->ell_work.clear();
+        p->n_ell_cls = 0;
+        for (int c = nc - 1; c >= 0; --c) {   // widest class first
+            if (by[c].empty()) continue;
+            const int k = p->n_ell_cls++;
+            p->ell_cls_off[k] = (int)p->ell_work.size();
+            p->ell_cls_n[k] = (int)by[c].size();
+            int wmax = 0;
+            for (const fk::WorkItem &it : by[c]) wmax = std::max(wmax, p->inst[it.inst].ell_w);
+            p->ell_cls_w[k] = wmax;
+            p->ell_work.insert(p->ell_work.end(), by[c].begin(), by[c].end());
+        }
+        // (the product keeps the instance order: sorted by width, the XCDs'
+        // contiguous shares of one launch would be far from equal in work)
     }
 
     // workspace layout
@@ -844,6 +874,7 @@ fk_status build_plan(fk_plan *p)
     add_region(p, "slope_work", sizeof(fk::WorkItem) * std::max<size_t>(p->slope_work.size(), 1));
     add_region(p, "node_work", sizeof(fk::WorkItem) * std::max<size_t>(p->node_work.size(), 1));
     add_region(p, "act_work", sizeof(fk::WorkItem) * std::max<size_t>(p->act_work.size(), 1));
+    add_region(p, "ell_work", sizeof(fk::WorkItem) * std::max<size_t>(p->ell_work.size(), 1));
     add_region(p, "row_work", sizeof(fk::WorkItem) * std::max<size_t>(p->row_work.size(), 1));
     add_region(p, "split_work", sizeof(fk::WorkItem) * std::max<size_t>(p->split_work.size(), 1));
     add_region(p, "afw_nodes", sizeof(int) * std::max<size_t>(p->adj.fw_nodes.size(), 1));
@@ -898,6 +929,14 @@ void fill_dev(fk_plan *p)
     D.slope_work = (const fk::WorkItem *)p->at("slope_work");
     D.node_work = (const fk::WorkItem *)p->at("node_work");
     D.act_work = (const fk::WorkItem *)p->at("act_work");
+    D.ell_work = (const fk::WorkItem *)p->at("ell_work");
+    D.n_ell_cls = p->n_ell_cls;
+    for (int c = 0; c < fk::kEllClasses; ++c) {
+        D.ell_cls_off[c] = p->ell_cls_off[c];
+        D.ell_cls_n[c] = p->ell_cls_n[c];
+        D.ell_cls_w[c] = p->ell_cls_w[c];
+        D.ell_cls_grid[c] = grid_for(p->ell_cls_n[c]);
+    }
     D.row_work = (const fk::WorkItem *)p->at("row_work");
     D.split_work = (const fk::WorkItem *)p->at("split_work");
     D.adj.fw_nodes = (const int *)p->at("afw_nodes");
@@ -1223,6 +1262,7 @@ fk_status fk_plan_set_workspace(fk_plan *p, void *dev_ptr, size_t bytes, void *s
     FK_TRY(up("slope_work", p->slope_work.data(), sizeof(fk::WorkItem) * p->slope_work.size()));
     FK_TRY(up("node_work", p->node_work.data(), sizeof(fk::WorkItem) * p->node_work.size()));
     FK_TRY(up("act_work", p->act_work.data(), sizeof(fk::WorkItem) * p->act_work.size()));
+    FK_TRY(up("ell_work", p->ell_work.data(), sizeof(fk::WorkItem) * p->ell_work.size()));
     FK_TRY(up("row_work", p->row_work.data(), sizeof(fk::WorkItem) * p->row_work.size()));
     FK_TRY(up("split_work", p->split_work.data(), sizeof(fk::WorkItem) * p->split_work.size()));
     FK_TRY(up("afw_nodes", p->adj.fw_nodes.data(), sizeof(int) * p->adj.fw_nodes.size()));

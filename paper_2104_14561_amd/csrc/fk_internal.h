@@ -47,6 +47,8 @@ struct DevInst {
 // A contiguous chunk of one instance's nodes (slope pass) or active nodes
 // (step pass) handled by one workgroup.  kind 0: nodes first .. first+count-1;
 // kind 1 + a: entries of the trig table of axis a.
+constexpr int kEllClasses = 8;   // ELL assembly width classes
+
 struct WorkItem {
     int inst;
     int first;
@@ -142,6 +144,14 @@ struct PlanDev {
     int ell_width;
     int ell_box[kMaxDim];
     int ell_grid;
+    // assembly work by row-width class: the LDS row boxes of a launch are
+    // sized by its class's widest row, not by the widest row of the plan
+    const WorkItem *ell_work;
+    int n_ell_cls;
+    int ell_cls_off[kEllClasses];
+    int ell_cls_n[kEllClasses];
+    int ell_cls_w[kEllClasses];
+    int ell_cls_grid[kEllClasses];
 };
 
 // Kernel launchers (fk_launch.hip).  T is double or float; all return the

@@ -103,11 +103,18 @@ hipError_t launch_step_fused(const PlanDev &P, bool f32, int n, const void *pack
 hipError_t launch_assemble_ell(const PlanDev &P, bool f32, int n, int *org, void *vals,
                                void *exit_mass, hipStream_t s)
 {
-    const size_t lds = (size_t)(kBlock / P.group) * P.ell_width * sizeof(double);   // FP64 row boxes
-    FK_DISPATCH_D(P.d, FK_DISPATCH_G(P.group,
-        if (f32) k_assemble_ell<float, D, G><<<P.act_grid, kBlock, lds, s>>>(P, n, org, (float *)vals, (float *)exit_mass);
-        else k_assemble_ell<double, D, G><<<P.act_grid, kBlock, lds, s>>>(P, n, org, (double *)vals, (double *)exit_mass)));
-    return hipGetLastError();
+    // one launch per row-width class, its FP64 row boxes sized by the class
+    for (int c = 0; c < P.n_ell_cls; ++c) {
+        const WorkItem *work = P.ell_work + P.ell_cls_off[c];
+        const int nw = P.ell_cls_n[c], bw = P.ell_cls_w[c], grid = P.ell_cls_grid[c];
+        const size_t lds = (size_t)(kBlock / P.group) * bw * sizeof(double);
+        FK_DISPATCH_D(P.d, FK_DISPATCH_G(P.group,
+            if (f32) k_assemble_ell<float, D, G><<<grid, kBlock, lds, s>>>(P, n, work, nw, bw, org, (float *)vals, (float *)exit_mass);
+            else k_assemble_ell<double, D, G><<<grid, kBlock, lds, s>>>(P, n, work, nw, bw, org, (double *)vals, (double *)exit_mass)));
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_ell_apply(const PlanDev &P, bool f32, const int *org, const void *vals,
