@@ -1274,12 +1274,29 @@ __global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n,
             const int bpf = I.ell_nbp / K;   // blocks per field
             const long long rows = I.n_act;
             const long long r0 = it.first;
-            for (int e = threadIdx.x; e < nrow * (D + 1) * bpf * K; e += blockDim.x) {
-                const int j = e % K, rest = e / K;
-                const int rr = rest % nrow, b = rest / nrow;
-                const int f = b / bpf, l = (b - f * bpf) * K + j;
-                const T v = l < nbox ? (T)box[(long long)rr * bstride + l * (D + 1) + f] : T(0);
-                vals[I.ell_off + ((long long)b * rows + r0 + rr) * K + j] = v;
+            // a thread keeps one (row, entry-in-block) pair and walks the blocks
+            // with a fixed stride (no division per entry); G >= 4 lanes per row
+            // bound nrow by blockDim / 4, so per <= blockDim and nb >= 1
+            const int per = nrow * K;                    // entries of one block index
+            const int nb = (int)blockDim.x / per;        // block indices per sweep
+            const int t = threadIdx.x;
+            if (nrow > 0 && t < nb * per) {
+                const int rr = (t % per) / K, j = t % K;
+                const int nblk = (D + 1) * bpf;
+                int b = t / per;
+                int f = b / bpf, lb = b - f * bpf;
+                T *dst = vals + I.ell_off + (r0 + rr) * K + j;
+                const double *src = box + (long long)rr * bstride + f;
+                for (; b < nblk; b += nb) {
+                    const int l = lb * K + j;
+                    dst[(long long)b * rows * K] = l < nbox ? (T)src[l * (D + 1)] : T(0);
+                    lb += nb;
+                    while (lb >= bpf) {
+                        lb -= bpf;
+                        ++f;
+                        ++src;
+                    }
+                }
             }
         }
         __syncthreads();
