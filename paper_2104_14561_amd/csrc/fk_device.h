@@ -1303,6 +1303,106 @@ __global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n,
     }
 }
 
+// Assembly of separable rows (no landing point can reach a curved exit
+// boundary; exits through the faces of a box region decide per axis): the
+// row is the outer product of per-axis vectors, the value and slope bases of
+// that axis summed with its 1D weights over the GH nodes that stay inside, so
+// it is written directly, with no LDS atomics.  One thread per row builds its
+// vectors in LDS (thread-minor, conflict-free), then writes its 16-byte
+// blocks: a wave's stores of one block index are 1 KB in one piece.  The exit
+// mass is accumulated axis by axis, exactly 0 when nothing leaves.
+template <typename T, int D>
+__global__ void __launch_bounds__(64) k_assemble_ell_sep(PlanDev P, int n,
+                                                         const WorkItem *__restrict__ work,
+                                                         int n_work, int lmax,
+                                                         int *__restrict__ org,
+                                                         T *__restrict__ vals,
+                                                         T *__restrict__ exit_mass)
+{
+    constexpr int K = EllBlock<T>::K;
+    using B = EllBlock<T>;
+    extern __shared__ unsigned char smem_raw[];
+    T *vec = reinterpret_cast<T *>(smem_raw);   // [D][value, slope][lmax][64]
+    const T *w1 = weights1<T>(P);
+    const int t = threadIdx.x;
+    auto V = [&](int a, int v, int l) -> T & { return vec[((a * 2 + v) * lmax + l) * 64 + t]; };
+    const WorkRange wr = work_range(0, n_work);
+    for (int w = wr.begin; w < wr.end; w += wr.step) {
+        const WorkItem it = work[w];
+        if (t >= it.count) continue;   // rows are independent: no barrier below
+        const DevInst &I = P.inst[it.inst];
+        const long long r = it.first + t;   // row within the instance
+        const long long row = I.act_off + r;
+        const int node = P.active[row];
+        int idx[3];
+        split_node<D>(I, node, idx);
+        double c[3];
+        node_centre<D>(I, P.coords, time_factors(P, n, it.inst), P.trig, idx, P.dt, c);
+        int origin[3] = {0, 0, 0};
+        T em = T(0), in_all = T(1);
+        for (int a = 0; a < D; ++a) {
+            const int L = I.ell_box[a];
+            for (int l = 0; l < L; ++l) {
+                V(a, 0, l) = T(0);
+                V(a, 1, l) = T(0);
+            }
+            origin[a] = eval_axis(I, P.coords, a, c[a], P.gh_a[0]).k;
+            T in_a = T(0), out_a = T(0);
+            for (int q = 0; q < P.qs; ++q) {
+                const AxisEval e = eval_axis(I, P.coords, a, c[a], P.gh_a[q]);
+                const T wq = w1[q];
+                if (e.ex) {
+                    out_a += wq;
+                    continue;
+                }
+                const int l = e.k - origin[a];
+                if (l < 0 || l + 1 >= L) {
+                    atomicOr(P.flags, 2);
+                    continue;
+                }
+                const Basis<T> Bq = hermite<T>(e.s, e.h);
+                V(a, 0, l) += wq * Bq.v0;
+                V(a, 0, l + 1) += wq * Bq.v1;
+                V(a, 1, l) += wq * Bq.d0;
+                V(a, 1, l + 1) += wq * Bq.d1;
+                in_a += wq;
+            }
+            // mass of the tensor points with some axis outside, over axes 0..a
+            em = em * (in_a + out_a) + in_all * out_a;
+            in_all *= in_a;
+        }
+        for (int a = 0; a < 3; ++a) org[row * 3 + a] = a < D ? origin[a] : 0;
+        exit_mass[row] = em;
+        // blocks: field f (0 value, 1 + a slope along a), K box nodes each,
+        // box nodes in order with the last axis fastest; padding nodes hold 0
+        const int nbox = I.ell_w / (D + 1);
+        const int bpf = I.ell_nbp / K;
+        const long long rows = I.n_act;
+        B *dst = reinterpret_cast<B *>(vals + I.ell_off) + r;
+        for (int f = 0; f <= D; ++f) {
+            int li[3] = {0, 0, 0};
+            int l = 0;
+            for (int lb = 0; lb < bpf; ++lb) {
+                B blk;
+#pragma unroll
+                for (int j = 0; j < K; ++j, ++l) {
+                    T v = T(0);
+                    if (l < nbox) {
+                        v = T(1);
+                        for (int a = 0; a < D; ++a) v *= V(a, f == a + 1 ? 1 : 0, li[a]);
+                        for (int a = D - 1; a >= 0; --a) {
+                            if (++li[a] < I.ell_box[a]) break;
+                            li[a] = 0;
+                        }
+                    }
+                    blk.v[j] = v;
+                }
+                dst[((long long)f * bpf + lb) * rows] = blk;
+            }
+        }
+    }
+}
+
 // Box-row product, one row per lane: the row walks its box nodes in order
 // (coordinates advanced incrementally), gathering one node record per box
 // node, and reads its values a 16-byte block (K box nodes of one field) at a

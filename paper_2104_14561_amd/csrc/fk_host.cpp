@@ -158,7 +158,9 @@ struct fk_plan {
     std::vector<float> gh_wf, gh_w1f;
     std::vector<double> tfac;
     std::vector<fk::WorkItem> slope_work, node_work, act_work, row_work, split_work;
-    std::vector<fk::WorkItem> ell_work;   // act_work by ELL width class
+    std::vector<fk::WorkItem> ell_work;   // non-separable ELL rows by width class
+    std::vector<fk::WorkItem> ell_sep_work;   // separable ELL rows, runs of up to 64
+    int ell_lmax = 1;                     // longest row box axis
     int n_ell_cls = 0;
     int ell_cls_off[fk::kEllClasses] = {}, ell_cls_n[fk::kEllClasses] = {},
         ell_cls_w[fk::kEllClasses] = {};
@@ -383,6 +385,7 @@ fk_status build_plan(fk_plan *p)
     std::vector<std::vector<int>> inst_sep, inst_rest;
     std::vector<int> inst_cls, inst_lneed;
     std::vector<std::vector<unsigned char>> inst_inner;   // per node: no landing point can exit
+    std::vector<std::vector<unsigned char>> inst_seprow;  // per active row: separable
     std::vector<std::array<int, 3>> inst_dils;
     p->node_off.assign(p->n_inst + 1, 0);
     p->act_count.assign(p->n_inst, 0);
@@ -531,6 +534,7 @@ fk_status build_plan(fk_plan *p)
                 if (Lneed <= kL[c2]) { cls_box = c2; break; }
             std::vector<int> sep, rest;
             std::vector<unsigned char> inner(J, 0);
+            std::vector<unsigned char> seprow(na, 0);
             double reach_a[3] = {0, 0, 0};
             for (int a = 0; a < pr.d; ++a) reach_a[a] = drift_bound(pr, a) * pr.dt + I.S * amax;
             for (int t = 0; t < na; ++t) {
@@ -558,9 +562,11 @@ fk_status build_plan(fk_plan *p)
                     interior = interior && separable;
                 }
                 inner[j] = interior ? 1 : 0;
+                seprow[t] = separable ? 1 : 0;
                 (separable ? sep : rest).push_back(j);
             }
             inst_inner.push_back(std::move(inner));
+            inst_seprow.push_back(std::move(seprow));
             inst_sep.push_back(sep);
             inst_rest.push_back(rest);
             inst_cls.push_back(cls_box);
@@ -835,8 +841,37 @@ fk_status build_plan(fk_plan *p)
         int nc = 0;
         for (long long bnd = 128; nc < fk::kEllClasses - 1 && bnd < W; bnd *= 2) bound[nc++] = (int)bnd;
         bound[nc++] = (int)W;
+        // separable rows go to the direct (outer-product) assembly in runs of
+        // up to 64 consecutive rows; the others to the LDS-box assembly in
+        // runs of up to block / G rows
+        std::vector<fk::WorkItem> rest_work;
+        p->ell_sep_work.clear();
+        p->ell_lmax = 1;
+        for (int a = 0; a < p->d; ++a) p->ell_lmax = std::max(p->ell_lmax, p->ell_box[a]);
+        // its per-thread axis vectors (d x 2 x lmax, 64 rows) must fit the LDS
+        const bool sep_ok = (size_t)p->d * 2 * p->ell_lmax * 64 * 8 <= 64 * 1024;
+        const int npb_e = kBlock / p->G;
+        for (int i = 0; i < p->n_inst; ++i) {
+            const std::vector<unsigned char> &sr = inst_seprow[i];
+            const int na_i = (int)sr.size();
+            for (int r = 0; r < na_i;) {
+                const unsigned char sv = sr[r] && sep_ok;
+                int e = r;
+                while (e < na_i && (sr[e] && sep_ok) == (bool)sv) ++e;
+                const int cap = sv ? 64 : npb_e;
+                for (int f0 = r; f0 < e; f0 += cap) {
+                    fk::WorkItem it;
+                    std::memset(&it, 0, sizeof(it));
+                    it.inst = i;
+                    it.first = f0;
+                    it.count = std::min(cap, e - f0);
+                    (sv ? p->ell_sep_work : rest_work).push_back(it);
+                }
+                r = e;
+            }
+        }
         std::vector<std::vector<fk::WorkItem>> by(nc);
-        for (const fk::WorkItem &it : p->act_work) {
+        for (const fk::WorkItem &it : rest_work) {
             const int w = p->inst[it.inst].ell_w;
             int c = 0;
             while (bound[c] < w) ++c;
@@ -875,6 +910,7 @@ fk_status build_plan(fk_plan *p)
     add_region(p, "node_work", sizeof(fk::WorkItem) * std::max<size_t>(p->node_work.size(), 1));
     add_region(p, "act_work", sizeof(fk::WorkItem) * std::max<size_t>(p->act_work.size(), 1));
     add_region(p, "ell_work", sizeof(fk::WorkItem) * std::max<size_t>(p->ell_work.size(), 1));
+    add_region(p, "ell_sep_work", sizeof(fk::WorkItem) * std::max<size_t>(p->ell_sep_work.size(), 1));
     add_region(p, "row_work", sizeof(fk::WorkItem) * std::max<size_t>(p->row_work.size(), 1));
     add_region(p, "split_work", sizeof(fk::WorkItem) * std::max<size_t>(p->split_work.size(), 1));
     add_region(p, "afw_nodes", sizeof(int) * std::max<size_t>(p->adj.fw_nodes.size(), 1));
@@ -930,6 +966,10 @@ void fill_dev(fk_plan *p)
     D.node_work = (const fk::WorkItem *)p->at("node_work");
     D.act_work = (const fk::WorkItem *)p->at("act_work");
     D.ell_work = (const fk::WorkItem *)p->at("ell_work");
+    D.ell_sep_work = (const fk::WorkItem *)p->at("ell_sep_work");
+    D.n_ell_sep_work = (int)p->ell_sep_work.size();
+    D.ell_sep_grid = grid_for(p->ell_sep_work.size());
+    D.ell_lmax = p->ell_lmax;
     D.n_ell_cls = p->n_ell_cls;
     for (int c = 0; c < fk::kEllClasses; ++c) {
         D.ell_cls_off[c] = p->ell_cls_off[c];
@@ -1263,6 +1303,7 @@ fk_status fk_plan_set_workspace(fk_plan *p, void *dev_ptr, size_t bytes, void *s
     FK_TRY(up("node_work", p->node_work.data(), sizeof(fk::WorkItem) * p->node_work.size()));
     FK_TRY(up("act_work", p->act_work.data(), sizeof(fk::WorkItem) * p->act_work.size()));
     FK_TRY(up("ell_work", p->ell_work.data(), sizeof(fk::WorkItem) * p->ell_work.size()));
+    FK_TRY(up("ell_sep_work", p->ell_sep_work.data(), sizeof(fk::WorkItem) * p->ell_sep_work.size()));
     FK_TRY(up("row_work", p->row_work.data(), sizeof(fk::WorkItem) * p->row_work.size()));
     FK_TRY(up("split_work", p->split_work.data(), sizeof(fk::WorkItem) * p->split_work.size()));
     FK_TRY(up("afw_nodes", p->adj.fw_nodes.data(), sizeof(int) * p->adj.fw_nodes.size()));

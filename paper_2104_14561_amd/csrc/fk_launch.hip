@@ -103,7 +103,16 @@ hipError_t launch_step_fused(const PlanDev &P, bool f32, int n, const void *pack
 hipError_t launch_assemble_ell(const PlanDev &P, bool f32, int n, int *org, void *vals,
                                void *exit_mass, hipStream_t s)
 {
-    // one launch per row-width class, its FP64 row boxes sized by the class
+    // separable rows: direct outer-product assembly, one thread per row
+    if (P.n_ell_sep_work > 0) {
+        const size_t lds = (size_t)P.d * 2 * P.ell_lmax * 64 * (f32 ? sizeof(float) : sizeof(double));
+        FK_DISPATCH_D(P.d,
+            if (f32) k_assemble_ell_sep<float, D><<<P.ell_sep_grid, 64, lds, s>>>(P, n, P.ell_sep_work, P.n_ell_sep_work, P.ell_lmax, org, (float *)vals, (float *)exit_mass);
+            else k_assemble_ell_sep<double, D><<<P.ell_sep_grid, 64, lds, s>>>(P, n, P.ell_sep_work, P.n_ell_sep_work, P.ell_lmax, org, (double *)vals, (double *)exit_mass));
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    // the other rows: one launch per row-width class, its FP64 row boxes sized by the class
     for (int c = 0; c < P.n_ell_cls; ++c) {
         const WorkItem *work = P.ell_work + P.ell_cls_off[c];
         const int nw = P.ell_cls_n[c], bw = P.ell_cls_w[c], grid = P.ell_cls_grid[c];
