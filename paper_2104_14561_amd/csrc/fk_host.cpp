@@ -159,8 +159,11 @@ struct fk_plan {
     std::vector<double> tfac;
     std::vector<fk::WorkItem> slope_work, node_work, act_work, row_work, split_work;
     std::vector<fk::WorkItem> ell_work;   // non-separable ELL rows by width class
-    std::vector<fk::WorkItem> ell_sep_work;   // separable ELL rows, runs of up to 64
+    std::vector<fk::WorkItem> ell_sep_work;   // separable ELL rows, runs of up to 64, by class
     int ell_lmax = 1;                     // longest row box axis
+    int n_ell_sep_cls = 0;
+    int ell_sep_off[fk::kEllClasses] = {}, ell_sep_n[fk::kEllClasses] = {},
+        ell_sep_l[fk::kEllClasses] = {};
     int n_ell_cls = 0;
     int ell_cls_off[fk::kEllClasses] = {}, ell_cls_n[fk::kEllClasses] = {},
         ell_cls_w[fk::kEllClasses] = {};
@@ -870,6 +873,34 @@ fk_status build_plan(fk_plan *p)
                 r = e;
             }
         }
+        // separable runs by the instance's longest box axis (8, 16, 32, ...):
+        // one launch per class, its LDS vectors sized by the class
+        {
+            std::vector<fk::WorkItem> sw;
+            sw.swap(p->ell_sep_work);
+            int nsc = 0;
+            for (int lb = 8; nsc < fk::kEllClasses; lb *= 2) {
+                const int lo = nsc == 0 ? 0 : lb / 2;
+                int lmax_c = 0, first = (int)p->ell_sep_work.size();
+                for (const fk::WorkItem &it : sw) {
+                    int li = 1;
+                    for (int a = 0; a < p->d; ++a) li = std::max(li, p->inst[it.inst].ell_box[a]);
+                    if (li > lo && li <= lb) {
+                        p->ell_sep_work.push_back(it);
+                        lmax_c = std::max(lmax_c, li);
+                    }
+                }
+                const int cnt = (int)p->ell_sep_work.size() - first;
+                if (cnt > 0) {
+                    p->ell_sep_off[nsc] = first;
+                    p->ell_sep_n[nsc] = cnt;
+                    p->ell_sep_l[nsc] = lmax_c;
+                    ++nsc;
+                }
+                if (lb >= p->ell_lmax) break;
+            }
+            p->n_ell_sep_cls = nsc;
+        }
         std::vector<std::vector<fk::WorkItem>> by(nc);
         for (const fk::WorkItem &it : rest_work) {
             const int w = p->inst[it.inst].ell_w;
@@ -967,9 +998,13 @@ void fill_dev(fk_plan *p)
     D.act_work = (const fk::WorkItem *)p->at("act_work");
     D.ell_work = (const fk::WorkItem *)p->at("ell_work");
     D.ell_sep_work = (const fk::WorkItem *)p->at("ell_sep_work");
-    D.n_ell_sep_work = (int)p->ell_sep_work.size();
-    D.ell_sep_grid = grid_for(p->ell_sep_work.size());
-    D.ell_lmax = p->ell_lmax;
+    D.n_ell_sep_cls = p->n_ell_sep_cls;
+    for (int c = 0; c < fk::kEllClasses; ++c) {
+        D.ell_sep_off[c] = p->ell_sep_off[c];
+        D.ell_sep_n[c] = p->ell_sep_n[c];
+        D.ell_sep_l[c] = p->ell_sep_l[c];
+        D.ell_sep_grid[c] = grid_for(p->ell_sep_n[c]);
+    }
     D.n_ell_cls = p->n_ell_cls;
     for (int c = 0; c < fk::kEllClasses; ++c) {
         D.ell_cls_off[c] = p->ell_cls_off[c];

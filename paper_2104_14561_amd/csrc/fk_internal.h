@@ -147,10 +147,12 @@ struct PlanDev {
     // assembly work by row-width class: the LDS row boxes of a launch are
     // sized by its class's widest row, not by the widest row of the plan
     const WorkItem *ell_work;
-    const WorkItem *ell_sep_work;   // separable rows, assembled as outer products
-    int n_ell_sep_work;
-    int ell_sep_grid;
-    int ell_lmax;                   // longest row box axis (LDS vectors of that kernel)
+    const WorkItem *ell_sep_work;   // separable rows, assembled as outer products,
+    int n_ell_sep_cls;              // by class of the longest box axis
+    int ell_sep_off[kEllClasses];
+    int ell_sep_n[kEllClasses];
+    int ell_sep_l[kEllClasses];     // longest box axis in the class (LDS vectors)
+    int ell_sep_grid[kEllClasses];
     int n_ell_cls;
     int ell_cls_off[kEllClasses];
     int ell_cls_n[kEllClasses];

@@ -103,12 +103,15 @@ hipError_t launch_step_fused(const PlanDev &P, bool f32, int n, const void *pack
 hipError_t launch_assemble_ell(const PlanDev &P, bool f32, int n, int *org, void *vals,
                                void *exit_mass, hipStream_t s)
 {
-    // separable rows: direct outer-product assembly, one thread per row
-    if (P.n_ell_sep_work > 0) {
-        const size_t lds = (size_t)P.d * 2 * P.ell_lmax * 64 * (f32 ? sizeof(float) : sizeof(double));
+    // separable rows: direct outer-product assembly, one thread per row, one
+    // launch per class of the longest box axis (LDS vectors sized by the class)
+    for (int c = 0; c < P.n_ell_sep_cls; ++c) {
+        const WorkItem *work = P.ell_sep_work + P.ell_sep_off[c];
+        const int nw = P.ell_sep_n[c], lm = P.ell_sep_l[c], grid = P.ell_sep_grid[c];
+        const size_t lds = (size_t)P.d * 2 * lm * 64 * (f32 ? sizeof(float) : sizeof(double));
         FK_DISPATCH_D(P.d,
-            if (f32) k_assemble_ell_sep<float, D><<<P.ell_sep_grid, 64, lds, s>>>(P, n, P.ell_sep_work, P.n_ell_sep_work, P.ell_lmax, org, (float *)vals, (float *)exit_mass);
-            else k_assemble_ell_sep<double, D><<<P.ell_sep_grid, 64, lds, s>>>(P, n, P.ell_sep_work, P.n_ell_sep_work, P.ell_lmax, org, (double *)vals, (double *)exit_mass));
+            if (f32) k_assemble_ell_sep<float, D><<<grid, 64, lds, s>>>(P, n, work, nw, lm, org, (float *)vals, (float *)exit_mass);
+            else k_assemble_ell_sep<double, D><<<grid, 64, lds, s>>>(P, n, work, nw, lm, org, (double *)vals, (double *)exit_mass));
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
