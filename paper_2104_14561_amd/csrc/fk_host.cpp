@@ -337,11 +337,11 @@ void build_work(std::vector<fk::WorkItem> &out, int inst, int count, int chunk, 
     }
 }
 
-int grid_for(size_t n_work)
+int grid_for(size_t n_work, int per_cu = 8)
 {
-    // persistent grid: enough workgroups for the work list, at most 8 per CU,
-    // a multiple of the 8 XCDs
-    size_t g = std::min<size_t>(n_work, 256 * 8);
+    // persistent grid: enough workgroups for the work list, at most per_cu per
+    // CU (8 for 256-thread workgroups), a multiple of the 8 XCDs
+    size_t g = std::min<size_t>(n_work, (size_t)256 * per_cu);
     if (g >= 8) g = (g + 7) / 8 * 8;
     return (int)std::max<size_t>(g, 1);
 }
@@ -1003,7 +1003,7 @@ void fill_dev(fk_plan *p)
         D.ell_sep_off[c] = p->ell_sep_off[c];
         D.ell_sep_n[c] = p->ell_sep_n[c];
         D.ell_sep_l[c] = p->ell_sep_l[c];
-        D.ell_sep_grid[c] = grid_for(p->ell_sep_n[c]);
+        D.ell_sep_grid[c] = grid_for(p->ell_sep_n[c], 32);   // 64-thread workgroups
     }
     D.n_ell_cls = p->n_ell_cls;
     for (int c = 0; c < fk::kEllClasses; ++c) {
