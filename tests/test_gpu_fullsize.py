@@ -188,3 +188,19 @@ def test_abc8_full_size_adjoint_wrt_D_vs_central_differences():
     rel = np.abs(g - fd) / np.abs(fd)
     print("adjoint dJ/dD", g, "central differences", fd, "rel", rel)
     assert np.all(rel <= 1e-5)   # measured <= 2e-7
+
+
+def test_abc8_full_size_fp32_adjoint_close_to_fp64():
+    """The same batch with the FP32 apply: dJ/dD per instance against the
+    FP64 adjoint."""
+    probs = W.abc3d_batch()
+    lam = torch.cat([torch.from_numpy(W.region_mean_weights(p).reshape(-1)) for p in probs])
+    res = {}
+    for prec in ("f64", "f32"):
+        plan = Plan(probs, precision=prec, ckpt_every=64, use_graph=True)
+        g, _ = plan.adjoint(lam.to("cuda", plan.dtype))
+        res[prec] = g.cpu().numpy()[:, 4]
+        plan.close()
+    rel = np.abs(res["f32"] - res["f64"]) / np.abs(res["f64"])
+    print("dJ/dD f64", res["f64"], "f32", res["f32"], "rel", rel)
+    assert np.all(rel <= 1e-4)   # measured <= 1e-5
