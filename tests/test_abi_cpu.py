@@ -188,3 +188,15 @@ def test_tune_rejects_bad_arguments(lib):
     assert lib.fk_tune(arr, 1, ctypes.byref(opt), 4, None, 0, None, ctypes.byref(res)) == -1
     assert "workspace" in lib.fk_last_error().decode()
     del keep
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus 2 exits with status 2 and says why,
+    before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and not r.stdout
