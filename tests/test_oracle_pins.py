@@ -604,3 +604,23 @@ def test_full_size_cell2d_adjoint_fixture_matches_frozen_central_differences():
     g, fd = np.array(ref["grad"]), np.array(ref["fd_frozen_exits"])
     assert np.all(np.abs(g - fd) <= 1e-5 * np.abs(fd) + 1e-12), (g, fd)
     assert 0.0 < ref["J0"] < 1.0
+
+
+def test_adjoint_taylor_remainder_is_second_order():
+    """With the exit classification frozen, J(theta + h e) - J(theta) - h <grad, e>
+    falls like h^2 along a mixed direction of all four parameters: a wrong or
+    dropped gradient term leaves an O(h) remainder (a factor 10 per decade)."""
+    prob = W.cell2d(nx=49, ny=25, n_steps=12, dt=2e-3, D=2e-3, A=1.1, eps=0.2, omega=5.0)
+    _, rec = oracle.solve(prob, snaps=[0], record_exits=True)
+    lam = np.random.default_rng(13).uniform(size=prob.shape)
+    grad, _ = oracle.adjoint(prob, lam, frozen_exits=rec)
+    theta = np.array(list(prob.coef) + [prob.D])
+    e = np.array([0.3, -0.5, 0.7, 0.4]) * theta
+
+    def J(t):
+        u0 = oracle.solve(prob, snaps=[0], frozen_exits=rec, coef=list(t[:3]), D=t[3])[0]
+        return float(np.sum(lam * u0))
+
+    J0 = J(theta)
+    R = [abs(J(theta + h * e) - J0 - h * float(np.dot(grad, e))) for h in (1e-2, 1e-3, 1e-4)]
+    assert 70 < R[0] / R[1] < 130 and 70 < R[1] / R[2] < 130, R
