@@ -95,6 +95,10 @@ def _load():
             "fko_solve": (ctypes.c_int, [P, ip, ctypes.c_int, dp, up, up]),
             "fko_assemble_row": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_long, dp, dp]),
             "fko_adjoint": (ctypes.c_int, [P, dp, dp, dp, up]),
+            "fko_solve_all": (ctypes.c_int, [P, dp, up]),
+            "fko_adjoint_states": (ctypes.c_int, [P, dp, dp, dp, dp, up]),
+            "fko_set_flat_rel": (None, [ctypes.c_double]),
+            "fko_get_flat_rel": (ctypes.c_double, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -306,3 +310,49 @@ def adjoint(prob, lam0: np.ndarray, frozen_exits: Optional[np.ndarray] = None, *
     if rc != 0:
         raise MemoryError("oracle adjoint failed")
     return grad[: num_theta(op)], lamN.reshape(op.shape)
+
+
+def solve_all(prob, frozen_exits: Optional[np.ndarray] = None, **kw) -> np.ndarray:
+    """Every state of the backward pass: array [N + 1] + grid shape, entry n = u^n."""
+    op = _op(prob, **kw)
+    N = int(op.prob.n_steps)
+    U = np.zeros((N + 1) * op.J)
+    use = None if frozen_exits is None else np.ascontiguousarray(frozen_exits, dtype=np.uint8)
+    if _load().fko_solve_all(op.ptr, _dp(U), _up(use)) != 0:
+        raise MemoryError("oracle solve_all failed")
+    return U.reshape((N + 1,) + tuple(op.shape))
+
+
+def adjoint_states(prob, U: np.ndarray, lam0: np.ndarray,
+                   frozen_exits: Optional[np.ndarray] = None, **kw):
+    """Reverse sweep of the adjoint from caller-supplied states U[n] = u^n
+    (n = 0..N); returns (grad, lam^N) like ``adjoint``."""
+    op = _op(prob, **kw)
+    UU = np.ascontiguousarray(U, dtype=np.float64).reshape(-1)
+    assert UU.shape[0] == (op.prob.n_steps + 1) * op.J
+    lam = np.ascontiguousarray(lam0, dtype=np.float64).reshape(-1)
+    grad = np.zeros(8)
+    lamN = np.zeros(op.J)
+    use = None if frozen_exits is None else np.ascontiguousarray(frozen_exits, dtype=np.uint8)
+    rc = _load().fko_adjoint_states(op.ptr, _dp(UU), _dp(lam), _dp(grad), _dp(lamN), _up(use))
+    if rc != 0:
+        raise MemoryError("oracle adjoint_states failed")
+    return grad[: num_theta(op)], lamN.reshape(op.shape)
+
+
+class flat_rel:
+    """Context manager setting the oracle's flat-stretch threshold of the PCHIP
+    linearisation (relative; default 2^-30, 0 = exact equality only)."""
+
+    def __init__(self, r: float):
+        self.r = float(r)
+
+    def __enter__(self):
+        lib = _load()
+        self.old = lib.fko_get_flat_rel()
+        lib.fko_set_flat_rel(self.r)
+        return self
+
+    def __exit__(self, *exc):
+        _load().fko_set_flat_rel(self.old)
+        return False

@@ -623,13 +623,21 @@ int fko_assemble_row(const fko_problem *P, int n, long j, double *row, double *e
 
 /* The slope map of Eq. (e300) is not differentiable where a divided
  * difference vanishes; its linearisation takes derivative 0 there.  A
- * difference below 2^-30 of the magnitude of the two values it is taken from
- * is rounding noise of a flat stretch (equal values computed along different
- * rounding paths) and counts as vanishing, so that the adjoint does not
- * depend on the last bits of u. */
+ * difference below flat_rel (default 2^-30) of the magnitude of the two
+ * values it is taken from is rounding noise of a flat stretch (equal values
+ * computed along different rounding paths) and counts as vanishing, so that
+ * the adjoint does not depend on the last bits of u.  flat_rel = 0 keeps only
+ * exact equality.  The tests set it to show that the parameter gradient does
+ * not depend on it. */
+static double flat_rel = 0x1p-30;
+
+void fko_set_flat_rel(double r) { flat_rel = r; }
+
+double fko_get_flat_rel(void) { return flat_rel; }
+
 static int flat_pair(double a, double b)
 {
-    return fabs(a - b) <= 0x1p-30 * (fabs(a) + fabs(b));
+    return fabs(a - b) <= flat_rel * (fabs(a) + fabs(b));
 }
 
 /* Transpose of the PCHIP slope map along every axis, linearised at u:
@@ -665,11 +673,13 @@ static void slopes_transpose(const fko_problem *P, const double *u, const double
     }
 }
 
-/* Given lam0 = dJ/du^0 (length J), returns grad = dJ/dtheta (fko_num_theta
- * entries, theta = (drift parameters, D)) and, if lamN is given, dJ/du^N on
- * active nodes.  Stores every u^n (plain, memory N*J doubles). */
-int fko_adjoint(const fko_problem *P, const double *lam0, double *grad, double *lamN,
-                const unsigned char *exit_use)
+/* Reverse sweep of the adjoint from the stored states U[n * J + j] = u^n_j,
+ * n = 0..N (the forward pass of the same problem, or any states the caller
+ * supplies).  Given lam0 = dJ/du^0 (length J), returns grad = dJ/dtheta
+ * (fko_num_theta entries, theta = (drift parameters, D)) and, if lamN is
+ * given, dJ/du^N on active nodes. */
+int fko_adjoint_states(const fko_problem *P, const double *U, const double *lam0,
+                       double *grad, double *lamN, const unsigned char *exit_use)
 {
     long J = fko_num_nodes(P);
     int N = P->n_steps;
@@ -678,25 +688,16 @@ int fko_adjoint(const fko_problem *P, const double *lam0, double *grad, double *
     for (int a = 0; a < P->d; a++) Q *= P->gh_n;
     long Ja = fko_active_nodes(P, NULL);
     long *active = (long *)malloc(sizeof(long) * (Ja > 0 ? Ja : 1));
-    double *U = (double *)malloc(sizeof(double) * J * (long)(N + 1));
     double *g = (double *)malloc(sizeof(double) * J * P->d);
     double *lam = (double *)malloc(sizeof(double) * J);
     double *mu = (double *)malloc(sizeof(double) * J * (P->d + 1));
     char *cls = (char *)malloc((size_t)J);
-    if (!active || !U || !g || !lam || !mu || !cls) {
-        free(active); free(U); free(g); free(lam); free(mu); free(cls);
+    if (!active || !g || !lam || !mu || !cls) {
+        free(active); free(g); free(lam); free(mu); free(cls);
         return -1;
     }
     fko_active_nodes(P, active);
     for (long j = 0; j < J; j++) cls[j] = (char)fko_node_class(P, j);
-
-    /* forward pass, keeping every state */
-    fko_chi(P, U + (long)N * J);
-    for (int n = N - 1; n >= 0; n--) {
-        fko_slopes(P, U + (long)(n + 1) * J, g);
-        step_impl(P, n, active, Ja, U + (long)(n + 1) * J, g, U + (long)n * J,
-                  NULL, exit_use, NULL, NULL);
-    }
 
     /* lam^0: only active nodes carry sensitivity; an image node's cotangent
      * belongs to the node it copies. */
@@ -790,6 +791,40 @@ int fko_adjoint(const fko_problem *P, const double *lam0, double *grad, double *
             if (cls[j] != 0) lam[j] = 0.0;
     }
     if (lamN) memcpy(lamN, lam, sizeof(double) * J);
-    free(active); free(U); free(g); free(lam); free(mu); free(cls);
+    free(active); free(g); free(lam); free(mu); free(cls);
     return 0;
+}
+
+/* Every state of the backward pass: U[n * J + j] = u^n_j, n = 0..N. */
+int fko_solve_all(const fko_problem *P, double *U, const unsigned char *exit_use)
+{
+    long J = fko_num_nodes(P);
+    int N = P->n_steps;
+    long Ja = fko_active_nodes(P, NULL);
+    long *active = (long *)malloc(sizeof(long) * (Ja > 0 ? Ja : 1));
+    double *g = (double *)malloc(sizeof(double) * J * P->d);
+    if (!active || !g) { free(active); free(g); return -1; }
+    fko_active_nodes(P, active);
+    fko_chi(P, U + (long)N * J);
+    for (int n = N - 1; n >= 0; n--) {
+        fko_slopes(P, U + (long)(n + 1) * J, g);
+        step_impl(P, n, active, Ja, U + (long)(n + 1) * J, g, U + (long)n * J,
+                  NULL, exit_use, NULL, NULL);
+    }
+    free(active); free(g);
+    return 0;
+}
+
+/* Adjoint of the whole pass: the forward pass keeping every u^n (memory
+ * (N + 1) J doubles), then the reverse sweep. */
+int fko_adjoint(const fko_problem *P, const double *lam0, double *grad, double *lamN,
+                const unsigned char *exit_use)
+{
+    long J = fko_num_nodes(P);
+    double *U = (double *)malloc(sizeof(double) * J * (long)(P->n_steps + 1));
+    if (!U) return -1;
+    int rc = fko_solve_all(P, U, exit_use);
+    if (rc == 0) rc = fko_adjoint_states(P, U, lam0, grad, lamN, exit_use);
+    free(U);
+    return rc;
 }
