@@ -624,3 +624,222 @@ def test_adjoint_taylor_remainder_is_second_order():
     J0 = J(theta)
     R = [abs(J(theta + h * e) - J0 - h * float(np.dot(grad, e))) for h in (1e-2, 1e-3, 1e-4)]
     assert 70 < R[0] / R[1] < 130 and 70 < R[1] / R[2] < 130, R
+
+
+# ---------------------------------------------------------------------------
+# Disc (ball) exit region (Section 2: exit region and exit time; a disc target
+# inside the grid box)
+# ---------------------------------------------------------------------------
+
+# an off-centre disc (centre not on the diagonal, so that swapped centre
+# coordinates change the region) on a rectangular grid
+DISC_C = (0.63, 0.41)
+DISC_R = 0.29
+
+
+def _disc_problem(n0=61, n1=37, **kw):
+    base = dict(axes=[W.uniform_axis(0.0, 2.0, n0), W.uniform_axis(0.0, 1.0, n1)],
+                coef_kind="const", coef=(0.0, 0.0), D=0.0, region_kind="ball",
+                center=DISC_C + (0.0,), radius=DISC_R, gh_q=2, dt=0.01, n_steps=1)
+    base.update(kw)
+    return W.Problem(**base)
+
+
+def _disc_exit_mask(X, Y, c, r, box):
+    """Exit region from numpy's hypot (a different formula from the squared
+    distance the scheme compares) and the box faces."""
+    (x0, x1), (y0, y1) = box
+    return (np.hypot(X - c[0], Y - c[1]) >= r) | (X <= x0) | (X >= x1) | (Y <= y0) | (Y >= y1)
+
+
+def test_disc_node_classes_match_hypot_mask():
+    """Exit nodes of a disc target are the nodes at distance >= r from the
+    centre (or on a face of the box); no node of this grid lies within 1e-6 of
+    the circle, so the two formulas must agree exactly."""
+    prob = _disc_problem()
+    x, y = prob.axes[0].nodes, prob.axes[1].nodes
+    X, Y = np.meshgrid(x, y, indexing="ij")
+    dist = np.hypot(X - DISC_C[0], Y - DISC_C[1])
+    assert np.abs(dist - DISC_R).min() > 1e-6
+    expect = _disc_exit_mask(X, Y, DISC_C, DISC_R, ((0.0, 2.0), (0.0, 1.0)))
+    cls = oracle.node_class(prob)
+    assert np.array_equal(cls == 1, expect)
+    assert np.array_equal(cls == 0, ~expect)
+    # chi is 1 exactly on the exit nodes
+    assert np.array_equal(oracle.chi(prob), expect.astype(float))
+    # the point test on off-grid points around the circle
+    rng = np.random.default_rng(3)
+    ang = rng.uniform(0, 2 * np.pi, 400)
+    rad = DISC_R * (1.0 + rng.choice([-1, 1], 400) * rng.uniform(1e-6, 0.2, 400))
+    for a, rr in zip(ang, rad):
+        z = (DISC_C[0] + rr * np.cos(a), DISC_C[1] + rr * np.sin(a))
+        assert oracle.is_exit_point(prob, z) == (rr >= DISC_R), (z, rr)
+
+
+def test_disc_translation_exits_exactly():
+    """sigma = 0 and b = (k0 h0, k1 h1)/dt: every landing point is a grid node,
+    shifted by (k0, k1) nodes per step, so u^n_j = 1 exactly when the walk
+    j + m (k0, k1), m = 0 .. N - n, meets an exit node (of the disc or of the
+    box) -- with the exit region taken from numpy's hypot, not the scheme."""
+    n0, n1, dt, N = 61, 37, 0.01, 7
+    x = np.linspace(0.0, 2.0, n0)
+    y = np.linspace(0.0, 1.0, n1)
+    h0, h1 = x[1] - x[0], y[1] - y[0]
+    for k0, k1 in ((1, 0), (0, -1), (2, 1), (-1, 2)):
+        prob = _disc_problem(coef=(k0 * h0 / dt, k1 * h1 / dt), dt=dt, n_steps=N, gh_q=3)
+        out = oracle.solve(prob, snaps=list(range(N + 1)))
+        I0, I1 = np.meshgrid(np.arange(n0), np.arange(n1), indexing="ij")
+        for n in range(N + 1):
+            hit = np.zeros((n0, n1), dtype=bool)
+            for m in range(N - n + 1):
+                J0, J1 = I0 + m * k0, I1 + m * k1
+                off = (J0 <= 0) | (J0 >= n0 - 1) | (J1 <= 0) | (J1 >= n1 - 1)
+                Jc0, Jc1 = np.clip(J0, 0, n0 - 1), np.clip(J1, 0, n1 - 1)
+                inside_exit = _disc_exit_mask(x[Jc0], y[Jc1], DISC_C, DISC_R,
+                                              ((0.0, 2.0), (0.0, 1.0)))
+                hit |= off | inside_exit
+            np.testing.assert_allclose(out[n], hit.astype(float), atol=1e-12,
+                                       err_msg=f"shift ({k0},{k1}) n={n}")
+
+
+def _disc_survival_bessel(T, D, R, K=200):
+    """Probability that sqrt(2 D) W started at the centre of a disc of radius
+    R has not left it by T: sum_k 2 / (j_k J1(j_k)) exp(-j_k^2 D T / R^2), j_k
+    the zeros of J0 (heat equation in the disc, radial eigenfunctions)."""
+    from scipy.special import j1, jn_zeros
+    j = jn_zeros(0, K)
+    return float(np.sum(2.0 / (j * j1(j)) * np.exp(-j * j * D * T / R ** 2)))
+
+
+def test_disc_exit_from_centre_vs_bessel_series():
+    """Zero drift, exit from a disc (r = 0.3) of the unit square, started at
+    the centre: the scheme against the closed-form exit probability.  The
+    scheme monitors exits at step ends only, which biases it low by about the
+    Broadie-Glasserman-Kou shift of the boundary, 0.5826 sigma sqrt(dt); with
+    the radius shifted by that amount the series agrees to a few 1e-3, and the
+    plain-series gap shrinks with dt."""
+    R, D, T = 0.3, 0.02, 0.4
+    sig = math.sqrt(2 * D)
+    gaps, gaps_bgk = [], []
+    for dt in (0.004, 0.001):
+        N = int(round(T / dt))
+        prob = W.Problem(axes=[W.uniform_axis(0, 1, 129), W.uniform_axis(0, 1, 129)],
+                         coef_kind="const", coef=(0.0, 0.0), D=D, region_kind="ball",
+                         center=(0.5, 0.5, 0.0), radius=R, gh_q=8, dt=dt, n_steps=N)
+        u0 = oracle.solve(prob, snaps=[0])[0]
+        pc = u0[64, 64]
+        gaps.append(pc - (1.0 - _disc_survival_bessel(T, D, R)))
+        gaps_bgk.append(pc - (1.0 - _disc_survival_bessel(T, D, R + 0.5826 * sig * math.sqrt(dt))))
+    print("plain", gaps, "shifted", gaps_bgk)
+    assert -0.015 < gaps[0] < 0 and -0.008 < gaps[1] < 0 and abs(gaps[1]) < 0.6 * abs(gaps[0])
+    assert all(abs(g) < 0.006 for g in gaps_bgk)
+
+
+def test_disc_exit_matches_discrete_chain_monte_carlo():
+    """Zero drift, off-centre disc: Monte Carlo of the chain the scheme
+    discretises (Gaussian steps, exit checked at step ends) from four nodes
+    near the circle.  The interpolant of u^{n+1} in cells cut by the circle
+    mixes inside values with the exit nodes' 1, an O(h) effect that shrinks
+    under refinement; at h = 1/200 the gap is within 0.015."""
+    c, r = (0.46, 0.55), 0.31
+    D, dt, N = 0.01, 0.004, 50
+    pts = [(0.62, 0.54), (0.46, 0.80), (0.24, 0.52), (0.46, 0.28)]
+    rng = np.random.default_rng(11)
+    s = math.sqrt(2 * D * dt)
+    mc = []
+    for px, py in pts:
+        npth = 300_000
+        pos = np.empty((npth, 2))
+        pos[:, 0], pos[:, 1] = px, py
+        alive = np.ones(npth, dtype=bool)
+        for _ in range(N):
+            pos[alive] += s * rng.standard_normal((int(alive.sum()), 2))
+            alive &= np.hypot(pos[:, 0] - c[0], pos[:, 1] - c[1]) < r
+        p = 1.0 - alive.mean()
+        mc.append((p, math.sqrt(max(p * (1 - p), 1e-12) / npth)))
+    worst = {}
+    for n in (51, 201):
+        prob = W.Problem(axes=[W.uniform_axis(0, 1, n), W.uniform_axis(0, 1, n)],
+                         coef_kind="const", coef=(0.0, 0.0), D=D, region_kind="ball",
+                         center=c + (0.0,), radius=r, gh_q=8, dt=dt, n_steps=N)
+        u0 = oracle.solve(prob, snaps=[0])[0]
+        errs = []
+        for (px, py), (p, se) in zip(pts, mc):
+            i, j = int(round(px * (n - 1))), int(round(py * (n - 1)))
+            errs.append(abs(u0[i, j] - p) - 5 * se)
+        worst[n] = max(errs)
+    print(worst)
+    assert worst[201] < 0.015 and worst[201] < worst[51] / 3
+
+
+# ---------------------------------------------------------------------------
+# Linearisation of the PCHIP slope at its kinks (adjoint)
+# ---------------------------------------------------------------------------
+
+
+def _box2d_adjoint_case():
+    prob = W.Problem(axes=[W.uniform_axis(0, 1, 37), W.uniform_axis(0, 2, 71)],
+                     coef_kind="const", coef=(0.4, -0.7), D=0.01, region_kind="box",
+                     gh_q=5, dt=0.01, n_steps=9)
+    lam0 = np.random.default_rng(21).uniform(size=prob.shape)
+    return prob, lam0
+
+
+def test_flat_rule_theta_gradient_independent_of_threshold():
+    """The slope 2ab/(a+b) has a kink where a divided difference vanishes; the
+    adjoint takes derivative 0 at differences below a relative threshold of
+    the values (2^-30).  On the box case, whose rows along x are equal up to
+    a factor that decays continuously away from the x faces (relative
+    differences of neighbours at every scale from 2^-52 up), the parameter
+    gradient does not depend on the threshold: 2^-20 .. 2^-44 and exact
+    equality give the same gradient within 1e-7."""
+    prob, lam0 = _box2d_adjoint_case()
+    U = oracle.solve_all(prob)
+    g0, _ = oracle.adjoint_states(prob, U, lam0)
+    for e in (20, 24, 28, 34, 40, 44, None):
+        with oracle.flat_rel(0.0 if e is None else 2.0 ** -e):
+            g, _ = oracle.adjoint_states(prob, U, lam0)
+        assert np.abs(g - g0).max() <= 1e-7 * np.abs(g0).max(), (e, g, g0)
+
+
+def test_flat_rule_makes_lamN_a_smooth_function_of_the_states():
+    """With the rule, dJ/du^N responds linearly to a perturbation of the
+    stored states (relative size 2^-52 .. 2^-40, slope below 2e5); without it
+    (exact equality only), a 1-ulp perturbation flips Jacobian branches of
+    rows that are flat up to rounding and moves dJ/du^N by more than 1e-3 of
+    its size.  The slope bounds the dJ/du^N difference between two correct
+    implementations whose states differ by their rounding."""
+    prob, lam0 = _box2d_adjoint_case()
+    U = oracle.solve_all(prob)
+    _, l0 = oracle.adjoint_states(prob, U, lam0)
+    rng = np.random.default_rng(7)
+    inner = (U > 0) & (U < 1)
+    for rel in (2.0 ** -52, 2.0 ** -46, 2.0 ** -40):
+        Up = np.where(inner, U * (1 + rel * rng.uniform(-1, 1, size=U.shape)), U)
+        _, l = oracle.adjoint_states(prob, Up, lam0)
+        assert np.abs(l - l0).max() <= 2e5 * rel * np.abs(l0).max(), rel
+    with oracle.flat_rel(0.0):
+        _, lr = oracle.adjoint_states(prob, U, lam0)
+        worst = 0.0
+        for _ in range(3):
+            up = rng.integers(0, 2, size=U.shape) == 1
+            Up = np.where(inner, np.where(up, np.nextafter(U, 2.0), np.nextafter(U, -1.0)), U)
+            _, l = oracle.adjoint_states(prob, Up, lam0)
+            worst = max(worst, float(np.abs(l - lr).max() / np.abs(lr).max()))
+    assert worst > 1e-3, worst
+
+
+def lamN_sensitivity(prob, lam0, rel=2.0 ** -44, trials=3, seed=7):
+    """Largest relative change of the oracle's dJ/du^N per unit relative
+    perturbation of its stored states (used to set the dJ/du^N bar of the GPU
+    comparison from the rounding difference of the two state sequences)."""
+    U = oracle.solve_all(prob)
+    _, l0 = oracle.adjoint_states(prob, U, lam0)
+    rng = np.random.default_rng(seed)
+    inner = (U > 0) & (U < 1)
+    worst = 0.0
+    for _ in range(trials):
+        Up = np.where(inner, U * (1 + rel * rng.uniform(-1, 1, size=U.shape)), U)
+        _, l = oracle.adjoint_states(prob, Up, lam0)
+        worst = max(worst, float(np.abs(l - l0).max() / np.abs(l0).max()) / rel)
+    return worst
