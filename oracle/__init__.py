@@ -93,6 +93,7 @@ def _load():
             "fko_step_cells": (ctypes.c_int, [P, ctypes.c_int, dp, ip, up]),
             "fko_chi": (None, [P, dp]),
             "fko_solve": (ctypes.c_int, [P, ip, ctypes.c_int, dp, up, up]),
+            "fko_solve_horizons": (ctypes.c_int, [P, ip, ctypes.c_int, dp]),
             "fko_assemble_row": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_long, dp, dp]),
             "fko_adjoint": (ctypes.c_int, [P, dp, dp, dp, up]),
             "fko_solve_all": (ctypes.c_int, [P, dp, up]),
@@ -284,6 +285,21 @@ def solve(prob, snaps: Sequence[int] = (0,), record_exits: bool = False,
         raise MemoryError("oracle solve failed")
     out = out.reshape((len(sn),) + tuple(op.shape))
     return (out, rec) if record_exits else out
+
+
+def solve_horizons(prob, horizons: Sequence[int]) -> np.ndarray:
+    """Algorithm 1 (Section 3.2): p^m of Eq. (e37) for every horizon m (in
+    steps, from the problem's t0) in one backward sweep; array
+    [len(horizons)] + grid shape."""
+    op = _op(prob)
+    m = np.ascontiguousarray(horizons, dtype=np.int32)
+    out = np.zeros((len(m), op.J))
+    rc = _load().fko_solve_horizons(op.ptr, _ip(m), len(m), _dp(out))
+    if rc == -2:
+        raise ValueError("horizons must be >= 1")
+    if rc != 0:
+        raise MemoryError("oracle solve_horizons failed")
+    return out.reshape((len(m),) + tuple(op.shape))
 
 
 def assemble_row(prob, n: int, j: int):

@@ -576,6 +576,48 @@ int fko_solve(const fko_problem *P, const int *snap, int n_snap, double *out,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Algorithm 1 (Section 3.2): several horizons in one backward sweep          */
+/* ------------------------------------------------------------------------ */
+
+/* Horizons m[h] >= 1 (in steps, any order, repeats allowed) from the start
+ * time t0: out[h * J + j] = p^{m[h]}_j of Eq. (e37), the approximate
+ * probability of exiting by t0 + m[h] dt when starting from x_j at t0.
+ * Algorithm 1: every column of P starts as chi; the sweep runs n = M, .., 1
+ * (M = the largest horizon), and at sweep index n every column whose horizon
+ * is at least n is replaced by Q Psi^{n-1} F^{n-1} of itself, i.e. takes one
+ * step of Scheme 1 with the coefficients at t0 + (n-1) dt (plus the exit
+ * mass).  Psi^{n-1} is the same for every column; here each column's step
+ * recomputes its landing points, which gives the same values.  P->n_steps is
+ * not used. */
+int fko_solve_horizons(const fko_problem *P, const int *m, int n_h, double *out)
+{
+    long J = fko_num_nodes(P);
+    long Ja = fko_active_nodes(P, NULL);
+    int M = 0;
+    for (int h = 0; h < n_h; h++) {
+        if (m[h] < 1) return -2;
+        if (m[h] > M) M = m[h];
+    }
+    long *active = (long *)malloc(sizeof(long) * (Ja > 0 ? Ja : 1));
+    double *g = (double *)malloc(sizeof(double) * J * P->d);
+    double *v = (double *)malloc(sizeof(double) * J);
+    if (!active || !g || !v) { free(active); free(g); free(v); return -1; }
+    fko_active_nodes(P, active);
+    for (int h = 0; h < n_h; h++) fko_chi(P, out + (long)h * J);   /* repmat(chi, 1, M) */
+    for (int n = M; n >= 1; n--) {
+        for (int h = 0; h < n_h; h++) {
+            if (m[h] < n) continue;                  /* columns n .. M only */
+            double *col = out + (long)h * J;
+            fko_slopes(P, col, g);                   /* F^{n-1} of this column */
+            step_impl(P, n - 1, active, Ja, col, g, v, NULL, NULL, NULL, NULL);
+            memcpy(col, v, sizeof(double) * J);
+        }
+    }
+    free(active); free(g); free(v);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Explicit row of the step operator A_n = Q Psi^n (Eq. (e34)-(e36))          */
 /* ------------------------------------------------------------------------ */
 

@@ -843,3 +843,79 @@ def lamN_sensitivity(prob, lam0, rel=2.0 ** -44, trials=3, seed=7):
         _, l = oracle.adjoint_states(prob, Up, lam0)
         worst = max(worst, float(np.abs(l - l0).max() / np.abs(l0).max()) / rel)
     return worst
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1 (Section 3.2): several horizons in one backward sweep
+# ---------------------------------------------------------------------------
+
+def test_algorithm1_columns_are_the_products_of_eq_e37():
+    """Column m of Algorithm 1 is p^m of Eq. (e37): the product of the step
+    operators with coefficients at t0 + (m-1) dt, .., t0 applied to chi.  Two
+    other routes to the same product: a Scheme-1 pass of N = m steps (same
+    arithmetic, bitwise), and one pass of N = M steps started at
+    t0 - (M - m) dt, whose state u^{M-m} has met the same coefficient times
+    (up to the rounding of the shifted times).  For this time-dependent flow
+    u^{M-m} of an unshifted pass is a different quantity (reading 12)."""
+    prob = W.cell2d(nx=49, ny=25, n_steps=30, D=2e-3, omega=7.0, eps=0.25)
+    hz = [7, 30, 18, 1, 18]
+    cols = oracle.solve_horizons(prob, hz)
+    M = max(hz)
+    one = oracle.solve(prob.replace(n_steps=M), snaps=[M - m for m in hz])
+    for h, m in enumerate(hz):
+        sep = oracle.solve(prob.replace(n_steps=m), snaps=[0])[0]
+        assert np.array_equal(cols[h], sep), m
+        shifted = prob.replace(n_steps=M, t0=prob.t0 - (M - m) * prob.dt)
+        s = oracle.solve(shifted, snaps=[M - m])[0]
+        assert np.abs(cols[h] - s).max() <= 1e-13, m
+        if m < M:
+            assert np.abs(cols[h] - one[h]).max() > 1e-3, m
+    assert np.array_equal(cols[2], cols[4])
+    with pytest.raises(ValueError):
+        oracle.solve_horizons(prob, [3, 0])
+
+
+def test_algorithm1_brownian_columns_vs_series():
+    """1D Brownian motion (Section 4.1, autonomous): every column is the
+    Scheme-1 state u^{M-m} of one pass, and approaches the closed form
+    Eq. (e45) at its own horizon on a Remark-2 grid (first order in dt:
+    halving dt roughly halves the error at every horizon); bounds [0, 1] and
+    monotone in the horizon."""
+    L, q = 10.0, 3
+    errs = []
+    for dt in (0.1, 0.05):
+        x = remark2_grid(L, 0.05, dt, 1.0, q)
+        hz = [int(round(T / dt)) for T in (0.5, 1.0, 2.0, 3.0)]
+        prob = W.Problem(axes=[W.Axis(x)], coef_kind="const", coef=(0.0,), D=0.5,
+                         region_kind="box", gh_q=q, dt=dt, n_steps=max(hz))
+        cols = oracle.solve_horizons(prob, hz)
+        one = oracle.solve(prob, snaps=[max(hz) - m for m in hz])
+        assert np.abs(cols - one).max() <= 1e-14
+        assert cols.min() >= -1e-14 and cols.max() <= 1 + 1e-14
+        assert np.all(np.diff(cols, axis=0) >= -1e-12)
+        errs.append([np.abs(c - p_exit_series(m * dt, x, L)).max() for c, m in zip(cols, hz)])
+    errs = np.array(errs)
+    assert np.all(errs[1] < 0.6 * errs[0]), errs
+    assert errs[1].max() < 0.04, errs
+
+
+def test_algorithm1_exit_probability_grows_with_horizon():
+    """Exiting by a later horizon is at least as likely (the events are
+    nested).  In 2D the scheme keeps this only approximately: the tensor
+    interpolant without twist terms (reading 8) can overshoot where the disc's
+    exit value 1 meets the interior, so a node next to the circle may lose a
+    little between horizons, and the scheme carries a trace of that inward.
+    Gates: the disc mean grows at every horizon; away from the circle (more
+    than two cells) no node decreases by more than 1e-4; next to it the
+    decrease stays below 1e-2 (observed: 1.7e-5 and 6.8e-3)."""
+    prob = W.cell2d(nx=65, ny=33, n_steps=60, D=3e-3, dt=2e-3, A=1.2, eps=0.2, omega=9.0)
+    hz = [5, 10, 20, 35, 60]
+    cols = oracle.solve_horizons(prob, hz)
+    w = W.region_mean_weights(prob)
+    means = [float((w * c).sum()) for c in cols]
+    assert np.all(np.diff(means) > 1e-3), means
+    inc = np.diff(cols, axis=0)
+    X, Y = np.meshgrid(prob.axes[0].nodes, prob.axes[1].nodes, indexing="ij")
+    near = np.abs(np.hypot(X - 0.5, Y - 0.5) - prob.radius) <= 2.0 / 32
+    assert inc[:, ~near].min() >= -1e-4, inc[:, ~near].min()
+    assert inc.min() >= -1e-2, inc.min()
