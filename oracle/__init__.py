@@ -28,7 +28,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fkoracle.c")
 _LIB = os.path.join(_HERE, "libfkoracle.so")
 
-COEF = {"const": 0, "cellular2d": 1, "abc3d": 2}
+COEF = {"const": 0, "cellular2d": 1, "abc3d": 2, "rolls2d": 3}
 REGION = {"box": 0, "ball": 1}
 
 

@@ -34,6 +34,7 @@
 #define FKO_COEF_CONST 0
 #define FKO_COEF_CELLULAR2D 1
 #define FKO_COEF_ABC3D 2
+#define FKO_COEF_ROLLS2D 3
 #define FKO_REGION_BOX 0
 #define FKO_REGION_BALL 1
 
@@ -155,6 +156,15 @@ void fko_drift(const fko_problem *P, double t, const double *x, double *b)
         double Api = p[0] * M_PI;
         b[0] = -(Api * sa * cy);
         b[1] = Api * ca * sy;
+    } else if (P->coef_kind == FKO_COEF_ROLLS2D) {
+        /* Section 4.2: Pe v with v_1 = -pi cos(pi x_2) [sin(n x_1) + eps f(t) cos(n x_1)],
+         * v_2 = n sin(pi x_2) [cos(n x_1) - eps f(t) sin(n x_1)], f(t) = cos(omega t);
+         * p = (Pe, eps, omega, n). */
+        double e = p[1] * cos(p[2] * t);
+        double s1 = sin(p[3] * x[0]), c1 = cos(p[3] * x[0]);
+        double s2 = sin(M_PI * x[1]), c2 = cos(M_PI * x[1]);
+        b[0] = -(p[0] * M_PI * c2 * (s1 + e * c1));
+        b[1] = p[0] * p[3] * s2 * (c1 - e * s1);
     } else {
         /* ABC flow, amplitudes modulated by f(t) = 1 + amp sin t */
         double f = 1.0 + p[3] * sin(t);
@@ -170,6 +180,7 @@ int fko_num_theta(const fko_problem *P)
 {
     if (P->coef_kind == FKO_COEF_CONST) return P->d + 1;
     if (P->coef_kind == FKO_COEF_CELLULAR2D) return 4;
+    if (P->coef_kind == FKO_COEF_ROLLS2D) return 4;   /* (Pe, eps, omega, D); n is a count */
     return 5;
 }
 
@@ -202,6 +213,24 @@ static void dz_dtheta(const fko_problem *P, double t, const double *x,
         dz[1 * 3 + 1] = dt * db1 * dphi_deps;
         dz[2 * 3 + 0] = dt * db0 * dphi_dom;
         dz[2 * 3 + 1] = dt * db1 * dphi_dom;
+    } else if (P->coef_kind == FKO_COEF_ROLLS2D) {
+        double Pe = p[0], eps = p[1], om = p[2], nn = p[3];
+        double e = eps * cos(om * t);
+        double s1 = sin(nn * x[0]), c1 = cos(nn * x[0]);
+        double s2 = sin(M_PI * x[1]), c2 = cos(M_PI * x[1]);
+        /* d b / d Pe = v */
+        dz[0 * 3 + 0] = dt * (-(M_PI * c2 * (s1 + e * c1)));
+        dz[0 * 3 + 1] = dt * (nn * s2 * (c1 - e * s1));
+        /* d b / d e, chained with d e / d eps = cos(omega t) and
+         * d e / d omega = -eps t sin(omega t) */
+        double db0 = -(Pe * M_PI * c2 * c1);
+        double db1 = -(Pe * nn * s2 * s1);
+        double de_deps = cos(om * t);
+        double de_dom = -(eps * t * sin(om * t));
+        dz[1 * 3 + 0] = dt * db0 * de_deps;
+        dz[1 * 3 + 1] = dt * db1 * de_deps;
+        dz[2 * 3 + 0] = dt * db0 * de_dom;
+        dz[2 * 3 + 1] = dt * db1 * de_dom;
     } else {
         double A = p[0], B = p[1], C = p[2], amp = p[3];
         double st = sin(t), f = 1.0 + amp * st;

@@ -297,6 +297,55 @@ def test_cellular_drift_is_rotated_stream_gradient_at_t_n():
     assert np.abs(beta[0] * (bx1 - bx)[sel]).max() > 1e-3
 
 
+def _psi_rolls(x1, x2, t, eps, om, n):
+    return np.sin(np.pi * x2) * (np.sin(n * x1) + eps * np.cos(om * t) * np.cos(n * x1))
+
+
+def test_paper2d_drift_is_roll_flow_of_stream_function():
+    """Section 4.2: Pe v with v = (-dpsi/dx2, dpsi/dx1) for the roll stream
+    function psi = sin(pi x2) (sin(n x1) + eps cos(omega t) cos(n x1)) (the
+    printed v_1, v_2 are its derivatives, so v is divergence-free); at
+    eps = 0 the elliptic points (+-pi/4, 1/2), (+-3pi/4, 1/2) and the hyperbolic
+    points (0, 0), (+-pi/2, 0), (pi, 1) are stagnation points."""
+    Pe, eps, om, n = 10.0, 0.15, 2 * math.pi / 10, 2
+    prob = W.paper2d(Pe=Pe, eps=eps, omega=om, n=n)
+    rng = np.random.default_rng(9)
+    hh = 1e-6
+    for _ in range(25):
+        x1, x2 = float(rng.uniform(-math.pi, math.pi)), float(rng.uniform(0, 1))
+        t = float(rng.uniform(0, 10))
+        b = oracle.drift(prob, t, [x1, x2])
+        d1 = (_psi_rolls(x1 + hh, x2, t, eps, om, n) - _psi_rolls(x1 - hh, x2, t, eps, om, n)) / (2 * hh)
+        d2 = (_psi_rolls(x1, x2 + hh, t, eps, om, n) - _psi_rolls(x1, x2 - hh, t, eps, om, n)) / (2 * hh)
+        np.testing.assert_allclose(b, [-Pe * d2, Pe * d1], atol=1e-7)
+    still = W.paper2d(eps=0.0)
+    for pt in [(math.pi / 4, 0.5), (-math.pi / 4, 0.5), (3 * math.pi / 4, 0.5),
+               (-3 * math.pi / 4, 0.5), (0.0, 0.0), (math.pi / 2, 0.0), (-math.pi / 2, 0.0),
+               (math.pi, 1.0)]:
+        assert np.abs(oracle.drift(still, 1.0, list(pt))).max() < 1e-12, pt
+    assert oracle.num_theta(prob) == 4
+
+
+def test_paper2d_exit_probability_low_in_roll_cores():
+    """The result stated for Fig. ex2:f1: with the time-dependent perturbation
+    the exit probability at T_max is small at the elliptic points (the roll
+    cores) and large near the separatrices, where the flow carries tracers
+    to the walls x2 = 0, 1.  Bounds hold (box exit: exit nodes at 1)."""
+    prob = W.paper2d()
+    u0 = oracle.solve(prob, snaps=[0])[0]
+    x1, x2 = prob.axes[0].nodes, prob.axes[1].nodes
+    mid = int(np.argmin(np.abs(x2 - 0.5)))
+    def at(v):
+        return u0[int(np.argmin(np.abs(x1 - v))), mid]
+    cores = [at(v) for v in (-3 * math.pi / 4, -math.pi / 4, math.pi / 4, 3 * math.pi / 4)]
+    seps = [at(v) for v in (-math.pi / 2, 0.0, math.pi / 2)]
+    assert max(cores) < 0.5 * min(seps), (cores, seps)
+    assert u0.min() >= -1e-3 and u0.max() <= 1 + 1e-12
+    assert np.all(u0[:, 0] == 1.0) and np.all(u0[:, -1] == 1.0)
+    # periodic in x1: the image column equals the first
+    assert np.array_equal(u0[0], u0[-1])
+
+
 def test_abc_drift_is_beltrami_and_modulated():
     """The ABC field satisfies curl v = v and div v = 0; the modulation
     multiplies it by 1 + amp sin t."""
@@ -505,26 +554,31 @@ def test_dense_row_reproduces_step():
 
 
 def _fd_grad(prob, k, h, rec, lam):
+    """Central difference of <lam, u^0> in theta_k = (differentiable drift
+    parameters..., D), exit classification frozen."""
     coef = list(prob.coef)
+    n_drift = W.N_DRIFT_PARAMS[prob.coef_kind] or prob.d
     D = prob.D
     vals = []
     for sgn in (+1, -1):
         c2, D2 = list(coef), D
-        if k < len(coef):
+        if k < n_drift:
             c2[k] = coef[k] + sgn * h * max(1.0, abs(coef[k]))
         else:
             D2 = D + sgn * h * D
         u0 = oracle.solve(prob, snaps=[0], frozen_exits=rec, coef=c2, D=D2)[0]
         vals.append(float(np.sum(lam * u0)))
-    step = h * (max(1.0, abs(coef[k])) if k < len(coef) else D)
+    step = h * (max(1.0, abs(coef[k])) if k < n_drift else D)
     return (vals[0] - vals[1]) / (2 * step)
 
 
-@pytest.mark.parametrize("which", ["cell", "const1d", "abc"])
+@pytest.mark.parametrize("which", ["cell", "const1d", "abc", "rolls"])
 def test_adjoint_matches_central_differences(which):
     """Frozen exit classification, central differences with h = 1e-6."""
     if which == "cell":
         prob = W.cell2d(nx=49, ny=25, n_steps=12, dt=2e-3, D=2e-3, A=1.1, eps=0.2, omega=5.0)
+    elif which == "rolls":
+        prob = W.paper2d(n1=41, n2=17, dt=2e-3, T=0.024, eps=0.4, omega=30.0, gh_q=4)
     elif which == "const1d":
         prob = W.Problem(axes=[W.uniform_axis(-1, 1, 41)], coef_kind="const", coef=(0.3,),
                          D=0.2, region_kind="box", gh_q=5, dt=0.01, n_steps=15)

@@ -25,6 +25,8 @@ there is no dataset):
 * ``cell2d_adj``  ``cell2d`` with dt = 5e-4 and 2000 steps.
 * ``abc3d``       time-modulated ABC flow on a 129^3 grid, periodic in x, y,
                   exit at |z| >= pi/2, 6x6x6 nodes; ``abc3d_batch8`` draws D.
+* ``paper2d``     the paper's own 2D example (Section 4.2): Pe = 10 roll flow,
+                  periodic in x_1, exit through x_2 in {0, 1}.
 """
 from __future__ import annotations
 
@@ -37,11 +39,12 @@ import numpy as np
 COEF_CONST = "const"            # p = (b_0, .., b_{d-1}); constant drift
 COEF_CELLULAR2D = "cellular2d"  # p = (A, eps, omega)
 COEF_ABC3D = "abc3d"            # p = (A, B, C, amp)
+COEF_ROLLS2D = "rolls2d"        # p = (Pe, eps, omega, n): the flow of Section 4.2
 
 REGION_BOX = "box"    # exit when a non-periodic coordinate leaves the open box
 REGION_BALL = "ball"  # exit also when |z - c| >= r
 
-N_DRIFT_PARAMS = {COEF_CONST: None, COEF_CELLULAR2D: 3, COEF_ABC3D: 4}
+N_DRIFT_PARAMS = {COEF_CONST: None, COEF_CELLULAR2D: 3, COEF_ABC3D: 4, COEF_ROLLS2D: 3}
 
 
 @dataclasses.dataclass
@@ -185,9 +188,21 @@ def abc3d_batch(n_inst: int = 8, seed: int = ABC8_SEED, **kw) -> List[Problem]:
 
 
 def paper2d(n1: int = 129, n2: int = 33, Pe: float = 10.0, eps: float = 0.15,
-            omega: float = 2.0 * math.pi / 10.0) -> dict:
-    """Parameters of the paper's own 2D example (Section 4.2), for reference."""
-    return dict(n1=n1, n2=n2, Pe=Pe, eps=eps, omega=omega, n=2, T=0.05)
+            omega: float = 2.0 * math.pi / 10.0, n: int = 2, T: float = 0.05,
+            dt: float = 5e-4, gh_q: int = 6) -> Problem:
+    """The paper's own 2D example (Section 4.2, Eq. (ex2model)-(ex3)):
+    dX = Pe v(X, t) dt + dW on [-pi, pi] x [0, 1], periodic in x_1, exit
+    through x_2 = 0 and x_2 = 1, with the cellular (Rayleigh-Benard roll)
+    velocity v of 2n cells perturbed by eps cos(omega t); Pe = 10,
+    eps = 0.15, omega = 2 pi / 10, n = 2, T_max = 0.05.  dW has unit
+    variance rate, so D = 1/2.  The grid, dt and Q* are not given in the
+    paper: 128 cells on the periodic axis, 32 across, dt = 5e-4 (100 steps)
+    and a 6-node rule."""
+    return Problem(axes=[uniform_axis(-math.pi, math.pi, n1, periodic=True),
+                         uniform_axis(0.0, 1.0, n2)],
+                   coef_kind=COEF_ROLLS2D, coef=(Pe, eps, omega, float(n)), D=0.5,
+                   region_kind=REGION_BOX, gh_q=gh_q, dt=dt,
+                   n_steps=int(round(T / dt)), name="paper2d")
 
 
 def region_mean_weights(prob: "Problem") -> np.ndarray:
