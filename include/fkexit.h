@@ -157,10 +157,11 @@ typedef struct {
     double ms_per_step[5];    /* indexed by step_kernel 0..4 (0 unused) */
 } fk_tune_result;
 
-/* Message of the last error on this thread ("" if none). */
+/* Message of the last error on this thread ("" if none).  Library plumbing:
+ * no passage of the paper defines it. */
 const char *fk_last_error(void);
 
-/* FK_ABI_VERSION of the loaded library. */
+/* FK_ABI_VERSION of the loaded library (plumbing, as fk_last_error). */
 int fk_version(void);
 
 /* Gauss-Hermite rule for the normalised Gaussian weight pi^{-1/2} e^{-xi^2}
@@ -168,48 +169,99 @@ int fk_version(void);
  * symmetric about 0.  host outputs of length q; 1 <= q <= 64. */
 fk_status fk_gh_rule(int q, double *nodes, double *weights);
 
-/* Validates n_inst >= 1 problems and builds a plan (host work only).  All
+/* Validates n_inst >= 1 problems and builds a plan (host work only).  The
+ * inputs are the paper's problem statement: the SDE's drift and diffusion
+ * (Section 2, Eq. (e1)), the exit region (Section 2; the ball is this
+ * library's addition), the Cartesian grid S (Section 3.1.2), the quadrature
+ * order Q* (Eq. (expec)-(quad)), dt and N (Section 3.1, Scheme 1).  The plan
+ * classifies every node (active, exit, periodic image: the terminal condition
+ * chi of Scheme 1) and builds the work lists of the step kernels.  All
  * instances must share d, gh_q, dt, n_steps, t0, coef_kind and region_kind;
  * grids and parameters may differ (batched, uneven grids).  Host arrays are
- * copied.  opt may be NULL (defaults: F64, fused, no graph, no adjoint). */
+ * copied.  opt may be NULL (defaults: F64, fused, no graph, no adjoint).
+ * Errors: FK_ERR_ARG (invalid problem: its message names the instance and the
+ * field), FK_ERR_UNSUPPORTED (a step layout not compiled for gh_q). */
 fk_status fk_plan_create(const fk_problem *probs, int n_inst, const fk_options *opt,
                          fk_plan **out);
 
+/* Frees the plan's host memory and its captured graph; the caller's
+ * workspace is not touched (the caller frees it).  NULL is ignored. */
 void fk_plan_destroy(fk_plan *p);
 
+/* Sizes of a plan (host output): node and active-node counts, Q = Q*^d
+ * (Eq. (quad) over d dimensions), workspace bytes.  FK_ERR_ARG on NULL. */
 fk_status fk_plan_get_info(const fk_plan *p, fk_plan_info *info);
 
-/* host: node_offset[n_inst + 1] and active_count[n_inst]. */
+/* Packed field layout (host outputs): node_offset[n_inst + 1] (instance i
+ * owns nodes node_offset[i] .. node_offset[i+1]-1 of every field) and
+ * active_count[n_inst] (its active nodes, the rows of A_n of Eq. (e36)). */
 fk_status fk_plan_layout(const fk_plan *p, int64_t *node_offset, int64_t *active_count);
 
 /* Attaches caller-owned device memory of at least workspace_bytes bytes
  * (256-byte aligned) and uploads the plan's tables into it; synchronises
  * stream before returning.  The memory must stay valid until the plan is
- * destroyed or another workspace is set. */
+ * destroyed or another workspace is set.  Plumbing (the library allocates no
+ * device memory itself); it holds the fields of Scheme 1's ping-pong, the
+ * records [u, F^n u] of Eq. (e36) and, for the adjoint, the checkpoints.
+ * Errors: FK_ERR_ARG (NULL or misaligned), FK_ERR_WORKSPACE (too small). */
 fk_status fk_plan_set_workspace(fk_plan *p, void *dev_ptr, size_t bytes, void *stream);
 
-/* Backward pass from u^N = chi.  u_out (device) receives n_snap fields,
- * u_out[s] = u^{snap_steps[s]} (0 <= snap_steps[s] <= N, host array).  A
- * non-finite value in a produced field is reported by fk_check_flags. */
+/* Backward pass of Scheme 1 (Section 3.1; matrix form Eq. (e36)-(e37)):
+ * from u^N = chi, u^n = A_n u^{n+1} + exit mass for n = N-1 .. 0.  u_out
+ * (device, caller-owned) receives n_snap fields, u_out[s] = u^{snap_steps[s]}
+ * (0 <= snap_steps[s] <= N, host array).  A non-finite value in a produced
+ * field is reported by fk_check_flags.  Errors: FK_ERR_STATE (no workspace),
+ * FK_ERR_ARG (snapshot outside [0, N], null output with n_snap > 0),
+ * FK_ERR_HIP. */
 fk_status fk_forward(fk_plan *p, const int *snap_steps, int n_snap, void *u_out,
                      void *stream);
 
-/* Backward pass resumed from a caller state u_start = u^{start_step}
- * (device, one field); snapshots with snap_steps[s] <= start_step. */
+/* Backward pass of Scheme 1 (Section 3.1) resumed from a caller state
+ * u_start = u^{start_step} (device, one field, read only); snapshots with
+ * snap_steps[s] <= start_step.  Errors as fk_forward. */
 fk_status fk_forward_from(fk_plan *p, const void *u_start, int start_step,
                           const int *snap_steps, int n_snap, void *u_out, void *stream);
 
-/* One step u^{n+1} -> u^n from an arbitrary state (device fields).  Exit
- * nodes of the result are 1, periodic images copy their originals. */
+/* One step of Scheme 1 (Section 3.1), u^n = Q Psi^n F^n u^{n+1} + exit mass
+ * (Eq. (e36)), from an arbitrary state u_next (device, one field) into u_out
+ * (device, one field).  Exit nodes of the result are 1, periodic images copy
+ * their originals.  Errors: FK_ERR_ARG (n outside [0, N-1], null field). */
 fk_status fk_step(fk_plan *p, int n, const void *u_next, void *u_out, void *stream);
 
-/* Landing cells of step n for instance inst (device outputs):
- * cells[Ja][Q][d] int32 (-1 where the landing point exits) and
- * exit_flags[Ja][Q] uint8, active nodes in increasing linear index. */
+/* The step operator A_n = Q Psi^n of Eq. (e34)-(e36) as a linear map, and its
+ * transpose (the reverse sweep's scatter, Eq. (e36) transposed), on caller
+ * data: a test hook for the adjoint identity <A_n x, y> = <x, A_n^T y>.
+ * Columns: the (d + 1) fields [u; g_0; ..; g_{d-1}] (values and nodal slopes
+ * along each axis, the column blocks of Psi^n), each one packed field, field
+ * f at element offset f * n_nodes.  Rows: the active nodes; the exit mass
+ * (the landing points that leave, value 1) is not part of A_n.
+ *   transpose = 0: x = (d + 1) fields (device, read), y = one field (device,
+ *     written): y_j = sum_q w_q I[x](z_jq) over the inside landing points of
+ *     active node j, y = 0 on every other node.  The coefficient tables of
+ *     step n are used (times t0 + n dt); the slopes are taken from x, not from
+ *     Eq. (e300).  FK_FORM_ELL plans assemble and apply A_n, fused plans
+ *     apply it matrix-free.
+ *   transpose = 1: x = one field (device, read; its values off the active
+ *     nodes are ignored), y = (d + 1) fields (device, written) = A_n^T x.
+ *     Needs a plan created with ckpt_every > 0 (FK_ERR_STATE otherwise).
+ * Uses the plan's ping-pong and record buffers: adjoint checkpoints stay
+ * valid.  Errors: FK_ERR_ARG (n outside [0, N-1], null field),
+ * FK_ERR_STATE, FK_ERR_HIP. */
+fk_status fk_apply_step(fk_plan *p, int n, int transpose, const void *x, void *y, void *stream);
+
+/* Landing points of step n (Eq. (e31)) located in the grid, for instance
+ * inst (device outputs, caller-owned): cells[Ja][Q][d] int32, the cell
+ * max{k : x_k <= z} of each coordinate clamped to [0, n-2] (Section 3.1.2;
+ * -1 where the landing point exits), and exit_flags[Ja][Q] uint8 (1: the point
+ * lies in the exit region, Section 2), active nodes in increasing linear
+ * index, tensor points in lexicographic order (last axis fastest).  Errors:
+ * FK_ERR_ARG (inst or n out of range, null output). */
 fk_status fk_export_cells(fk_plan *p, int inst, int n, int *cells,
                           unsigned char *exit_flags, void *stream);
 
-/* Assembled step operator of step n (FK_FORM_ELL plans): for every active
+/* Assembled step operator A_n = Q Psi^n of step n (Eq. (e34)-(e36); the
+ * paper's own GPU formulation assembles it, Section 3.2.1), FK_FORM_ELL plans
+ * only (FK_ERR_STATE otherwise): for every active
  * node (all instances, packed order) a row of ell_width (column, value) pairs,
  * column = (d + 1) * node + field (field 0: u, field 1 + a: slope along a,
  * node = packed node index), padding has value 0; exit_mass[row] = sum of
@@ -218,11 +270,16 @@ fk_status fk_export_cells(fk_plan *p, int inst, int n, int *cells,
 fk_status fk_export_ell(fk_plan *p, int n, int *cols, void *vals, void *exit_mass,
                         void *stream);
 
-/* Reads and clears the device status flags (synchronises stream).
- * *flags bit 0: a non-finite value was produced since the last check. */
+/* Reads and clears the device status flags (synchronises stream); plumbing,
+ * no passage of the paper defines it.  *flags bit 0: a non-finite value was
+ * produced since the last check (returns FK_ERR_NONFINITE); bit 1: a landing
+ * cell fell outside an assembled row box (FK_ERR_UNSUPPORTED). */
 fk_status fk_check_flags(fk_plan *p, void *stream, int *flags);
 
-/* Adjoint of the whole pass with the exit classification held fixed.
+/* Adjoint of the whole backward pass of Scheme 1 (the reverse sweep of the
+ * matrix form Eq. (e36): lam^{n+1} = F^n' ^T (Q Psi^n)^T lam^n, plus the
+ * derivatives of the landing points Eq. (e31) and of the Hermite weights with
+ * respect to theta), the exit classification of landing points held fixed.
  * lam0 (device, one field) = dJ/du^0.  Outputs: grad (device, double,
  * n_inst * FK_MAX_THETA, overwritten; entry [i * FK_MAX_THETA + k] is dJ/dtheta_k
  * of instance i for k < n_theta, theta = (coef[0..np-1], D)) and, if lamN is
@@ -235,7 +292,8 @@ fk_status fk_check_flags(fk_plan *p, void *stream, int *flags);
 fk_status fk_adjoint(fk_plan *p, const void *lam0, double *grad, void *lamN,
                      void *stream);
 
-/* Autotuner for batched plans: builds a trial plan for each step layout
+/* Autotuner for batched plans (an engineering addition; the paper has no
+ * counterpart): builds a trial plan for each step layout
  * (fk_options.step_kernel 1..4) of the problems with n_steps replaced by
  * trial_steps (the cost of a step does not depend on n), runs its backward
  * pass twice on stream with the caller's other options, and returns the
@@ -247,7 +305,9 @@ fk_status fk_adjoint(fk_plan *p, const void *lam0, double *grad, void *lamN,
 fk_status fk_tune(const fk_problem *probs, int n_inst, const fk_options *opt, int trial_steps,
                   void *workspace, size_t workspace_bytes, void *stream, fk_tune_result *out);
 
-/* Measurement hook: runs one backward pass from chi without a graph on
+/* Measurement hook (Scheme 1, Section 3.1, timed; the cost model of
+ * Section 3.2.1 names assembly and product): runs one backward pass from chi
+ * without a graph on
  * stream, with HIP events around every kernel launch, and returns the mean
  * duration in milliseconds per launch of each pass kind in ms[4] (host):
  * [0] slope pass, [1] fused step pass, [2] ELL assembly, [3] ELL product
@@ -255,7 +315,8 @@ fk_status fk_tune(const fk_problem *probs, int n_inst, const fk_options *opt, in
  * number of launches timed.  Synchronises stream. */
 fk_status fk_profile_pass(fk_plan *p, double *ms, int *counts, void *stream);
 
-/* Measurement hook for the adjoint: runs fk_adjoint(p, lam0, grad, NULL,
+/* Measurement hook for the adjoint (the reverse sweep of Eq. (e36), timed):
+ * runs fk_adjoint(p, lam0, grad, NULL,
  * stream) with HIP events around every kernel group of the reverse sweep and
  * returns the mean duration in milliseconds per step of each group in ms[5]
  * (host): [0] slope pass of u^{n+1}, [1] transposed step of the nodes

@@ -2435,6 +2435,48 @@ __global__ void __launch_bounds__(kBlock) k_fold_images(PlanDev P, T *__restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// Step-operator hooks: A_n = Q Psi^n of Eq. (e36) as a linear map from the
+// (d + 1) fields [u; g_0; ..; g_{d-1}] (values and nodal slopes, the column
+// blocks of Psi^n) to the active rows, applied to caller data instead of the
+// slope pass' records.
+// ---------------------------------------------------------------------------
+
+// fields x[f * n + i] (f = 0 value, 1 + a slope along axis a) -> records
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_pack_fields(long long n, const T *__restrict__ x,
+                                                        T *__restrict__ packed)
+{
+    constexpr int PS = RecStride<D>::value;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+#pragma unroll
+        for (int f = 0; f < PS; ++f) packed[i * PS + f] = (f <= D) ? x[f * n + i] : T(0);
+}
+
+// records -> fields (inverse of k_pack_fields)
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_unpack_fields(long long n, const T *__restrict__ rec,
+                                                          T *__restrict__ x)
+{
+    constexpr int PS = RecStride<D>::value;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+#pragma unroll
+        for (int f = 0; f <= D; ++f) x[f * n + i] = rec[i * PS + f];
+}
+
+// out = a - b (b may be null: out = a) on active nodes, 0 on all others
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_masked_diff(const unsigned char *__restrict__ cls,
+                                                        long long n, const T *a, const T *b,
+                                                        T *out)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        out[i] = (cls[i] == 0) ? (b ? a[i] - b[i] : a[i]) : T(0);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------

@@ -1188,6 +1188,10 @@ fk_status run_pass(fk_plan *p, const void *u_start, int start, const int *snaps,
     return FK_OK;
 }
 
+// Copies the plan's host tables into the workspace the plan points at
+// (asynchronous on s) and clears the device flags.
+fk_status upload_tables(fk_plan *p, hipStream_t s);
+
 fk_status check_snaps(const fk_plan *p, const int *snaps, int n_snap, int start, const void *u_out)
 {
     if (n_snap < 0) return fail(FK_ERR_ARG, "n_snap < 0");
@@ -1320,6 +1324,17 @@ fk_status fk_plan_set_workspace(fk_plan *p, void *dev_ptr, size_t bytes, void *s
     p->ws = (unsigned char *)dev_ptr;
     p->ckpt_valid = false;
     fill_dev(p);
+    FK_TRY(upload_tables(p, s));
+    FK_HIP(hipStreamSynchronize(s));
+    return FK_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+fk_status upload_tables(fk_plan *p, hipStream_t s)
+{
     auto up = [&](const char *name, const void *src, size_t n) -> fk_status {
         if (n) FK_HIP(hipMemcpyAsync(p->at(name), src, n, hipMemcpyHostToDevice, s));
         return FK_OK;
@@ -1353,9 +1368,12 @@ fk_status fk_plan_set_workspace(fk_plan *p, void *dev_ptr, size_t bytes, void *s
     FK_TRY(up("box_nodes", p->box_nodes.data(), sizeof(int) * p->box_nodes.size()));
     FK_TRY(up("box_work", p->box_work.data(), sizeof(fk::WorkItem) * p->box_work.size()));
     FK_LAUNCH(fk::launch_clear_flags(p->dev, s));
-    FK_HIP(hipStreamSynchronize(s));
     return FK_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 fk_status fk_forward(fk_plan *p, const int *snap_steps, int n_snap, void *u_out, void *stream)
 {
@@ -1388,6 +1406,56 @@ fk_status fk_step(fk_plan *p, int n, const void *u_next, void *u_out, void *stre
     hipStream_t s = (hipStream_t)stream;
     FK_LAUNCH(fk::launch_init_field(p->dev, p->f32, u_out, s));
     return enqueue_step(p, n, u_next, u_out, s);
+}
+
+fk_status fk_apply_step(fk_plan *p, int n, int transpose, const void *x, void *y, void *stream)
+{
+    FK_TRY(need_ws(p));
+    if (!x || !y) return fail(FK_ERR_ARG, "null field");
+    if (n < 0 || n >= p->N) return fail(FK_ERR_ARG, "step %d outside [0, N-1]", n);
+    if (transpose && p->opt.ckpt_every <= 0)
+        return fail(FK_ERR_STATE, "the transposed operator needs a plan created with ckpt_every > 0");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t fb = elt(p) * (size_t)p->n_nodes;
+    void *packed = p->at("packed");
+    // coefficient tables of step n (the slope pass is replaced by caller data)
+    FK_LAUNCH(fk::launch_tables(p->dev, n, s));
+    auto apply = [&](void *out) -> fk_status {
+        FK_LAUNCH(fk::launch_init_field(p->dev, p->f32, out, s));
+        if (p->opt.form == FK_FORM_ELL) {
+            int *cols = (int *)p->at("ell_org");
+            void *vals = p->at("ell_vals"), *em = p->at("ell_em");
+            FK_LAUNCH(fk::launch_assemble_ell(p->dev, p->f32, n, cols, vals, em, s));
+            FK_LAUNCH(fk::launch_ell_apply(p->dev, p->f32, cols, vals, em, packed, out, s));
+        } else {
+            FK_LAUNCH(fk::launch_step_fused(p->dev, p->f32, n, packed, out, s));
+        }
+        return FK_OK;
+    };
+    if (!transpose) {
+        // the step kernels evaluate the affine map [u; g] -> A_n [u; g] + e
+        // (e = exit mass); A_n x is that map at x minus the map at 0
+        void *ya = p->at("uA"), *yb = p->at("uB");
+        FK_LAUNCH(fk::launch_pack_fields(p->dev, p->f32, x, packed, s));
+        FK_TRY(apply(ya));
+        FK_LAUNCH(fk::launch_zero(packed, fb * rec_stride(p->d), s));
+        FK_TRY(apply(yb));
+        FK_LAUNCH(fk::launch_masked_diff(p->dev, p->f32, ya, yb, y, s));
+    } else {
+        // mu = A_n^T lam with lam = y on the active rows: the adjoint step's
+        // scatter; its theta-gradient (zero records) goes to the plan's
+        // gradient buffer and is discarded
+        void *la = p->at("lamA"), *mu = p->at("mu");
+        double *g = (double *)p->at("grad");
+        FK_LAUNCH(fk::launch_zero(packed, fb * rec_stride(p->d), s));
+        FK_LAUNCH(fk::launch_masked_diff(p->dev, p->f32, x, nullptr, la, s));
+        FK_LAUNCH(fk::launch_zero(mu, fb * rec_stride(p->d), s));
+        FK_LAUNCH(fk::launch_zero(g, sizeof(double) * fk::kThetaSlots * p->n_inst, s));
+        FK_LAUNCH(fk::launch_adjoint_step(p->dev, p->f32, n, packed, la, mu, g, s));
+        FK_LAUNCH(fk::launch_unpack_fields(p->dev, p->f32, mu, y, s));
+        FK_LAUNCH(fk::launch_zero(mu, fb * rec_stride(p->d), s));
+    }
+    return FK_OK;
 }
 
 fk_status fk_export_cells(fk_plan *p, int inst, int n, int *cells, unsigned char *exit_flags,

@@ -208,5 +208,13 @@ hipError_t launch_adjoint_slopes_T(const PlanDev &P, bool f32, const void *u, vo
 hipError_t launch_adjoint_init(const PlanDev &P, bool f32, const void *lam0, void *lam,
                                hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+// Step-operator hooks: (d + 1) fields <-> node records; a - b on active nodes
+// and 0 elsewhere (b may be null).
+hipError_t launch_pack_fields(const PlanDev &P, bool f32, const void *x, void *packed,
+                              hipStream_t s);
+hipError_t launch_unpack_fields(const PlanDev &P, bool f32, const void *packed, void *x,
+                                hipStream_t s);
+hipError_t launch_masked_diff(const PlanDev &P, bool f32, const void *a, const void *b, void *out,
+                              hipStream_t s);
 
 }  // namespace fk

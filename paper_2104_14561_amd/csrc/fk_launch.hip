@@ -8,6 +8,7 @@
 
 namespace fk {
 
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -214,6 +215,34 @@ hipError_t launch_adjoint_slopes_T(const PlanDev &P, bool f32, const void *u, vo
             k_adjoint_slopes_T<double, D><<<g, kBlock, 0, s>>>(P, (const double *)u, (double *)mu, (double *)lam_next, runs, r0, nr);
             k_fold_images<double, D><<<g, kBlock, 0, s>>>(P, (double *)lam_next, runs, r0, nr);
         });
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_fields(const PlanDev &P, bool f32, const void *x, void *packed,
+                              hipStream_t s)
+{
+    FK_DISPATCH_D(P.d,
+        if (f32) k_pack_fields<float, D><<<flat_grid(P.n_nodes), kBlock, 0, s>>>(P.n_nodes, (const float *)x, (float *)packed);
+        else k_pack_fields<double, D><<<flat_grid(P.n_nodes), kBlock, 0, s>>>(P.n_nodes, (const double *)x, (double *)packed));
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_fields(const PlanDev &P, bool f32, const void *packed, void *x,
+                                hipStream_t s)
+{
+    FK_DISPATCH_D(P.d,
+        if (f32) k_unpack_fields<float, D><<<flat_grid(P.n_nodes), kBlock, 0, s>>>(P.n_nodes, (const float *)packed, (float *)x);
+        else k_unpack_fields<double, D><<<flat_grid(P.n_nodes), kBlock, 0, s>>>(P.n_nodes, (const double *)packed, (double *)x));
+    return hipGetLastError();
+}
+
+hipError_t launch_masked_diff(const PlanDev &P, bool f32, const void *a, const void *b, void *out,
+                              hipStream_t s)
+{
+    if (f32)
+        k_masked_diff<float><<<flat_grid(P.n_nodes), kBlock, 0, s>>>(P.chi, P.n_nodes, (const float *)a, (const float *)b, (float *)out);
+    else
+        k_masked_diff<double><<<flat_grid(P.n_nodes), kBlock, 0, s>>>(P.chi, P.n_nodes, (const double *)a, (const double *)b, (double *)out);
     return hipGetLastError();
 }
 

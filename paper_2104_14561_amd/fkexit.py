@@ -28,7 +28,7 @@ MAX_THETA = 8
 
 EXPORTED = ["fk_last_error", "fk_version", "fk_gh_rule", "fk_plan_create", "fk_plan_destroy",
             "fk_plan_get_info", "fk_plan_layout", "fk_plan_set_workspace", "fk_forward",
-            "fk_forward_from", "fk_step", "fk_export_cells", "fk_export_ell",
+            "fk_forward_from", "fk_step", "fk_apply_step", "fk_export_cells", "fk_export_ell",
             "fk_check_flags", "fk_adjoint", "fk_profile_pass", "fk_profile_adjoint", "fk_tune"]
 
 
@@ -97,6 +97,7 @@ def load(path: str = LIB_PATH):
         "fk_forward": (ctypes.c_int, [vp, ip, ctypes.c_int, vp, vp]),
         "fk_forward_from": (ctypes.c_int, [vp, vp, ctypes.c_int, ip, ctypes.c_int, vp, vp]),
         "fk_step": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
+        "fk_apply_step": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]),
         "fk_export_cells": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]),
         "fk_export_ell": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp, vp]),
         "fk_check_flags": (ctypes.c_int, [vp, vp, ip]),
@@ -287,6 +288,22 @@ class Plan:
         out = torch.empty(self.n_nodes, dtype=self.dtype, device=self.device)
         _check(load().fk_step(self._h, int(n), ctypes.c_void_p(_ptr(u_next)),
                               ctypes.c_void_p(_ptr(out)), ctypes.c_void_p(_stream(stream))))
+        return out
+
+    def apply_step(self, n: int, x, transpose: bool = False, stream=None):
+        """fk_apply_step: A_n x for x = (d + 1) packed fields [u; g_0; ..]
+        (shape [d + 1, n_nodes]) -> one field, or A_n^T x for one field x ->
+        [d + 1, n_nodes] (transpose=True)."""
+        import torch
+        d = int(self.info.d)
+        x = x.to(self.device, self.dtype).contiguous()
+        if transpose:
+            out = torch.empty((d + 1, self.n_nodes), dtype=self.dtype, device=self.device)
+        else:
+            out = torch.empty(self.n_nodes, dtype=self.dtype, device=self.device)
+        _check(load().fk_apply_step(self._h, int(n), int(bool(transpose)),
+                                    ctypes.c_void_p(_ptr(x)), ctypes.c_void_p(_ptr(out)),
+                                    ctypes.c_void_p(_stream(stream))))
         return out
 
     def export_cells(self, inst: int, n: int, stream=None):
