@@ -44,6 +44,8 @@ extern "C" {
 #define FK_ABI_VERSION 1
 #define FK_MAX_DIM 3
 #define FK_MAX_THETA 8
+/* Bytes of the library's static device buffer used by fk_forward_static. */
+#define FK_STATIC_SCRATCH_BYTES (64u << 20)
 
 typedef enum {
     FK_OK = 0,
@@ -215,6 +217,24 @@ fk_status fk_plan_set_workspace(fk_plan *p, void *dev_ptr, size_t bytes, void *s
  * FK_ERR_HIP. */
 fk_status fk_forward(fk_plan *p, const int *snap_steps, int n_snap, void *u_out,
                      void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): fk_forward without
+ * a caller workspace.  The plan's tables, the ping-pong fields and the node
+ * records live in one static device array of FK_STATIC_SCRATCH_BYTES bytes
+ * per device, held until the process ends; the call allocates and frees
+ * nothing.  Same outputs as fk_forward (u_out device, caller-owned; snapshot
+ * rules alike) and the same kernels, without a graph and without adjoint
+ * checkpoints; a plan workspace, if set, is neither needed nor touched.  The
+ * tables are copied from host memory on every call (the array keeps the last
+ * call's contents, and every plan on the device shares it), so calls that
+ * overlap on one device race: serialise them (one stream, or
+ * synchronisation).  Non-finite values are not reported (fk_check_flags reads
+ * the workspace's flags).  Errors: FK_ERR_WORKSPACE when the plan's forward
+ * workspace exceeds FK_STATIC_SCRATCH_BYTES, FK_ERR_ARG as fk_forward,
+ * FK_ERR_HIP. */
+fk_status fk_forward_static(fk_plan *p, const int *snap_steps, int n_snap, void *u_out,
+                            void *stream);
 
 /* Backward pass of Scheme 1 (Section 3.1) resumed from a caller state
  * u_start = u^{start_step} (device, one field, read only); snapshots with

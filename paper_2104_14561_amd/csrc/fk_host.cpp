@@ -194,6 +194,7 @@ struct fk_plan {
     // workspace
     std::map<std::string, Region> reg;
     size_t ws_bytes = 0;
+    size_t ws_fwd_bytes = 0;   // prefix of the workspace that a forward pass uses
     unsigned char *ws = nullptr;
     fk::PlanDev dev{};
     // graph cache
@@ -965,6 +966,7 @@ fk_status build_plan(fk_plan *p)
         add_region(p, "ell_vals", elt(p) * (size_t)std::max<long long>(p->ell_total, 1));
         add_region(p, "ell_em", elt(p) * (size_t)std::max<long long>(p->n_active, 1));
     }
+    p->ws_fwd_bytes = p->ws_bytes;   // tables, fields and records of the forward pass
     if (p->opt.ckpt_every > 0) {
         const int K = p->opt.ckpt_every;
         p->n_ckpt = (p->N - 1) / K + 2;
@@ -1327,6 +1329,32 @@ fk_status fk_plan_set_workspace(fk_plan *p, void *dev_ptr, size_t bytes, void *s
     FK_TRY(upload_tables(p, s));
     FK_HIP(hipStreamSynchronize(s));
     return FK_OK;
+}
+
+fk_status fk_forward_static(fk_plan *p, const int *snap_steps, int n_snap, void *u_out,
+                            void *stream)
+{
+    if (!p) return fail(FK_ERR_ARG, "null plan");
+    FK_TRY(check_snaps(p, snap_steps, n_snap, p->N, u_out));
+    if (p->ws_fwd_bytes > (size_t)FK_STATIC_SCRATCH_BYTES)
+        return fail(FK_ERR_WORKSPACE,
+                    "plan needs %zu bytes of forward workspace, the static scratch holds %zu",
+                    p->ws_fwd_bytes, (size_t)FK_STATIC_SCRATCH_BYTES);
+    void *scr = nullptr;
+    hipError_t e = fk::static_scratch(&scr);
+    if (e != hipSuccess) return fail(FK_ERR_HIP, "static scratch: %s", hipGetErrorString(e));
+    hipStream_t s = (hipStream_t)stream;
+    // run on the static scratch, then give the plan back its own workspace
+    // (host-side pointers only: the caller's workspace is not touched)
+    unsigned char *saved_ws = p->ws;
+    const fk::PlanDev saved_dev = p->dev;
+    p->ws = (unsigned char *)scr;
+    fill_dev(p);
+    fk_status st = upload_tables(p, s);
+    if (st == FK_OK) st = enqueue_pass(p, nullptr, p->N, snap_steps, n_snap, u_out, s, false);
+    p->ws = saved_ws;
+    p->dev = saved_dev;
+    return st;
 }
 
 }  // extern "C"

@@ -208,6 +208,10 @@ hipError_t launch_adjoint_slopes_T(const PlanDev &P, bool f32, const void *u, vo
 hipError_t launch_adjoint_init(const PlanDev &P, bool f32, const void *lam0, void *lam,
                                hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+// Device address of the static scratch array on the current device (taken
+// with hipGetSymbolAddress on the first call per device).
+hipError_t static_scratch(void **out);
+
 // Step-operator hooks: (d + 1) fields <-> node records; a - b on active nodes
 // and 0 elsewhere (b may be null).
 hipError_t launch_pack_fields(const PlanDev &P, bool f32, const void *x, void *packed,

@@ -5,9 +5,40 @@
 // the plan's Q* has a compiled specialisation and fall back to the lane-group
 // kernels otherwise.
 #include "fk_device.h"
+#include "fkexit.h"
+
+#include <mutex>
 
 namespace fk {
 
+// ---------------------------------------------------------------------------
+// Fixed device buffer of the allocation-free forward pass (fk_forward_static):
+// one copy per device, held until the process ends.  Host code never uses the
+// array's name as an address: the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[FK_STATIC_SCRATCH_BYTES];
+
+hipError_t static_scratch(void **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
 
 // ---------------------------------------------------------------------------
 // Launchers

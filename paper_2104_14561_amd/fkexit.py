@@ -28,7 +28,7 @@ MAX_THETA = 8
 
 EXPORTED = ["fk_last_error", "fk_version", "fk_gh_rule", "fk_plan_create", "fk_plan_destroy",
             "fk_plan_get_info", "fk_plan_layout", "fk_plan_set_workspace", "fk_forward",
-            "fk_forward_from", "fk_step", "fk_apply_step", "fk_export_cells", "fk_export_ell",
+            "fk_forward_from", "fk_forward_static", "fk_step", "fk_apply_step", "fk_export_cells", "fk_export_ell",
             "fk_check_flags", "fk_adjoint", "fk_profile_pass", "fk_profile_adjoint", "fk_tune"]
 
 
@@ -96,6 +96,7 @@ def load(path: str = LIB_PATH):
         "fk_plan_set_workspace": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
         "fk_forward": (ctypes.c_int, [vp, ip, ctypes.c_int, vp, vp]),
         "fk_forward_from": (ctypes.c_int, [vp, vp, ctypes.c_int, ip, ctypes.c_int, vp, vp]),
+        "fk_forward_static": (ctypes.c_int, [vp, ip, ctypes.c_int, vp, vp]),
         "fk_step": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
         "fk_apply_step": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]),
         "fk_export_cells": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]),
@@ -270,6 +271,17 @@ class Plan:
         _check(load().fk_forward(self._h, sn.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                                  len(sn), ctypes.c_void_p(_ptr(out)),
                                  ctypes.c_void_p(_stream(stream))))
+        return out
+
+    def forward_static(self, snaps: Sequence[int] = (0,), stream=None):
+        """fk_forward_static: the backward pass on the library's static
+        device buffer (no workspace needed; see include/fkexit.h)."""
+        import torch
+        sn = np.ascontiguousarray(snaps, dtype=np.int32)
+        out = torch.empty((len(sn), self.n_nodes), dtype=self.dtype, device=self.device)
+        _check(load().fk_forward_static(self._h, sn.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                        len(sn), ctypes.c_void_p(_ptr(out)),
+                                        ctypes.c_void_p(_stream(stream))))
         return out
 
     def forward_from(self, u_start, start_step: int, snaps: Sequence[int] = (0,), stream=None):
