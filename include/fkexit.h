@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define FK_ABI_VERSION 1
+#define FK_ABI_VERSION 2
 #define FK_MAX_DIM 3
 #define FK_MAX_THETA 8
 /* Bytes of the library's static device buffer used by fk_forward_static. */
@@ -109,6 +109,11 @@ typedef struct {
     double dt;             /* > 0 */
     int n_steps;           /* N >= 1 */
     double t0;             /* step n evaluates coefficients at t0 + n dt */
+    int force_f64;         /* nonzero in an FK_PREC_F32 plan: this instance is
+                              computed entirely in FP64 (its fields are still
+                              delivered and taken in FP32); ignored in FP64
+                              plans.  fk_probe_precision picks the instances
+                              whose FP32 result misses a tolerance. */
 } fk_problem;
 
 typedef struct {
@@ -182,7 +187,10 @@ fk_status fk_gh_rule(int q, double *nodes, double *weights);
  * grids and parameters may differ (batched, uneven grids).  Host arrays are
  * copied.  opt may be NULL (defaults: F64, fused, no graph, no adjoint).
  * Errors: FK_ERR_ARG (invalid problem: its message names the instance and the
- * field), FK_ERR_UNSUPPORTED (a step layout not compiled for gh_q). */
+ * field), FK_ERR_UNSUPPORTED (a step layout not compiled for gh_q; instances
+ * forced to FP64 in an FK_FORM_ELL plan).  An FP32 plan with instances forced
+ * to FP64 computes them in an internal FP64 plan that reads and writes this
+ * plan's fields (every call below handles both, in stream order). */
 fk_status fk_plan_create(const fk_problem *probs, int n_inst, const fk_options *opt,
                          fk_plan **out);
 
@@ -232,7 +240,7 @@ fk_status fk_forward(fk_plan *p, const int *snap_steps, int n_snap, void *u_out,
  * synchronisation).  Non-finite values are not reported (fk_check_flags reads
  * the workspace's flags).  Errors: FK_ERR_WORKSPACE when the plan's forward
  * workspace exceeds FK_STATIC_SCRATCH_BYTES, FK_ERR_ARG as fk_forward,
- * FK_ERR_HIP. */
+ * FK_ERR_UNSUPPORTED (a plan with instances forced to FP64), FK_ERR_HIP. */
 fk_status fk_forward_static(fk_plan *p, const int *snap_steps, int n_snap, void *u_out,
                             void *stream);
 
@@ -266,7 +274,8 @@ fk_status fk_step(fk_plan *p, int n, const void *u_next, void *u_out, void *stre
  *     Needs a plan created with ckpt_every > 0 (FK_ERR_STATE otherwise).
  * Uses the plan's ping-pong and record buffers: adjoint checkpoints stay
  * valid.  Errors: FK_ERR_ARG (n outside [0, N-1], null field),
- * FK_ERR_STATE, FK_ERR_HIP. */
+ * FK_ERR_STATE, FK_ERR_UNSUPPORTED (a plan with instances forced to FP64),
+ * FK_ERR_HIP. */
 fk_status fk_apply_step(fk_plan *p, int n, int transpose, const void *x, void *y, void *stream);
 
 /* Landing points of step n (Eq. (e31)) located in the grid, for instance
@@ -325,9 +334,27 @@ fk_status fk_adjoint(fk_plan *p, const void *lam0, double *grad, void *lamN,
 fk_status fk_tune(const fk_problem *probs, int n_inst, const fk_options *opt, int trial_steps,
                   void *workspace, size_t workspace_bytes, void *stream, fk_tune_result *out);
 
+/* Precision probe for FP32 plans (the precision split is an engineering
+ * addition; the error of every FP32 result against FP64 is what it bounds):
+ * runs the backward pass of the problems once in FP64 and once with
+ * FK_PREC_F32 (fused form, no graph unless opt->use_graph, opt's step layout)
+ * and returns per instance diff[i] = max over the instance's nodes of
+ * |u^0 (FP64) - u^0 (FP32)| and force_f64[i] = (diff[i] > tol / 2) (host
+ * outputs of length n_inst), ready for fk_problem.force_f64: an instance
+ * whose scheme amplifies the FP32 rounding beyond half the tolerance is then
+ * computed in FP64 (the other half is left for the FP64 evaluation's own
+ * rounding).  force_f64 of the inputs is ignored.  With workspace == NULL
+ * only *bytes_needed is written (device bytes, 256-byte aligned); otherwise
+ * workspace (device, caller-owned, contents destroyed) must hold that many.
+ * Synchronises stream.  Errors: FK_ERR_ARG, FK_ERR_WORKSPACE, plan-creation
+ * and HIP errors. */
+fk_status fk_probe_precision(const fk_problem *probs, int n_inst, const fk_options *opt,
+                             double tol, void *workspace, size_t workspace_bytes, void *stream,
+                             size_t *bytes_needed, int *force_f64, double *diff);
+
 /* Measurement hook (Scheme 1, Section 3.1, timed; the cost model of
- * Section 3.2.1 names assembly and product): runs one backward pass from chi
- * without a graph on
+ * Section 3.2.1 names assembly and product; instances forced to FP64 are not
+ * timed): runs one backward pass from chi without a graph on
  * stream, with HIP events around every kernel launch, and returns the mean
  * duration in milliseconds per launch of each pass kind in ms[4] (host):
  * [0] slope pass, [1] fused step pass, [2] ELL assembly, [3] ELL product

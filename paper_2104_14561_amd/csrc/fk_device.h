@@ -2436,6 +2436,53 @@ __global__ void __launch_bounds__(kBlock) k_fold_images(PlanDev P, T *__restrict
 }
 
 // ---------------------------------------------------------------------------
+// Fields of an FP64 sub-plan in the layout (and precision) of its FP32 parent
+// plan.  items: every node of every instance (node runs).
+// ---------------------------------------------------------------------------
+template <bool OUT>
+__global__ void __launch_bounds__(kBlock) k_convert(PlanDev P, const WorkItem *__restrict__ items,
+                                                    int n_items, double *__restrict__ u,
+                                                    float *__restrict__ f)
+{
+    const WorkRange wr = work_range(0, n_items);
+    for (int w = wr.begin; w < wr.end; w += wr.step) {
+        const WorkItem it = items[w];
+        if ((int)threadIdx.x >= it.count) continue;
+        const DevInst &I = P.inst[it.inst];
+        const long long j = it.first + threadIdx.x;
+        if (OUT) f[I.out_off + j] = (float)u[I.node_off + j];
+        else u[I.node_off + j] = (double)f[I.out_off + j];
+    }
+}
+
+// Largest |a - b| over each instance's nodes (a wave-level maximum, then one
+// atomic per wave on the bit pattern, which orders like the value for
+// non-negative doubles; a NaN compares above every number).
+__global__ void __launch_bounds__(kBlock) k_inst_maxdiff(PlanDev P, const WorkItem *__restrict__ items,
+                                                         int n_items, const double *__restrict__ a,
+                                                         const float *__restrict__ b,
+                                                         unsigned long long *__restrict__ out)
+{
+    const WorkRange wr = work_range(0, n_items);
+    for (int w = wr.begin; w < wr.end; w += wr.step) {
+        const WorkItem it = items[w];
+        const DevInst &I = P.inst[it.inst];
+        double v = 0.0;
+        if ((int)threadIdx.x < it.count) {
+            const long long j = I.node_off + it.first + threadIdx.x;
+            v = fabs(a[j] - (double)b[j]);
+            if (v != v) v = __longlong_as_double(0x7ff8000000000000LL);
+        }
+        unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(bits, off, 64);
+            bits = o > bits ? o : bits;
+        }
+        if ((threadIdx.x % 64) == 0 && bits) atomicMax(&out[it.inst], bits);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Step-operator hooks: A_n = Q Psi^n of Eq. (e36) as a linear map from the
 // (d + 1) fields [u; g_0; ..; g_{d-1}] (values and nodal slopes, the column
 // blocks of Psi^n) to the active rows, applied to caller data instead of the

@@ -206,6 +206,16 @@ struct fk_plan {
     hipStream_t ckpt_stream = nullptr;
     std::string gkey;
     int n_ckpt = 0;
+    // instances computed in FP64 inside an FP32 plan (fk_problem.force_f64):
+    // they stay in this plan's layout without active nodes, and a child FP64
+    // plan over them reads and writes this plan's fields through conversion
+    // kernels
+    std::vector<unsigned char> skip;   // per instance: handled by the child
+    fk_plan *sub = nullptr;            // the child
+    std::vector<int> sub_inst;         // child instance k = instance sub_inst[k]
+    bool conv = false;                 // this is a child: fields of the parent
+    long long out_n_nodes = 0;         // child: nodes of the parent's fields
+    std::vector<int> parent_inst;      // child: parent index of each instance
 
     void *at(const char *name) const { return ws + reg.at(name).off; }
 };
@@ -438,7 +448,9 @@ fk_status build_plan(fk_plan *p)
         I.S = std::sqrt(2.0 * pr.D) * sq;
         I.dSdD = pr.D > 0 ? I.S / (2.0 * pr.D) : 0.0;
         I.node_off = p->n_nodes;
+        I.out_off = p->n_nodes;
         I.act_off = p->n_active;
+        const bool skip_i = !p->skip.empty() && p->skip[i];
 
         // node classes: 0 active, 1 exit, 2 image of active, 3 image of exit
         std::vector<unsigned char> c(J);
@@ -451,7 +463,7 @@ fk_status build_plan(fk_plan *p)
             for (int a = 0; a < pr.d; ++a)
                 if (pr.ax[a].periodic && idx[a] == pr.ax[a].n - 1) { image = true; idx[a] = 0; }
             for (int a = 0; a < pr.d; ++a) x[a] = pr.ax[a].nodes[idx[a]];
-            const bool ex = exit_point(pr, x);
+            const bool ex = skip_i || exit_point(pr, x);
             c[j] = (unsigned char)((image ? 2 : 0) | (ex ? 1 : 0));
         }
         int na = 0;
@@ -1123,16 +1135,23 @@ fk_status enqueue_pass(fk_plan *p, const void *u_start, int start, const int *sn
     FK_LAUNCH(fk::launch_clear_flags(p->dev, s));
     // both buffers hold 1 on exit nodes (and chi elsewhere)
     FK_LAUNCH(fk::launch_init_field(p->dev, p->f32, ub, s));
-    if (u_start) {
+    if (u_start && p->conv) {
+        FK_LAUNCH(fk::launch_convert_in(p->dev, (const float *)u_start, (double *)ua, s));
+    } else if (u_start) {
         FK_HIP(hipMemcpyAsync(ua, u_start, fb, hipMemcpyDeviceToDevice, s));
     } else {
         FK_LAUNCH(fk::launch_init_field(p->dev, p->f32, ua, s));
     }
     auto snap_copy = [&](int n, const void *u) -> fk_status {
-        for (int k = 0; k < n_snap; ++k)
-            if (snaps[k] == n)
+        for (int k = 0; k < n_snap; ++k) {
+            if (snaps[k] != n) continue;
+            if (p->conv)
+                FK_LAUNCH(fk::launch_convert_out(p->dev, (const double *)u,
+                                                 (float *)u_out + (size_t)k * p->out_n_nodes, s));
+            else
                 FK_HIP(hipMemcpyAsync((unsigned char *)u_out + (size_t)k * fb, u, fb,
                                       hipMemcpyDeviceToDevice, s));
+        }
         return FK_OK;
     };
     auto ckpt_copy = [&](int n, const void *u) -> fk_status {
@@ -1252,11 +1271,21 @@ fk_status fk_plan_create(const fk_problem *probs, int n_inst, const fk_options *
     if (o.ckpt_every > 0)
         for (int i = 0; i < n_inst; ++i)
             if (!(probs[i].D > 0)) return fail(FK_ERR_ARG, "adjoint needs D > 0 (instance %d)", i);
+    std::vector<int> forced;
+    if (o.precision == FK_PREC_F32)
+        for (int i = 0; i < n_inst; ++i)
+            if (probs[i].force_f64) forced.push_back(i);
+    if (!forced.empty() && o.form != FK_FORM_FUSED)
+        return fail(FK_ERR_UNSUPPORTED, "instances forced to FP64 need the fused form");
     fk_plan *p = new (std::nothrow) fk_plan();
     if (!p) return fail(FK_ERR_ARG, "out of host memory");
     p->opt = o;
     p->f32 = o.precision == FK_PREC_F32;
     p->n_inst = n_inst;
+    if (!forced.empty()) {
+        p->skip.assign(n_inst, 0);
+        for (int i : forced) p->skip[i] = 1;
+    }
     p->probs.assign(probs, probs + n_inst);
     for (auto &pr : p->probs)
         for (int ax = 0; ax < 3; ++ax) pr.ax[ax].nodes = nullptr;   // copied into coords
@@ -1269,6 +1298,31 @@ fk_status fk_plan_create(const fk_problem *probs, int n_inst, const fk_options *
         delete p;
         return st;
     }
+    if (!forced.empty()) {
+        std::vector<fk_problem> sp;
+        for (int i : forced) {
+            sp.push_back(probs[i]);
+            sp.back().force_f64 = 0;
+        }
+        fk_options so = o;
+        so.precision = FK_PREC_F64;
+        fk_plan *c = nullptr;
+        st = fk_plan_create(sp.data(), (int)sp.size(), &so, &c);
+        if (st != FK_OK) {
+            delete p;
+            return st;
+        }
+        c->conv = true;
+        c->out_n_nodes = p->n_nodes;
+        c->parent_inst = forced;
+        for (size_t k = 0; k < forced.size(); ++k) {
+            c->inst[k].out_off = p->inst[forced[k]].node_off;
+            p->act_count[forced[k]] = c->act_count[k];
+        }
+        p->sub = c;
+        p->sub_inst = forced;
+        add_region(p, "sub_ws", c->ws_bytes);
+    }
     *out = p;
     return FK_OK;
 }
@@ -1276,6 +1330,7 @@ fk_status fk_plan_create(const fk_problem *probs, int n_inst, const fk_options *
 void fk_plan_destroy(fk_plan *p)
 {
     if (!p) return;
+    fk_plan_destroy(p->sub);
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     delete p;
@@ -1297,6 +1352,11 @@ fk_status fk_plan_get_info(const fk_plan *p, fk_plan_info *info)
     info->adj_point_nodes = (int64_t)p->adj.fw_nodes.size();
     info->adj_box_nodes = (int64_t)p->adj.box_nodes.size();
     info->workspace_bytes = p->ws_bytes;
+    if (p->sub) {
+        info->n_active += p->sub->n_active;
+        info->adj_point_nodes += (int64_t)p->sub->adj.fw_nodes.size();
+        info->adj_box_nodes += (int64_t)p->sub->adj.box_nodes.size();
+    }
     return FK_OK;
 }
 
@@ -1328,6 +1388,7 @@ fk_status fk_plan_set_workspace(fk_plan *p, void *dev_ptr, size_t bytes, void *s
     fill_dev(p);
     FK_TRY(upload_tables(p, s));
     FK_HIP(hipStreamSynchronize(s));
+    if (p->sub) FK_TRY(fk_plan_set_workspace(p->sub, p->at("sub_ws"), p->sub->ws_bytes, stream));
     return FK_OK;
 }
 
@@ -1336,6 +1397,7 @@ fk_status fk_forward_static(fk_plan *p, const int *snap_steps, int n_snap, void 
 {
     if (!p) return fail(FK_ERR_ARG, "null plan");
     FK_TRY(check_snaps(p, snap_steps, n_snap, p->N, u_out));
+    if (p->sub) return fail(FK_ERR_UNSUPPORTED, "plans with instances forced to FP64");
     if (p->ws_fwd_bytes > (size_t)FK_STATIC_SCRATCH_BYTES)
         return fail(FK_ERR_WORKSPACE,
                     "plan needs %zu bytes of forward workspace, the static scratch holds %zu",
@@ -1408,11 +1470,13 @@ fk_status fk_forward(fk_plan *p, const int *snap_steps, int n_snap, void *u_out,
     FK_TRY(need_ws(p));
     FK_TRY(check_snaps(p, snap_steps, n_snap, p->N, u_out));
     // a plan built for the adjoint stores its checkpoints on the way
-    const bool store = p->opt.ckpt_every > 0;
-    p->ckpt_valid = false;
-    FK_TRY(run_pass(p, nullptr, p->N, snap_steps, n_snap, u_out, (hipStream_t)stream, store));
-    p->ckpt_valid = store;
-    p->ckpt_stream = (hipStream_t)stream;
+    for (fk_plan *q = p; q; q = q->sub) {
+        const bool store = q->opt.ckpt_every > 0;
+        q->ckpt_valid = false;
+        FK_TRY(run_pass(q, nullptr, q->N, snap_steps, n_snap, u_out, (hipStream_t)stream, store));
+        q->ckpt_valid = store;
+        q->ckpt_stream = (hipStream_t)stream;
+    }
     return FK_OK;
 }
 
@@ -1423,7 +1487,9 @@ fk_status fk_forward_from(fk_plan *p, const void *u_start, int start_step, const
     if (!u_start) return fail(FK_ERR_ARG, "null start state");
     if (start_step < 0 || start_step > p->N) return fail(FK_ERR_ARG, "start_step outside [0, N]");
     FK_TRY(check_snaps(p, snap_steps, n_snap, start_step, u_out));
-    return run_pass(p, u_start, start_step, snap_steps, n_snap, u_out, (hipStream_t)stream, false);
+    for (fk_plan *q = p; q; q = q->sub)
+        FK_TRY(run_pass(q, u_start, start_step, snap_steps, n_snap, u_out, (hipStream_t)stream, false));
+    return FK_OK;
 }
 
 fk_status fk_step(fk_plan *p, int n, const void *u_next, void *u_out, void *stream)
@@ -1433,7 +1499,15 @@ fk_status fk_step(fk_plan *p, int n, const void *u_next, void *u_out, void *stre
     if (n < 0 || n >= p->N) return fail(FK_ERR_ARG, "step %d outside [0, N-1]", n);
     hipStream_t s = (hipStream_t)stream;
     FK_LAUNCH(fk::launch_init_field(p->dev, p->f32, u_out, s));
-    return enqueue_step(p, n, u_next, u_out, s);
+    FK_TRY(enqueue_step(p, n, u_next, u_out, s));
+    if (fk_plan *c = p->sub) {
+        double *ua = (double *)c->at("uA"), *ub = (double *)c->at("uB");
+        FK_LAUNCH(fk::launch_convert_in(c->dev, (const float *)u_next, ua, s));
+        FK_LAUNCH(fk::launch_init_field(c->dev, false, ub, s));
+        FK_TRY(enqueue_step(c, n, ua, ub, s));
+        FK_LAUNCH(fk::launch_convert_out(c->dev, ub, (float *)u_out, s));
+    }
+    return FK_OK;
 }
 
 fk_status fk_apply_step(fk_plan *p, int n, int transpose, const void *x, void *y, void *stream)
@@ -1443,6 +1517,7 @@ fk_status fk_apply_step(fk_plan *p, int n, int transpose, const void *x, void *y
     if (n < 0 || n >= p->N) return fail(FK_ERR_ARG, "step %d outside [0, N-1]", n);
     if (transpose && p->opt.ckpt_every <= 0)
         return fail(FK_ERR_STATE, "the transposed operator needs a plan created with ckpt_every > 0");
+    if (p->sub) return fail(FK_ERR_UNSUPPORTED, "plans with instances forced to FP64");
     hipStream_t s = (hipStream_t)stream;
     const size_t fb = elt(p) * (size_t)p->n_nodes;
     void *packed = p->at("packed");
@@ -1493,6 +1568,9 @@ fk_status fk_export_cells(fk_plan *p, int inst, int n, int *cells, unsigned char
     if (inst < 0 || inst >= p->n_inst) return fail(FK_ERR_ARG, "instance out of range");
     if (n < 0 || n >= p->N) return fail(FK_ERR_ARG, "step outside [0, N-1]");
     if (!cells || !exit_flags) return fail(FK_ERR_ARG, "null output");
+    if (p->sub)
+        for (size_t k = 0; k < p->sub_inst.size(); ++k)
+            if (p->sub_inst[k] == inst) return fk_export_cells(p->sub, (int)k, n, cells, exit_flags, stream);
     FK_LAUNCH(fk::launch_tables(p->dev, n, (hipStream_t)stream));
     FK_LAUNCH(fk::launch_export_cells(p->dev, inst, n, cells, exit_flags, (hipStream_t)stream));
     return FK_OK;
@@ -1523,6 +1601,12 @@ fk_status fk_check_flags(fk_plan *p, void *stream, int *flags)
     FK_HIP(hipMemcpyAsync(&h, p->at("flags"), sizeof(int), hipMemcpyDeviceToHost, s));
     FK_HIP(hipStreamSynchronize(s));
     FK_LAUNCH(fk::launch_clear_flags(p->dev, s));
+    if (p->sub) {
+        int hs = 0;
+        fk_status st = fk_check_flags(p->sub, stream, &hs);
+        if (st != FK_OK && st != FK_ERR_NONFINITE && st != FK_ERR_UNSUPPORTED) return st;
+        h |= hs;
+    }
     *flags = h;
     if (h & 1) return fail(FK_ERR_NONFINITE, "a non-finite value was produced");
     if (h & 2) return fail(FK_ERR_UNSUPPORTED, "a landing point fell outside the ELL row box");
@@ -1562,7 +1646,7 @@ fk_status fk_adjoint(fk_plan *p, const void *lam0, double *grad, void *lamN, voi
     unsigned char *seg = (unsigned char *)p->at("seg");
     void *packed = p->at("packed");
     FK_LAUNCH(fk::launch_zero(g, sizeof(double) * fk::kThetaSlots * p->n_inst, s));
-    FK_LAUNCH(fk::launch_adjoint_init(p->dev, p->f32, lam0, la, s));
+    FK_LAUNCH(fk::launch_adjoint_init(p->dev, p->f32, lam0, la, s, p->conv));
     // the per-step passes touch only the nodes a step can reach and leave mu
     // clear behind them: clear mu and the second lam buffer once
     FK_LAUNCH(fk::launch_zero(mu, fb * rec_stride(p->d), s));
@@ -1602,9 +1686,19 @@ fk_status fk_adjoint(fk_plan *p, const void *lam0, double *grad, void *lamN, voi
             std::swap(la, lb);
         }
     }
+    if (p->conv) {
+        // child: gradient rows and dJ/du^N into the parent's outputs
+        for (int k = 0; k < p->n_inst; ++k)
+            FK_HIP(hipMemcpyAsync(grad + (size_t)p->parent_inst[k] * fk::kThetaSlots,
+                                  g + (size_t)k * fk::kThetaSlots, sizeof(double) * fk::kThetaSlots,
+                                  hipMemcpyDeviceToDevice, s));
+        if (lamN) FK_LAUNCH(fk::launch_convert_out(p->dev, (const double *)la, (float *)lamN, s));
+        return FK_OK;
+    }
     FK_HIP(hipMemcpyAsync(grad, g, sizeof(double) * fk::kThetaSlots * p->n_inst,
                           hipMemcpyDeviceToDevice, s));
     if (lamN) FK_HIP(hipMemcpyAsync(lamN, la, fb, hipMemcpyDeviceToDevice, s));
+    if (p->sub) FK_TRY(fk_adjoint(p->sub, lam0, grad, lamN, stream));
     return FK_OK;
 }
 
@@ -1725,6 +1819,65 @@ fk_status fk_tune(const fk_problem *probs, int n_inst, const fk_options *opt, in
     }
     if (out->step_kernel == 0) return fail(FK_ERR_UNSUPPORTED, "no step layout could be built");
     return FK_OK;
+}
+
+fk_status fk_probe_precision(const fk_problem *probs, int n_inst, const fk_options *opt,
+                             double tol, void *workspace, size_t workspace_bytes, void *stream,
+                             size_t *bytes_needed, int *force_f64, double *diff)
+{
+    if (!probs || n_inst < 1) return fail(FK_ERR_ARG, "null problems");
+    if (!(tol > 0)) return fail(FK_ERR_ARG, "tol must be > 0");
+    if (!workspace && !bytes_needed) return fail(FK_ERR_ARG, "null workspace and size output");
+    if (workspace && (!force_f64 || !diff)) return fail(FK_ERR_ARG, "null outputs");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<fk_problem> pr(probs, probs + n_inst);
+    for (fk_problem &q : pr) q.force_f64 = 0;
+    fk_options o{};
+    if (opt) o = *opt;
+    o.form = FK_FORM_FUSED;
+    o.ckpt_every = 0;
+    fk_plan *p64 = nullptr, *p32 = nullptr;
+    o.precision = FK_PREC_F64;
+    FK_TRY(fk_plan_create(pr.data(), n_inst, &o, &p64));
+    o.precision = FK_PREC_F32;
+    fk_status st = fk_plan_create(pr.data(), n_inst, &o, &p32);
+    if (st != FK_OK) {
+        fk_plan_destroy(p64);
+        return st;
+    }
+    const size_t nn = (size_t)p64->n_nodes;
+    const size_t o32 = align_up(p64->ws_bytes), of64 = o32 + align_up(p32->ws_bytes);
+    const size_t of32 = of64 + align_up(8 * nn), odiff = of32 + align_up(4 * nn);
+    const size_t need = odiff + align_up(8 * (size_t)n_inst);
+    if (bytes_needed) *bytes_needed = need;
+    if (workspace) {
+        unsigned char *ws = (unsigned char *)workspace;
+        if (((uintptr_t)ws) % kAlign) st = fail(FK_ERR_ARG, "workspace must be 256-byte aligned");
+        else if (workspace_bytes < need)
+            st = fail(FK_ERR_WORKSPACE, "probe needs %zu workspace bytes, %zu given", need,
+                      workspace_bytes);
+        const int snap = 0;
+        double *u64 = (double *)(ws + of64);
+        float *u32 = (float *)(ws + of32);
+        double *dd = (double *)(ws + odiff);
+        if (st == FK_OK) st = fk_plan_set_workspace(p64, ws, p64->ws_bytes, stream);
+        if (st == FK_OK) st = fk_plan_set_workspace(p32, ws + o32, p32->ws_bytes, stream);
+        if (st == FK_OK) st = fk_forward(p64, &snap, 1, u64, stream);
+        if (st == FK_OK) st = fk_forward(p32, &snap, 1, u32, stream);
+        if (st == FK_OK && fk::launch_zero(dd, 8 * (size_t)n_inst, s) != hipSuccess)
+            st = fail(FK_ERR_HIP, "clear");
+        if (st == FK_OK && fk::launch_inst_maxdiff(p64->dev, u64, u32, dd, s) != hipSuccess)
+            st = fail(FK_ERR_HIP, "difference kernel");
+        if (st == FK_OK &&
+            hipMemcpyAsync(diff, dd, 8 * (size_t)n_inst, hipMemcpyDeviceToHost, s) != hipSuccess)
+            st = fail(FK_ERR_HIP, "copy");
+        if (st == FK_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(FK_ERR_HIP, "sync");
+        if (st == FK_OK)
+            for (int i = 0; i < n_inst; ++i) force_f64[i] = !(diff[i] <= 0.5 * tol);
+    }
+    fk_plan_destroy(p64);
+    fk_plan_destroy(p32);
+    return st;
 }
 
 fk_status fk_profile_adjoint(fk_plan *p, const void *lam0, double *grad, double *ms,

@@ -42,6 +42,10 @@ struct DevInst {
     int ell_w;
     int ell_nbp;
     long long ell_off;
+    // offset of the instance in the caller's fields: node_off, except in the
+    // FP64 sub-plan of an FP32 plan, whose inputs and outputs use the
+    // parent's layout
+    long long out_off;
 };
 
 // A contiguous chunk of one instance's nodes (slope pass) or active nodes
@@ -206,6 +210,13 @@ hipError_t launch_adjoint_step(const PlanDev &P, bool f32, int n, const void *pa
 hipError_t launch_adjoint_slopes_T(const PlanDev &P, bool f32, const void *u, void *mu,
                                    void *lam_next, hipStream_t s);
 hipError_t launch_adjoint_init(const PlanDev &P, bool f32, const void *lam0, void *lam,
+                               hipStream_t s, bool lam0_parent_f32 = false);
+// FP64 sub-plan <-> the parent FP32 plan's fields: out[out_off + j] =
+// (float) u[node_off + j] and back, over every node of every instance.
+hipError_t launch_convert_out(const PlanDev &P, const double *u, float *out, hipStream_t s);
+hipError_t launch_convert_in(const PlanDev &P, const float *in, double *u, hipStream_t s);
+// out[inst] = max over the instance's nodes of |a - b| (out cleared by the caller)
+hipError_t launch_inst_maxdiff(const PlanDev &P, const double *a, const float *b, double *out,
                                hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
 // Device address of the static scratch array on the current device (taken

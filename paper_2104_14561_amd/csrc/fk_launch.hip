@@ -277,11 +277,37 @@ hipError_t launch_masked_diff(const PlanDev &P, bool f32, const void *a, const v
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_init(const PlanDev &P, bool f32, const void *lam0, void *lam,
+hipError_t launch_convert_out(const PlanDev &P, const double *u, float *out, hipStream_t s)
+{
+    if (P.n_node_work == 0) return hipSuccess;
+    k_convert<true><<<P.node_grid, kBlock, 0, s>>>(P, P.node_work, P.n_node_work,
+                                                  const_cast<double *>(u), out);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_in(const PlanDev &P, const float *in, double *u, hipStream_t s)
+{
+    if (P.n_node_work == 0) return hipSuccess;
+    k_convert<false><<<P.node_grid, kBlock, 0, s>>>(P, P.node_work, P.n_node_work, u,
+                                                   const_cast<float *>(in));
+    return hipGetLastError();
+}
+
+hipError_t launch_inst_maxdiff(const PlanDev &P, const double *a, const float *b, double *out,
                                hipStream_t s)
 {
-    hipError_t e = hipMemcpyAsync(lam, lam0, (size_t)P.n_nodes * (f32 ? 4 : 8),
-                                  hipMemcpyDeviceToDevice, s);
+    if (P.n_node_work == 0) return hipSuccess;
+    k_inst_maxdiff<<<P.node_grid, kBlock, 0, s>>>(P, P.node_work, P.n_node_work, a, b,
+                                                 (unsigned long long *)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_init(const PlanDev &P, bool f32, const void *lam0, void *lam,
+                               hipStream_t s, bool lam0_parent_f32)
+{
+    hipError_t e = lam0_parent_f32
+        ? launch_convert_in(P, (const float *)lam0, (double *)lam, s)
+        : hipMemcpyAsync(lam, lam0, (size_t)P.n_nodes * (f32 ? 4 : 8), hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
     FK_DISPATCH_D(P.d,
         if (f32) k_fold_images<float, D><<<P.node_grid, kBlock, 0, s>>>(P, (float *)lam, P.node_work, 0, P.n_node_work);

@@ -29,7 +29,8 @@ MAX_THETA = 8
 EXPORTED = ["fk_last_error", "fk_version", "fk_gh_rule", "fk_plan_create", "fk_plan_destroy",
             "fk_plan_get_info", "fk_plan_layout", "fk_plan_set_workspace", "fk_forward",
             "fk_forward_from", "fk_forward_static", "fk_step", "fk_apply_step", "fk_export_cells", "fk_export_ell",
-            "fk_check_flags", "fk_adjoint", "fk_profile_pass", "fk_profile_adjoint", "fk_tune"]
+            "fk_check_flags", "fk_adjoint", "fk_profile_pass", "fk_profile_adjoint", "fk_tune",
+            "fk_probe_precision"]
 
 
 class FkError(RuntimeError):
@@ -48,7 +49,8 @@ class _Problem(ctypes.Structure):
                 ("coef", ctypes.c_double * 7), ("D", ctypes.c_double),
                 ("region_kind", ctypes.c_int), ("center", ctypes.c_double * 3),
                 ("radius", ctypes.c_double), ("gh_q", ctypes.c_int), ("dt", ctypes.c_double),
-                ("n_steps", ctypes.c_int), ("t0", ctypes.c_double)]
+                ("n_steps", ctypes.c_int), ("t0", ctypes.c_double),
+                ("force_f64", ctypes.c_int)]
 
 
 class _Options(ctypes.Structure):
@@ -108,6 +110,10 @@ def load(path: str = LIB_PATH):
         "fk_tune": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_int, ctypes.POINTER(_Options),
                                    ctypes.c_int, vp, ctypes.c_size_t, vp,
                                    ctypes.POINTER(_TuneResult)]),
+        "fk_probe_precision": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_int,
+                                              ctypes.POINTER(_Options), ctypes.c_double, vp,
+                                              ctypes.c_size_t, vp, ctypes.POINTER(ctypes.c_size_t),
+                                              ip, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -131,7 +137,7 @@ def gh_rule(q: int):
     return a, w
 
 
-def _marshal(problems) -> tuple:
+def _marshal(problems, force_f64=None) -> tuple:
     arr = (_Problem * len(problems))()
     keep = []
     for i, pr in enumerate(problems):
@@ -156,6 +162,7 @@ def _marshal(problems) -> tuple:
         s.dt = float(pr.dt)
         s.n_steps = int(pr.n_steps)
         s.t0 = float(pr.t0)
+        s.force_f64 = int(bool(force_f64[i])) if force_f64 is not None else 0
     return arr, keep
 
 
@@ -180,12 +187,14 @@ class Plan:
     "box", or "tune" (fk_tune times the layouts on this device first and the
     plan takes the fastest; the choice and timings are in .tuned).
     allocate=False builds the plan on the host only (for its info: workspace
-    size, node counts); calls need a workspace.
+    size, node counts); calls need a workspace.  force_f64: per-instance
+    flags (an FP32 plan computes the flagged instances in FP64; see
+    precision_probe).
     """
 
     def __init__(self, problems, precision: str = "f64", form: str = "fused",
                  use_graph: bool = False, ckpt_every: int = 0, device: str = "cuda",
-                 step_kernel: str = "auto", allocate: bool = True):
+                 step_kernel: str = "auto", allocate: bool = True, force_f64=None):
         import torch
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
@@ -196,7 +205,8 @@ class Plan:
                               use_graph=use_graph, device=device)
             step_kernel = self.tuned["step_kernel"]
         lib = load()
-        arr, keep = _marshal(self.problems)
+        self.force_f64 = None if force_f64 is None else [bool(v) for v in force_f64]
+        arr, keep = _marshal(self.problems, self.force_f64)
         opt = _Options()
         opt.precision = PREC[precision]
         opt.form = FORM[form]
@@ -408,6 +418,34 @@ def tune(problems, precision: str = "f64", form: str = "fused", use_graph: bool 
     return {"step_kernel": names[res.step_kernel],
             "ms_per_step": {names[k]: float(res.ms_per_step[k]) for k in range(1, 5)
                             if res.ms_per_step[k] > 0}}
+
+
+def precision_probe(problems, tol: float = 1e-5, use_graph: bool = False,
+                    step_kernel: str = "auto", device: str = "cuda", stream=None):
+    """fk_probe_precision: per instance, max |u^0 (FP64) - u^0 (FP32)| over
+    one backward pass of each, and the flags (diff > tol / 2) for
+    Plan(..., force_f64=flags).  Returns (flags, diffs)."""
+    import torch
+    if not isinstance(problems, (list, tuple)):
+        problems = [problems]
+    lib = load()
+    arr, keep = _marshal(list(problems))
+    opt = _Options()
+    opt.use_graph = int(bool(use_graph))
+    opt.step_kernel = STEP_KERNEL[step_kernel]
+    need = ctypes.c_size_t(0)
+    n = len(problems)
+    flags = (ctypes.c_int * n)()
+    diffs = (ctypes.c_double * n)()
+    _check(lib.fk_probe_precision(arr, n, ctypes.byref(opt), float(tol), None, 0, None,
+                                  ctypes.byref(need), flags, diffs))
+    ws = torch.empty(int(need.value) + 256, dtype=torch.uint8, device=torch.device(device))
+    aligned = (_ptr(ws) + 255) // 256 * 256
+    _check(lib.fk_probe_precision(arr, n, ctypes.byref(opt), float(tol), ctypes.c_void_p(aligned),
+                                  int(need.value), ctypes.c_void_p(_stream(stream)), None, flags,
+                                  diffs))
+    del keep, ws
+    return [bool(v) for v in flags], [float(v) for v in diffs]
 
 
 def solve(problems, snaps: Sequence[int] = (0,), **plan_kw):

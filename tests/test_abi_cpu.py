@@ -35,7 +35,9 @@ def test_exports_every_declared_symbol(lib):
     for s in syms:
         assert hasattr(lib, s), s
     assert set(syms) == set(fkexit.EXPORTED)
-    assert lib.fk_version() == 1
+    txt = open(os.path.join(ROOT, "include", "fkexit.h")).read()
+    version = int(re.search(r"#define FK_ABI_VERSION (\d+)", txt).group(1))
+    assert lib.fk_version() == version
 
 
 @pytest.mark.parametrize("q", [1, 2, 3, 6, 8, 16, 32, 64])
