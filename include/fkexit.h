@@ -63,8 +63,14 @@ typedef enum {
  *                      b = (-dpsi/dy, dpsi/dx), coef = (A, eps, omega); np = 3
  *                      (cellular flow of Section 4.2, the paper's sign convention)
  *  FK_COEF_ABC3D       b = f(t) (A sin z + C cos y, B sin x + A cos z, C sin y + B cos x),
- *                      f(t) = 1 + amp sin t, coef = (A, B, C, amp); np = 4 */
-enum { FK_COEF_CONST = 0, FK_COEF_CELLULAR2D = 1, FK_COEF_ABC3D = 2 };
+ *                      f(t) = 1 + amp sin t, coef = (A, B, C, amp); np = 4
+ *  FK_COEF_ROLLS2D     the paper's own 2D example (Section 4.2, Eq. (ex3)): b = Pe v,
+ *                      v_1 = -pi cos(pi y) (sin(n x) + e(t) cos(n x)),
+ *                      v_2 = n sin(pi y) (cos(n x) - e(t) sin(n x)), e(t) = eps cos(omega t)
+ *                      (2n Rayleigh-Benard rolls on x in [-pi, pi], periodic, exit
+ *                      through y = 0, 1 with a box region); coef = (Pe, eps, omega, n);
+ *                      np = 3 (n, a count, is not differentiated) */
+enum { FK_COEF_CONST = 0, FK_COEF_CELLULAR2D = 1, FK_COEF_ABC3D = 2, FK_COEF_ROLLS2D = 3 };
 
 /* Exit region (paper Section 2: D is an open box; the benchmark spec's targets add
  * a ball).  FK_REGION_BOX: a point exits when a coordinate on a non-periodic

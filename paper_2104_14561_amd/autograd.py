@@ -14,8 +14,10 @@ from .fkexit import Plan
 
 
 def _with_theta(prob, th: Sequence[float]):
+    """theta = (differentiable drift parameters..., D); coefficients past them
+    (the roll count of the Section 4.2 example) are kept."""
     npar = len(th) - 1
-    coef = tuple(float(v) for v in th[:npar])
+    coef = tuple(float(v) for v in th[:npar]) + tuple(prob.coef[npar:])
     return prob.replace(coef=coef, D=float(th[npar]))
 
 

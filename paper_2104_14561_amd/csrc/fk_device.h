@@ -220,12 +220,14 @@ __device__ inline bool ball_exit(const double *dz2, int d, double r2)
 // ABC (1 + amp sin t, sin t, 0, t).  trig = per-axis (sin, cos) table of the
 // drift's argument at each node coordinate for the current step:
 // cellular axis 0: pi (x + eps sin(omega t)); cellular axis 1: pi y;
-// ABC: the coordinate itself.
+// ABC: the coordinate itself; rolls (Section 4.2 example): axis 0 n x,
+// axis 1 pi y (the roll count n is coef[3]).
 // ---------------------------------------------------------------------------
 __device__ inline double trig_arg(const DevInst &I, const double *tf, int a, double x)
 {
 #pragma clang fp contract(off)
     if (I.coef_kind == 1) return (a == 0) ? M_PI * (x + tf[0]) : M_PI * x;
+    if (I.coef_kind == 3) return (a == 0) ? I.coef[3] * x : M_PI * x;
     return x;
 }
 
@@ -244,6 +246,15 @@ __device__ inline void drift(const DevInst &I, const double *tf, const double2 *
         const double Api = I.coef[0] * M_PI;
         b[0] = -(Api * sa * cy);
         b[1] = Api * ca * sy;
+    } else if (I.coef_kind == 3) {
+        // rolls: Pe v with v_1 = -pi cos(pi y) (sin(n x) + e cos(n x)),
+        // v_2 = n sin(pi y) (cos(n x) - e sin(n x)), e = eps cos(omega t)
+        const double2 t0 = trig[I.coord_off[0] + idx[0]];
+        const double2 t1 = trig[I.coord_off[1] + idx[1]];
+        const double s1 = t0.x, c1 = t0.y, s2 = t1.x, c2 = t1.y;
+        const double e = tf[0];
+        b[0] = -(I.coef[0] * M_PI * c2 * (s1 + e * c1));
+        b[1] = I.coef[0] * I.coef[3] * s2 * (c1 - e * s1);
     } else {
         const double2 tx = trig[I.coord_off[0] + idx[0]];
         const double2 ty = trig[I.coord_off[1] + idx[1]];
@@ -280,6 +291,21 @@ __device__ inline int drift_dtheta(const DevInst &I, const double *tf, const dou
         db[0] = -M_PI * sphi * cy;  db[1] = M_PI * cphi * sy;
         db[3] = db0 * dpe;          db[4] = db1 * dpe;
         db[6] = db0 * dpo;          db[7] = db1 * dpo;
+        return 3;
+    } else if (I.coef_kind == 3) {
+        // rolls: theta = (Pe, eps, omega); e = eps cos(omega t)
+        const double Pe = I.coef[0], eps = I.coef[1], nn = I.coef[3];
+        const double e = tf[0], cwt = tf[1], swt = tf[2], t = tf[3];
+        const double2 t0 = trig[I.coord_off[0] + idx[0]];
+        const double2 t1 = trig[I.coord_off[1] + idx[1]];
+        const double s1 = t0.x, c1 = t0.y, s2 = t1.x, c2 = t1.y;
+        const double db0 = -(Pe * M_PI * c2 * c1);   // d b0 / d e
+        const double db1 = -(Pe * nn * s2 * s1);     // d b1 / d e
+        const double dee = cwt;                      // d e / d eps
+        const double deo = -(eps * t * swt);         // d e / d omega
+        db[0] = -(M_PI * c2 * (s1 + e * c1));  db[1] = nn * s2 * (c1 - e * s1);
+        db[3] = db0 * dee;                     db[4] = db1 * dee;
+        db[6] = db0 * deo;                     db[7] = db1 * deo;
         return 3;
     } else {
         const double A = I.coef[0], B = I.coef[1], C = I.coef[2];

@@ -244,7 +244,9 @@ fk_status validate(const fk_problem &pr, int i)
     long long J = 1;
     for (int a = 0; a < pr.d; ++a) J *= pr.ax[a].n;
     if (J > (1LL << 29)) return fail(FK_ERR_UNSUPPORTED, "instance %d: more than 2^29 nodes", i);
-    if (pr.coef_kind < 0 || pr.coef_kind > 2) return fail(FK_ERR_ARG, "instance %d: coef_kind", i);
+    if (pr.coef_kind < 0 || pr.coef_kind > 3) return fail(FK_ERR_ARG, "instance %d: coef_kind", i);
+    if (pr.coef_kind == FK_COEF_ROLLS2D && pr.d != 2)
+        return fail(FK_ERR_ARG, "instance %d: roll flow needs d = 2", i);
     if (pr.coef_kind == FK_COEF_CELLULAR2D && pr.d != 2)
         return fail(FK_ERR_ARG, "instance %d: cellular flow needs d = 2", i);
     if (pr.coef_kind == FK_COEF_ABC3D && pr.d != 3)
@@ -301,6 +303,8 @@ double drift_bound(const fk_problem &pr, int a)
     const double *c = pr.coef;
     if (pr.coef_kind == FK_COEF_CONST) return std::fabs(c[a]);
     if (pr.coef_kind == FK_COEF_CELLULAR2D) return std::fabs(c[0]) * M_PI;
+    if (pr.coef_kind == FK_COEF_ROLLS2D)
+        return std::fabs(c[0]) * (a == 0 ? M_PI : std::fabs(c[3])) * (1.0 + std::fabs(c[1]));
     const double f = 1.0 + std::fabs(c[3]);
     if (a == 0) return (std::fabs(c[0]) + std::fabs(c[2])) * f;
     if (a == 1) return (std::fabs(c[1]) + std::fabs(c[0])) * f;
@@ -371,7 +375,8 @@ fk_status build_plan(fk_plan *p)
     // at least d Q* lanes for the per-axis staging of the step pass
     p->G = std::max(4, std::min(64, group_of(p->Q)));
     if (p->d * p->qs > p->G) return fail(FK_ERR_UNSUPPORTED, "d * gh_q above the lane group");
-    p->n_theta = (p0.coef_kind == FK_COEF_CONST) ? p->d + 1 : (p0.coef_kind == FK_COEF_CELLULAR2D ? 4 : 5);
+    p->n_theta = (p0.coef_kind == FK_COEF_CONST) ? p->d + 1
+               : (p0.coef_kind == FK_COEF_ABC3D ? 5 : 4);
     if ((long long)p->Q > 256) return fail(FK_ERR_UNSUPPORTED, "Q = gh_q^d above 256");
 
     p->gh_a.assign(p->qs, 0.0);
@@ -829,6 +834,11 @@ fk_status build_plan(fk_plan *p)
                 tf[0] = pr.coef[1] * std::sin(pr.coef[2] * t);
                 tf[1] = std::sin(pr.coef[2] * t);
                 tf[2] = std::cos(pr.coef[2] * t);
+                tf[3] = t;
+            } else if (pr.coef_kind == FK_COEF_ROLLS2D) {
+                tf[0] = pr.coef[1] * std::cos(pr.coef[2] * t);
+                tf[1] = std::cos(pr.coef[2] * t);
+                tf[2] = std::sin(pr.coef[2] * t);
                 tf[3] = t;
             } else if (pr.coef_kind == FK_COEF_ABC3D) {
                 tf[0] = 1.0 + pr.coef[3] * std::sin(t);

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libfkexit.so")
 FK_OK = 0
 STATUS = {0: "FK_OK", -1: "FK_ERR_ARG", -2: "FK_ERR_UNSUPPORTED", -3: "FK_ERR_WORKSPACE",
           -4: "FK_ERR_HIP", -5: "FK_ERR_NONFINITE", -6: "FK_ERR_STATE"}
-COEF = {"const": 0, "cellular2d": 1, "abc3d": 2}
+COEF = {"const": 0, "cellular2d": 1, "abc3d": 2, "rolls2d": 3}
 REGION = {"box": 0, "ball": 1}
 PREC = {"f64": 0, "f32": 1}
 FORM = {"fused": 0, "ell": 1}
