@@ -140,7 +140,10 @@ typedef struct {
                         plans with many active nodes, 1 for other large plans,
                         3 for small ones, 2 when the others are not compiled
                         for gh_q; fk_tune measures them instead */
-    int reserved[2];
+    int columns;     /* fk_forward_horizons: most columns one launch of the
+                        FK_FORM_ELL product takes (1..4; 0 = 1); the workspace
+                        holds that many record planes */
+    int reserved;
 } fk_options;
 
 typedef struct {
@@ -249,6 +252,22 @@ fk_status fk_forward(fk_plan *p, const int *snap_steps, int n_snap, void *u_out,
  * FK_ERR_UNSUPPORTED (a plan with instances forced to FP64), FK_ERR_HIP. */
 fk_status fk_forward_static(fk_plan *p, const int *snap_steps, int n_snap, void *u_out,
                             void *stream);
+
+/* Algorithm 1 (Section 3.2): the exit probabilities p^m of Eq. (e37) for
+ * several horizons in one backward sweep.  horizons (host, n_h >= 1 entries,
+ * each in [1, N], repeats allowed): horizon m is the time t0 + m dt.  Column h
+ * starts as chi; at sweep index n = M .. 1 (M the largest horizon) every
+ * column with horizons[h] >= n takes one step with the coefficients at
+ * t0 + (n-1) dt, the same operator A_{n-1} for all of them, so that
+ * u_out[h] = P(exit by t0 + horizons[h] dt | X_{t0} = x) (device, n_h fields,
+ * caller-owned, also the working storage).  FK_FORM_ELL plans assemble
+ * A_{n-1} once per sweep index and apply it to up to fk_options.columns
+ * columns per launch (a sparse matrix times a dense block of columns); fused
+ * plans run the matrix-free step once per active column.  Errors:
+ * FK_ERR_ARG (horizon outside [1, N], null arguments), FK_ERR_UNSUPPORTED
+ * (plans with instances forced to FP64), FK_ERR_HIP. */
+fk_status fk_forward_horizons(fk_plan *p, const int *horizons, int n_h, void *u_out,
+                              void *stream);
 
 /* Backward pass of Scheme 1 (Section 3.1) resumed from a caller state
  * u_start = u^{start_step} (device, one field, read only); snapshots with

@@ -1506,6 +1506,93 @@ __global__ void __launch_bounds__(kBlock) k_ell_apply(PlanDev P, const int *__re
     }
 }
 
+// Multi-column product (Algorithm 1): the assembled A_n applied to nc <= NC
+// columns at once, a sparse matrix times a dense block.  Each row's value
+// blocks are read once and contracted with the records of every column
+// (column c's records at packed + c * plane, its field at u_out + c * fstride);
+// the per-column arithmetic is that of k_ell_apply.
+template <typename T, int D, int NC>
+__global__ void __launch_bounds__(kBlock) k_ell_apply_mc(PlanDev P, const int *__restrict__ org,
+                                                         const T *__restrict__ vals,
+                                                         const T *__restrict__ exit_mass,
+                                                         const T *__restrict__ packed,
+                                                         long long plane, T *__restrict__ u_out,
+                                                         long long fstride, int nc)
+{
+    constexpr int PS = RecStride<D>::value;
+    using R = typename RecT<T, PS>::type;
+    const R *rec = reinterpret_cast<const R *>(packed);
+    const long long rplane = plane / PS;   // records between column planes
+    const WorkRange wr = work_range(0, P.n_row_work);
+    for (int w = wr.begin; w < wr.end; w += wr.step) {
+        const WorkItem it = P.row_work[w];
+        if ((int)threadIdx.x >= it.count) continue;
+        const DevInst &I = P.inst[it.inst];
+        const long long rows = I.n_act;
+        const long long r = it.first + threadIdx.x;
+        const long long row = I.act_off + r;
+        const int node = P.active[row];
+        const T em = exit_mass[row];
+        T uref[NC], acc[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            uref[c] = c < nc ? rec[c * rplane + I.node_off + node].x : T(0);
+            acc[c] = em * (T(1) - uref[c]);
+        }
+        int o[3] = {0, 0, 0};
+        for (int a = 0; a < D; ++a) o[a] = org[row * 3 + a];
+        constexpr int K = EllBlock<T>::K;
+        using B = EllBlock<T>;
+        const int bpf = I.ell_nbp / K;
+        const B *v0 = reinterpret_cast<const B *>(vals + I.ell_off) + r;
+        const long long fs = (long long)bpf * rows;
+        int bi[3] = {0, 0, 0};
+        for (int lb = 0; lb < bpf; ++lb) {
+            const B *vp = v0 + (long long)lb * rows;
+            B vf[D + 1];
+#pragma unroll
+            for (int f = 0; f <= D; ++f) vf[f] = vp[f * fs];
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                long long nd = I.node_off;
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    int ia = o[a] + bi[a];
+                    if (ia > I.n[a] - 1) ia = I.n[a] - 1;
+                    nd += (long long)ia * I.stride[a];
+                }
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    if (c >= nc) break;
+                    const R rc = rec[c * rplane + nd];
+                    if constexpr (D == 1) {
+                        acc[c] += vf[0].v[j] * (rc.x - uref[c]) + vf[1].v[j] * rc.y;
+                    } else if constexpr (D == 2) {
+                        acc[c] += vf[0].v[j] * (rc.x - uref[c]) + vf[1].v[j] * rc.y + vf[2].v[j] * rc.z;
+                    } else {
+                        acc[c] += vf[0].v[j] * (rc.x - uref[c]) + vf[1].v[j] * rc.y +
+                                  vf[2].v[j] * rc.z + vf[3].v[j] * rc.w;
+                    }
+                }
+#pragma unroll
+                for (int a = D - 1; a >= 0; --a) {
+                    if (++bi[a] < I.ell_box[a]) break;
+                    bi[a] = 0;
+                }
+            }
+        }
+        int idx[3];
+        split_node<D>(I, node, idx);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (c >= nc) break;
+            const T v = uref[c] + acc[c];
+            flag_nonfinite(P.flags, v);
+            store_node<D, T>(I, idx, node, v, u_out + c * fstride);
+        }
+    }
+}
+
 // Export in the documented layout: width P.ell_width (the largest instance
 // width), column-major over all active rows, columns (d+1) node + field,
 // padding entries value 0 (column of the row's own node value).

@@ -984,6 +984,8 @@ fk_status build_plan(fk_plan *p)
     add_region(p, "uB", fb);
     add_region(p, "packed", fb * rec_stride(p->d));
     if (p->opt.form == FK_FORM_ELL) {
+        const int nc = std::max(1, std::min(4, p->opt.columns));
+        add_region(p, "packed_mc", fb * rec_stride(p->d) * nc);
         add_region(p, "ell_org", sizeof(int) * 3 * (size_t)std::max<long long>(p->n_active, 1));
         add_region(p, "ell_vals", elt(p) * (size_t)std::max<long long>(p->ell_total, 1));
         add_region(p, "ell_em", elt(p) * (size_t)std::max<long long>(p->n_active, 1));
@@ -1187,14 +1189,12 @@ fk_status enqueue_pass(fk_plan *p, const void *u_start, int start, const int *sn
     return FK_OK;
 }
 
-fk_status run_pass(fk_plan *p, const void *u_start, int start, const int *snaps, int n_snap,
-                   void *u_out, hipStream_t s, bool store_ckpt)
+// Runs body on s, captured once into a HIP graph and replayed while key
+// (the body's arguments) stays the same, when the plan uses graphs.
+template <typename Body>
+fk_status run_captured(fk_plan *p, const std::string &k, hipStream_t s, const Body &body)
 {
-    if (!p->opt.use_graph) return enqueue_pass(p, u_start, start, snaps, n_snap, u_out, s, store_ckpt);
-    char key[256];
-    snprintf(key, sizeof(key), "%p|%d|%p|%d|", u_start, start, u_out, store_ckpt ? 1 : 0);
-    std::string k = key;
-    for (int i = 0; i < n_snap; ++i) k += std::to_string(snaps[i]) + ",";
+    if (!p->opt.use_graph) return body(s);
     if (!p->gexec || k != p->gkey) {
         if (p->gexec) {
             (void)hipGraphExecDestroy(p->gexec);
@@ -1203,7 +1203,7 @@ fk_status run_pass(fk_plan *p, const void *u_start, int start, const int *snaps,
         if (!p->cap_stream) FK_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
         hipGraph_t graph = nullptr;
         FK_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-        fk_status st = enqueue_pass(p, u_start, start, snaps, n_snap, u_out, p->cap_stream, store_ckpt);
+        fk_status st = body(p->cap_stream);
         hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
         if (st != FK_OK) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -1216,6 +1216,69 @@ fk_status run_pass(fk_plan *p, const void *u_start, int start, const int *snaps,
         p->gkey = k;
     }
     FK_HIP(hipGraphLaunch(p->gexec, s));
+    return FK_OK;
+}
+
+fk_status run_pass(fk_plan *p, const void *u_start, int start, const int *snaps, int n_snap,
+                   void *u_out, hipStream_t s, bool store_ckpt)
+{
+    char key[256];
+    snprintf(key, sizeof(key), "pass|%p|%d|%p|%d|", u_start, start, u_out, store_ckpt ? 1 : 0);
+    std::string k = key;
+    for (int i = 0; i < n_snap; ++i) k += std::to_string(snaps[i]) + ",";
+    return run_captured(p, k, s, [&](hipStream_t cs) {
+        return enqueue_pass(p, u_start, start, snaps, n_snap, u_out, cs, store_ckpt);
+    });
+}
+
+// Algorithm 1: columns u_out[h] (in place), sweep index n = M .. 1 with the
+// operator of step n - 1 shared by the columns whose horizon is >= n.
+fk_status enqueue_horizons(fk_plan *p, const int *hz, int n_h, void *u_out, hipStream_t s)
+{
+    const size_t fe = (size_t)p->n_nodes;              // elements per field
+    const size_t fb = elt(p) * fe;
+    std::vector<int> order(n_h);
+    for (int h = 0; h < n_h; ++h) order[h] = h;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hz[a] < hz[b]; });
+    int M = 0;
+    for (int h = 0; h < n_h; ++h) M = std::max(M, hz[h]);
+    auto col = [&](int h) { return (void *)((unsigned char *)u_out + (size_t)h * fb); };
+    FK_LAUNCH(fk::launch_clear_flags(p->dev, s));
+    for (int h = 0; h < n_h; ++h) FK_LAUNCH(fk::launch_init_field(p->dev, p->f32, col(h), s));
+    const bool ell = p->opt.form == FK_FORM_ELL;
+    const int chunk = std::max(1, std::min(4, p->opt.columns));
+    void *packed = p->at("packed");
+    size_t first = order.size();   // order[first ..] are the columns with horizon >= n
+    for (int n = M; n >= 1; --n) {
+        while (first > 0 && hz[order[first - 1]] >= n) --first;
+        const int step = n - 1;
+        if (!ell) {
+            for (size_t k = first; k < order.size(); ++k) {
+                FK_LAUNCH(fk::launch_slopes(p->dev, p->f32, step, col(order[k]), packed, s));
+                FK_LAUNCH(fk::launch_step_fused(p->dev, p->f32, step, packed, col(order[k]), s));
+            }
+            continue;
+        }
+        int *org = (int *)p->at("ell_org");
+        void *vals = p->at("ell_vals"), *em = p->at("ell_em");
+        unsigned char *planes = (unsigned char *)p->at("packed_mc");
+        const size_t plane_b = fb * rec_stride(p->d);
+        FK_LAUNCH(fk::launch_tables(p->dev, step, s));
+        FK_LAUNCH(fk::launch_assemble_ell(p->dev, p->f32, step, org, vals, em, s));
+        for (size_t k0 = first; k0 < order.size();) {
+            // columns of consecutive storage in one launch: runs of order[]
+            // entries whose fields are adjacent in u_out
+            int nc = 1;
+            while (nc < chunk && k0 + nc < order.size() && order[k0 + nc] == order[k0] + nc) ++nc;
+            for (int c = 0; c < nc; ++c)
+                FK_LAUNCH(fk::launch_slopes(p->dev, p->f32, step, col(order[k0 + c]),
+                                            planes + (size_t)c * plane_b, s));
+            FK_LAUNCH(fk::launch_ell_apply_mc(p->dev, p->f32, org, vals, em, planes,
+                                              (long long)(fe * rec_stride(p->d)), col(order[k0]),
+                                              (long long)fe, nc, s));
+            k0 += nc;
+        }
+    }
     return FK_OK;
 }
 
@@ -1265,6 +1328,7 @@ fk_status fk_plan_create(const fk_problem *probs, int n_inst, const fk_options *
     if (o.ckpt_every < 0) return fail(FK_ERR_ARG, "ckpt_every must be >= 0");
     if (o.block != 0 && o.block != kBlock) return fail(FK_ERR_UNSUPPORTED, "block must be 0 or 256");
     if (o.step_kernel < 0 || o.step_kernel > 4) return fail(FK_ERR_ARG, "step_kernel must be 0..4");
+    if (o.columns < 0 || o.columns > 4) return fail(FK_ERR_ARG, "columns must be 0..4");
     if ((o.step_kernel == 1 || o.step_kernel == 3 || o.step_kernel == 4) &&
         !fk::step_node_compiled(probs[0].d, probs[0].gh_q))
         return fail(FK_ERR_UNSUPPORTED, "no thread-per-node kernel compiled for d=%d, gh_q=%d",
@@ -1488,6 +1552,23 @@ fk_status fk_forward(fk_plan *p, const int *snap_steps, int n_snap, void *u_out,
         q->ckpt_stream = (hipStream_t)stream;
     }
     return FK_OK;
+}
+
+fk_status fk_forward_horizons(fk_plan *p, const int *horizons, int n_h, void *u_out, void *stream)
+{
+    FK_TRY(need_ws(p));
+    if (!horizons || n_h < 1 || !u_out) return fail(FK_ERR_ARG, "null horizons or output, or n_h < 1");
+    for (int h = 0; h < n_h; ++h)
+        if (horizons[h] < 1 || horizons[h] > p->N)
+            return fail(FK_ERR_ARG, "horizon %d outside [1, %d]", horizons[h], p->N);
+    if (p->sub) return fail(FK_ERR_UNSUPPORTED, "plans with instances forced to FP64");
+    char key[64];
+    snprintf(key, sizeof(key), "horizons|%p|", u_out);
+    std::string k = key;
+    for (int h = 0; h < n_h; ++h) k += std::to_string(horizons[h]) + ",";
+    return run_captured(p, k, (hipStream_t)stream, [&](hipStream_t cs) {
+        return enqueue_horizons(p, horizons, n_h, u_out, cs);
+    });
 }
 
 fk_status fk_forward_from(fk_plan *p, const void *u_start, int start_step, const int *snap_steps,

@@ -195,6 +195,11 @@ hipError_t launch_assemble_ell(const PlanDev &P, bool f32, int n, int *org, void
 hipError_t launch_ell_apply(const PlanDev &P, bool f32, const int *org, const void *vals,
                             const void *exit_mass, const void *packed, void *u_out,
                             hipStream_t s);
+// The assembled operator applied to nc <= 4 columns (records of column c at
+// packed + c * plane elements, its field at u_out + c * fstride elements).
+hipError_t launch_ell_apply_mc(const PlanDev &P, bool f32, const int *org, const void *vals,
+                               const void *exit_mass, const void *packed, long long plane,
+                               void *u_out, long long fstride, int nc, hipStream_t s);
 hipError_t launch_export_ell(const PlanDev &P, bool f32, const int *org_in, const void *vals_in,
                              int *cols_out, void *vals_out, hipStream_t s);
 hipError_t launch_export_cells(const PlanDev &P, int inst, int n, int *cells,

@@ -170,6 +170,17 @@ hipError_t launch_ell_apply(const PlanDev &P, bool f32, const int *org, const vo
     return hipGetLastError();
 }
 
+hipError_t launch_ell_apply_mc(const PlanDev &P, bool f32, const int *org, const void *vals,
+                               const void *exit_mass, const void *packed, long long plane,
+                               void *u_out, long long fstride, int nc, hipStream_t s)
+{
+    if (nc < 1 || nc > 4) return hipErrorInvalidValue;
+    FK_DISPATCH_D(P.d,
+        if (f32) k_ell_apply_mc<float, D, 4><<<P.row_grid, kBlock, 0, s>>>(P, org, (const float *)vals, (const float *)exit_mass, (const float *)packed, plane, (float *)u_out, fstride, nc);
+        else k_ell_apply_mc<double, D, 4><<<P.row_grid, kBlock, 0, s>>>(P, org, (const double *)vals, (const double *)exit_mass, (const double *)packed, plane, (double *)u_out, fstride, nc));
+    return hipGetLastError();
+}
+
 hipError_t launch_export_ell(const PlanDev &P, bool f32, const int *org_in, const void *vals_in,
                              int *cols_out, void *vals_out, hipStream_t s)
 {

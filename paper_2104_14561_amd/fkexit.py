@@ -28,7 +28,7 @@ MAX_THETA = 8
 
 EXPORTED = ["fk_last_error", "fk_version", "fk_gh_rule", "fk_plan_create", "fk_plan_destroy",
             "fk_plan_get_info", "fk_plan_layout", "fk_plan_set_workspace", "fk_forward",
-            "fk_forward_from", "fk_forward_static", "fk_step", "fk_apply_step", "fk_export_cells", "fk_export_ell",
+            "fk_forward_from", "fk_forward_horizons", "fk_forward_static", "fk_step", "fk_apply_step", "fk_export_cells", "fk_export_ell",
             "fk_check_flags", "fk_adjoint", "fk_profile_pass", "fk_profile_adjoint", "fk_tune",
             "fk_probe_precision"]
 
@@ -56,7 +56,8 @@ class _Problem(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("form", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("ckpt_every", ctypes.c_int), ("block", ctypes.c_int),
-                ("step_kernel", ctypes.c_int), ("reserved", ctypes.c_int * 2)]
+                ("step_kernel", ctypes.c_int), ("columns", ctypes.c_int),
+                ("reserved", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -99,6 +100,7 @@ def load(path: str = LIB_PATH):
         "fk_forward": (ctypes.c_int, [vp, ip, ctypes.c_int, vp, vp]),
         "fk_forward_from": (ctypes.c_int, [vp, vp, ctypes.c_int, ip, ctypes.c_int, vp, vp]),
         "fk_forward_static": (ctypes.c_int, [vp, ip, ctypes.c_int, vp, vp]),
+        "fk_forward_horizons": (ctypes.c_int, [vp, ip, ctypes.c_int, vp, vp]),
         "fk_step": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp]),
         "fk_apply_step": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]),
         "fk_export_cells": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]),
@@ -189,12 +191,14 @@ class Plan:
     allocate=False builds the plan on the host only (for its info: workspace
     size, node counts); calls need a workspace.  force_f64: per-instance
     flags (an FP32 plan computes the flagged instances in FP64; see
-    precision_probe).
+    precision_probe).  columns: columns per launch of the assembled
+    product in forward_horizons (1..4).
     """
 
     def __init__(self, problems, precision: str = "f64", form: str = "fused",
                  use_graph: bool = False, ckpt_every: int = 0, device: str = "cuda",
-                 step_kernel: str = "auto", allocate: bool = True, force_f64=None):
+                 step_kernel: str = "auto", allocate: bool = True, force_f64=None,
+                 columns: int = 1):
         import torch
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
@@ -213,6 +217,7 @@ class Plan:
         opt.use_graph = int(bool(use_graph))
         opt.ckpt_every = int(ckpt_every)
         opt.step_kernel = STEP_KERNEL[step_kernel]
+        opt.columns = int(columns)
         h = ctypes.c_void_p()
         _check(lib.fk_plan_create(arr, len(self.problems), ctypes.byref(opt), ctypes.byref(h)))
         del keep
@@ -281,6 +286,17 @@ class Plan:
         _check(load().fk_forward(self._h, sn.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                                  len(sn), ctypes.c_void_p(_ptr(out)),
                                  ctypes.c_void_p(_stream(stream))))
+        return out
+
+    def forward_horizons(self, horizons: Sequence[int], stream=None):
+        """fk_forward_horizons (Algorithm 1): one field per horizon m (in steps
+        from t0), the exit probability by t0 + m dt; [len(horizons), n_nodes]."""
+        import torch
+        hz = np.ascontiguousarray(horizons, dtype=np.int32)
+        out = torch.empty((len(hz), self.n_nodes), dtype=self.dtype, device=self.device)
+        _check(load().fk_forward_horizons(self._h, hz.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                          len(hz), ctypes.c_void_p(_ptr(out)),
+                                          ctypes.c_void_p(_stream(stream))))
         return out
 
     def forward_static(self, snaps: Sequence[int] = (0,), stream=None):
