@@ -359,23 +359,39 @@ fk_status fk_adjoint(fk_plan *p, const void *lam0, double *grad, void *lamN,
 fk_status fk_tune(const fk_problem *probs, int n_inst, const fk_options *opt, int trial_steps,
                   void *workspace, size_t workspace_bytes, void *stream, fk_tune_result *out);
 
+/* Measurement hook (hardware, no passage of the paper): the lane-level rate of
+ * LDS floating-point atomic adds of the device, FP64 (f32 = 0) or FP32
+ * (f32 = 1), with conflict-free addresses: 2048 workgroups x 256 lanes x
+ * 4096 adds each, the best of three timed launches after a warm-up, HIP
+ * events on stream.  *adds_per_s (host) receives the rate.  workspace
+ * (device, caller-owned, >= 16 KiB) receives one value per workgroup.
+ * The transposed step accumulates in FP64 LDS atomics; this is its ceiling.
+ * Synchronises stream.  Errors: FK_ERR_ARG, FK_ERR_WORKSPACE, FK_ERR_HIP. */
+fk_status fk_probe_lds_atomics(int f32, double *adds_per_s, void *workspace, size_t workspace_bytes,
+                               void *stream);
+
 /* Precision probe for FP32 plans (the precision split is an engineering
  * addition; the error of every FP32 result against FP64 is what it bounds):
  * runs the backward pass of the problems once in FP64 and once with
- * FK_PREC_F32 (fused form, no graph unless opt->use_graph, opt's step layout)
- * and returns per instance diff[i] = max over the instance's nodes of
- * |u^0 (FP64) - u^0 (FP32)| and force_f64[i] = (diff[i] > tol / 2) (host
- * outputs of length n_inst), ready for fk_problem.force_f64: an instance
- * whose scheme amplifies the FP32 rounding beyond half the tolerance is then
- * computed in FP64 (the other half is left for the FP64 evaluation's own
- * rounding).  force_f64 of the inputs is ignored.  With workspace == NULL
- * only *bytes_needed is written (device bytes, 256-byte aligned); otherwise
- * workspace (device, caller-owned, contents destroyed) must hold that many.
- * Synchronises stream.  Errors: FK_ERR_ARG, FK_ERR_WORKSPACE, plan-creation
- * and HIP errors. */
+ * FK_PREC_F32 (fused form, opt's graph use and step layout) and returns per
+ * instance diff[i] = max over the instance's nodes of |u^0 (FP64) - u^0 (FP32)|.
+ * With a cotangent lam0 (device, double, one field of the problems' packed
+ * layout; NULL: fields only) it also runs both adjoints (checkpoints every 32
+ * steps; the FP32 one with lam0 rounded to FP32) and returns grad_diff[i] =
+ * max_k |dJ/dtheta_k (FP64) - (FP32)| / max_k |dJ/dtheta_k (FP64)| (if
+ * grad_diff is not NULL).  force_f64[i] = (diff[i] > tol / 2) or, with lam0,
+ * (grad_diff[i] > grad_tol / 2) (host outputs of length n_inst), ready for
+ * fk_problem.force_f64: an instance whose scheme amplifies the FP32 rounding
+ * beyond half a tolerance is then computed in FP64 (the other half is left for
+ * the FP64 evaluation's own rounding).  force_f64 of the inputs is ignored.
+ * With workspace == NULL only *bytes_needed is written (device bytes for the
+ * same call with a cotangent); otherwise workspace (device, 256-byte aligned,
+ * caller-owned, contents destroyed) must hold that many.  Synchronises stream.
+ * Errors: FK_ERR_ARG, FK_ERR_WORKSPACE, plan-creation and HIP errors. */
 fk_status fk_probe_precision(const fk_problem *probs, int n_inst, const fk_options *opt,
-                             double tol, void *workspace, size_t workspace_bytes, void *stream,
-                             size_t *bytes_needed, int *force_f64, double *diff);
+                             double tol, const double *lam0, double grad_tol, void *workspace,
+                             size_t workspace_bytes, void *stream, size_t *bytes_needed,
+                             int *force_f64, double *diff, double *grad_diff);
 
 /* Measurement hook (Scheme 1, Section 3.1, timed; the cost model of
  * Section 3.2.1 names assembly and product; instances forced to FP64 are not

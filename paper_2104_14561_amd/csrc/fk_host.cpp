@@ -44,6 +44,7 @@ fk_status fail(fk_status st, const char *fmt, ...)
 
 constexpr int kBlock = 256;
 constexpr size_t kAlign = 256;
+constexpr int kProbeCkpt = 32;   // checkpoint interval of the precision probe's adjoints
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -1179,12 +1180,20 @@ fk_status enqueue_pass(fk_plan *p, const void *u_start, int start, const int *sn
     };
     FK_TRY(snap_copy(start, ua));
     FK_TRY(ckpt_copy(start, ua));
-    void *cur = ua, *nxt = ub;
+    // a step whose state is a checkpoint writes it straight into its slot
+    // (the slots hold 1 on exit nodes since the workspace was set); the others
+    // alternate between the two work fields
+    auto slot_of = [&](int n) -> void * {
+        if (!store_ckpt || n == p->N || n % p->opt.ckpt_every != 0) return nullptr;
+        return (unsigned char *)p->at("ckpt") + (size_t)(n / p->opt.ckpt_every) * fb;
+    };
+    void *cur = ua;
     for (int n = start - 1; n >= 0; --n) {
-        FK_TRY(enqueue_step(p, n, cur, nxt, s));
-        std::swap(cur, nxt);
+        void *dst = slot_of(n);
+        if (!dst) dst = (cur == ua) ? ub : ua;
+        FK_TRY(enqueue_step(p, n, cur, dst, s));
+        cur = dst;
         FK_TRY(snap_copy(n, cur));
-        FK_TRY(ckpt_copy(n, cur));
     }
     return FK_OK;
 }
@@ -1461,6 +1470,13 @@ fk_status fk_plan_set_workspace(fk_plan *p, void *dev_ptr, size_t bytes, void *s
     p->ckpt_valid = false;
     fill_dev(p);
     FK_TRY(upload_tables(p, s));
+    if (p->opt.ckpt_every > 0) {
+        // checkpoint slots hold 1 on exit nodes for good: the forward pass
+        // writes only the active nodes (and their images) of a slot
+        const size_t fb = elt(p) * (size_t)p->n_nodes;
+        for (int k = 0; k < p->n_ckpt; ++k)
+            FK_LAUNCH(fk::launch_init_field(p->dev, p->f32, (unsigned char *)p->at("ckpt") + (size_t)k * fb, s));
+    }
     FK_HIP(hipStreamSynchronize(s));
     if (p->sub) FK_TRY(fk_plan_set_workspace(p->sub, p->at("sub_ws"), p->sub->ws_bytes, stream));
     return FK_OK;
@@ -1912,12 +1928,43 @@ fk_status fk_tune(const fk_problem *probs, int n_inst, const fk_options *opt, in
     return FK_OK;
 }
 
+fk_status fk_probe_lds_atomics(int f32, double *adds_per_s, void *workspace, size_t workspace_bytes,
+                               void *stream)
+{
+    const int blocks = 2048, iters = 4096;
+    if (!adds_per_s || !workspace) return fail(FK_ERR_ARG, "null argument");
+    if (workspace_bytes < sizeof(double) * blocks)
+        return fail(FK_ERR_WORKSPACE, "probe needs %zu bytes", sizeof(double) * blocks);
+    hipStream_t s = (hipStream_t)stream;
+    double *out = (double *)workspace;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    FK_HIP(hipEventCreate(&e0));
+    FK_HIP(hipEventCreate(&e1));
+    fk_status st = FK_OK;
+    float best = 1e30f;
+    for (int rep = 0; rep < 4 && st == FK_OK; ++rep) {
+        float ms = 0.f;
+        if (hipEventRecord(e0, s) != hipSuccess ||
+            fk::launch_lds_atomic_probe(f32 != 0, blocks, iters, out, s) != hipSuccess ||
+            hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            st = fail(FK_ERR_HIP, "LDS atomic probe");
+        if (rep > 0) best = std::min(best, ms);   // the first run warms up
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == FK_OK) *adds_per_s = (double)blocks * 256.0 * iters / (best * 1e-3);
+    return st;
+}
+
 fk_status fk_probe_precision(const fk_problem *probs, int n_inst, const fk_options *opt,
-                             double tol, void *workspace, size_t workspace_bytes, void *stream,
-                             size_t *bytes_needed, int *force_f64, double *diff)
+                             double tol, const double *lam0, double grad_tol, void *workspace,
+                             size_t workspace_bytes, void *stream, size_t *bytes_needed,
+                             int *force_f64, double *diff, double *grad_diff)
 {
     if (!probs || n_inst < 1) return fail(FK_ERR_ARG, "null problems");
     if (!(tol > 0)) return fail(FK_ERR_ARG, "tol must be > 0");
+    if (lam0 && !(grad_tol > 0)) return fail(FK_ERR_ARG, "grad_tol must be > 0");
     if (!workspace && !bytes_needed) return fail(FK_ERR_ARG, "null workspace and size output");
     if (workspace && (!force_f64 || !diff)) return fail(FK_ERR_ARG, "null outputs");
     hipStream_t s = (hipStream_t)stream;
@@ -1926,7 +1973,7 @@ fk_status fk_probe_precision(const fk_problem *probs, int n_inst, const fk_optio
     fk_options o{};
     if (opt) o = *opt;
     o.form = FK_FORM_FUSED;
-    o.ckpt_every = 0;
+    o.ckpt_every = lam0 || !workspace ? kProbeCkpt : 0;
     fk_plan *p64 = nullptr, *p32 = nullptr;
     o.precision = FK_PREC_F64;
     FK_TRY(fk_plan_create(pr.data(), n_inst, &o, &p64));
@@ -1936,10 +1983,12 @@ fk_status fk_probe_precision(const fk_problem *probs, int n_inst, const fk_optio
         fk_plan_destroy(p64);
         return st;
     }
-    const size_t nn = (size_t)p64->n_nodes;
+    const size_t nn = (size_t)p64->n_nodes, ni = (size_t)n_inst;
     const size_t o32 = align_up(p64->ws_bytes), of64 = o32 + align_up(p32->ws_bytes);
     const size_t of32 = of64 + align_up(8 * nn), odiff = of32 + align_up(4 * nn);
-    const size_t need = odiff + align_up(8 * (size_t)n_inst);
+    const size_t olam = odiff + align_up(8 * ni), og64 = olam + align_up(4 * nn);
+    const size_t og32 = og64 + align_up(8 * fk::kThetaSlots * ni);
+    const size_t need = og32 + align_up(8 * fk::kThetaSlots * ni);
     if (bytes_needed) *bytes_needed = need;
     if (workspace) {
         unsigned char *ws = (unsigned char *)workspace;
@@ -1951,20 +2000,51 @@ fk_status fk_probe_precision(const fk_problem *probs, int n_inst, const fk_optio
         double *u64 = (double *)(ws + of64);
         float *u32 = (float *)(ws + of32);
         double *dd = (double *)(ws + odiff);
+        float *lam32 = (float *)(ws + olam);
+        double *g64 = (double *)(ws + og64), *g32 = (double *)(ws + og32);
         if (st == FK_OK) st = fk_plan_set_workspace(p64, ws, p64->ws_bytes, stream);
         if (st == FK_OK) st = fk_plan_set_workspace(p32, ws + o32, p32->ws_bytes, stream);
         if (st == FK_OK) st = fk_forward(p64, &snap, 1, u64, stream);
         if (st == FK_OK) st = fk_forward(p32, &snap, 1, u32, stream);
-        if (st == FK_OK && fk::launch_zero(dd, 8 * (size_t)n_inst, s) != hipSuccess)
+        if (st == FK_OK && fk::launch_zero(dd, 8 * ni, s) != hipSuccess)
             st = fail(FK_ERR_HIP, "clear");
         if (st == FK_OK && fk::launch_inst_maxdiff(p64->dev, u64, u32, dd, s) != hipSuccess)
             st = fail(FK_ERR_HIP, "difference kernel");
-        if (st == FK_OK &&
-            hipMemcpyAsync(diff, dd, 8 * (size_t)n_inst, hipMemcpyDeviceToHost, s) != hipSuccess)
+        if (st == FK_OK && hipMemcpyAsync(diff, dd, 8 * ni, hipMemcpyDeviceToHost, s) != hipSuccess)
             st = fail(FK_ERR_HIP, "copy");
+        std::vector<double> h64(fk::kThetaSlots * ni), h32(fk::kThetaSlots * ni);
+        if (lam0) {
+            // the same cotangent, rounded to FP32 for the FP32 plan
+            if (st == FK_OK && fk::launch_convert_out(p32->dev, lam0, lam32, s) != hipSuccess)
+                st = fail(FK_ERR_HIP, "convert");
+            if (st == FK_OK) st = fk_adjoint(p64, lam0, g64, nullptr, stream);
+            if (st == FK_OK) st = fk_adjoint(p32, lam32, g32, nullptr, stream);
+            if (st == FK_OK && (hipMemcpyAsync(h64.data(), g64, 8 * h64.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                                hipMemcpyAsync(h32.data(), g32, 8 * h32.size(), hipMemcpyDeviceToHost, s) != hipSuccess))
+                st = fail(FK_ERR_HIP, "copy");
+        }
         if (st == FK_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(FK_ERR_HIP, "sync");
-        if (st == FK_OK)
-            for (int i = 0; i < n_inst; ++i) force_f64[i] = !(diff[i] <= 0.5 * tol);
+        if (st == FK_OK) {
+            const int nt = p64->n_theta;
+            for (int i = 0; i < n_inst; ++i) {
+                bool f = !(diff[i] <= 0.5 * tol);
+                double gd = 0.0;
+                if (lam0) {
+                    double gmax = 0.0, dmax = 0.0;
+                    for (int k = 0; k < nt; ++k) {
+                        const double a = h64[(size_t)i * fk::kThetaSlots + k];
+                        const double b = h32[(size_t)i * fk::kThetaSlots + k];
+                        gmax = std::max(gmax, std::fabs(a));
+                        dmax = std::max(dmax, std::fabs(a - b));
+                        if (!(std::fabs(a - b) >= 0)) dmax = HUGE_VAL;   // NaN
+                    }
+                    gd = dmax == 0.0 ? 0.0 : (gmax > 0.0 ? dmax / gmax : HUGE_VAL);
+                    f = f || !(gd <= 0.5 * grad_tol);
+                }
+                force_f64[i] = f ? 1 : 0;
+                if (grad_diff) grad_diff[i] = gd;
+            }
+        }
     }
     fk_plan_destroy(p64);
     fk_plan_destroy(p32);

@@ -224,6 +224,10 @@ hipError_t launch_convert_in(const PlanDev &P, const float *in, double *u, hipSt
 hipError_t launch_inst_maxdiff(const PlanDev &P, const double *a, const float *b, double *out,
                                hipStream_t s);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+// LDS atomic throughput probe (measurement): blocks x 256 lanes, iters
+// conflict-free ds_add per lane, out[blocks] written.
+hipError_t launch_lds_atomic_probe(bool f32, int blocks, int iters, double *out, hipStream_t s);
+
 // Device address of the static scratch array on the current device (taken
 // with hipGetSymbolAddress on the first call per device).
 hipError_t static_scratch(void **out);

@@ -260,6 +260,33 @@ hipError_t launch_adjoint_slopes_T(const PlanDev &P, bool f32, const void *u, vo
     return hipGetLastError();
 }
 
+// LDS atomic throughput probe: every lane adds into its own LDS word (no
+// bank conflicts, no contention), iters times; one value per workgroup is
+// written out so that nothing is dead.
+template <typename T>
+__global__ void __launch_bounds__(256) k_lds_atomic_probe(int iters, double *out)
+{
+    __shared__ T buf[256];
+    buf[threadIdx.x] = T(0);
+    __syncthreads();
+    const T v = T(1) + T(threadIdx.x) * T(1e-3);
+#pragma unroll 16
+    for (int i = 0; i < iters; ++i) atomicAdd(&buf[threadIdx.x], v);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int k = 0; k < 256; ++k) s += (double)buf[k];
+        out[blockIdx.x] = s;
+    }
+}
+
+hipError_t launch_lds_atomic_probe(bool f32, int blocks, int iters, double *out, hipStream_t s)
+{
+    if (f32) k_lds_atomic_probe<float><<<blocks, 256, 0, s>>>(iters, out);
+    else k_lds_atomic_probe<double><<<blocks, 256, 0, s>>>(iters, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_pack_fields(const PlanDev &P, bool f32, const void *x, void *packed,
                               hipStream_t s)
 {

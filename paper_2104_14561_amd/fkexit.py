@@ -30,7 +30,7 @@ EXPORTED = ["fk_last_error", "fk_version", "fk_gh_rule", "fk_plan_create", "fk_p
             "fk_plan_get_info", "fk_plan_layout", "fk_plan_set_workspace", "fk_forward",
             "fk_forward_from", "fk_forward_horizons", "fk_forward_static", "fk_step", "fk_apply_step", "fk_export_cells", "fk_export_ell",
             "fk_check_flags", "fk_adjoint", "fk_profile_pass", "fk_profile_adjoint", "fk_tune",
-            "fk_probe_precision"]
+            "fk_probe_precision", "fk_probe_lds_atomics"]
 
 
 class FkError(RuntimeError):
@@ -112,10 +112,11 @@ def load(path: str = LIB_PATH):
         "fk_tune": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_int, ctypes.POINTER(_Options),
                                    ctypes.c_int, vp, ctypes.c_size_t, vp,
                                    ctypes.POINTER(_TuneResult)]),
+        "fk_probe_lds_atomics": (ctypes.c_int, [ctypes.c_int, dp, vp, ctypes.c_size_t, vp]),
         "fk_probe_precision": (ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_int,
                                               ctypes.POINTER(_Options), ctypes.c_double, vp,
-                                              ctypes.c_size_t, vp, ctypes.POINTER(ctypes.c_size_t),
-                                              ip, dp]),
+                                              ctypes.c_double, vp, ctypes.c_size_t, vp,
+                                              ctypes.POINTER(ctypes.c_size_t), ip, dp, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -436,11 +437,14 @@ def tune(problems, precision: str = "f64", form: str = "fused", use_graph: bool 
                             if res.ms_per_step[k] > 0}}
 
 
-def precision_probe(problems, tol: float = 1e-5, use_graph: bool = False,
-                    step_kernel: str = "auto", device: str = "cuda", stream=None):
+def precision_probe(problems, tol: float = 1e-5, lam0=None, grad_tol: float = 1e-4,
+                    use_graph: bool = False, step_kernel: str = "auto", device: str = "cuda",
+                    stream=None):
     """fk_probe_precision: per instance, max |u^0 (FP64) - u^0 (FP32)| over
-    one backward pass of each, and the flags (diff > tol / 2) for
-    Plan(..., force_f64=flags).  Returns (flags, diffs)."""
+    one backward pass of each and, with a cotangent lam0 (packed field),
+    the relative gradient difference of the two adjoints; flags
+    (diff > tol / 2 or grad diff > grad_tol / 2) for
+    Plan(..., force_f64=flags).  Returns (flags, diffs, grad_diffs)."""
     import torch
     if not isinstance(problems, (list, tuple)):
         problems = [problems]
@@ -453,15 +457,32 @@ def precision_probe(problems, tol: float = 1e-5, use_graph: bool = False,
     n = len(problems)
     flags = (ctypes.c_int * n)()
     diffs = (ctypes.c_double * n)()
-    _check(lib.fk_probe_precision(arr, n, ctypes.byref(opt), float(tol), None, 0, None,
-                                  ctypes.byref(need), flags, diffs))
+    gdiffs = (ctypes.c_double * n)()
+    _check(lib.fk_probe_precision(arr, n, ctypes.byref(opt), float(tol), None, float(grad_tol),
+                                  None, 0, None, ctypes.byref(need), flags, diffs, gdiffs))
+    lam = None
+    if lam0 is not None:
+        lam = lam0.to(torch.device(device), torch.float64).contiguous()
     ws = torch.empty(int(need.value) + 256, dtype=torch.uint8, device=torch.device(device))
     aligned = (_ptr(ws) + 255) // 256 * 256
-    _check(lib.fk_probe_precision(arr, n, ctypes.byref(opt), float(tol), ctypes.c_void_p(aligned),
-                                  int(need.value), ctypes.c_void_p(_stream(stream)), None, flags,
-                                  diffs))
+    _check(lib.fk_probe_precision(arr, n, ctypes.byref(opt), float(tol),
+                                  ctypes.c_void_p(_ptr(lam)) if lam is not None else None,
+                                  float(grad_tol), ctypes.c_void_p(aligned), int(need.value),
+                                  ctypes.c_void_p(_stream(stream)), None, flags, diffs, gdiffs))
     del keep, ws
-    return [bool(v) for v in flags], [float(v) for v in diffs]
+    return ([bool(v) for v in flags], [float(v) for v in diffs],
+            [float(v) for v in gdiffs] if lam0 is not None else None)
+
+
+def probe_lds_atomics(f32: bool = False, device: str = "cuda", stream=None) -> float:
+    """fk_probe_lds_atomics: lane-level LDS atomic adds per second (FP64 or
+    FP32, conflict-free addresses)."""
+    import torch
+    ws = torch.empty(2048, dtype=torch.float64, device=torch.device(device))
+    rate = ctypes.c_double(0.0)
+    _check(load().fk_probe_lds_atomics(int(bool(f32)), ctypes.byref(rate), ctypes.c_void_p(_ptr(ws)),
+                                       2048 * 8, ctypes.c_void_p(_stream(stream))))
+    return float(rate.value)
 
 
 def solve(problems, snaps: Sequence[int] = (0,), **plan_kw):
