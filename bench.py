@@ -454,10 +454,12 @@ def main():
         # its ceiling on this device: FP64 LDS atomic adds, 2^d (d+1) per
         # inside landing point, against the rate measured live by the probe
         peak = probe_lds_atomics(f32=False)
+        peak32 = probe_lds_atomics(f32=True)
         adds = n_point * Q * (1 << d) * (d + 1)
         rate = adds / (ms_k * 1e-3)
         roof["lds_fp64_atomic_adds"] = {
             "per_launch_upper_bound": adds, "achieved_per_s": rate, "probe_peak_per_s": peak,
+            "probe_f32_adds_per_s": peak32,
             "frac": round(rate / peak, 4),
             "note": "lane-level ds_add_f64; peak from fk_probe_lds_atomics (2048 x 256 lanes, "
                     "conflict-free) on this device, this run"}

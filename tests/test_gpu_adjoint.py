@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
+from bars import STATE_REL_DIFF, lamN_sensitivity
 import workloads as W
 
 torch = pytest.importorskip("torch")
@@ -60,11 +61,15 @@ def test_adjoint_matches_oracle_fp64(case, kernel):
     nt = len(g_ref)
     print(case, g[:nt], g_ref, "lamN rel", _rel(lamN, lamN_ref))
     assert _rel(g[:nt], g_ref) <= 1e-10
-    # lam^N passes through the PCHIP Jacobian of u^1, whose derivative depends
-    # on the ratio of divided differences: where rows are nearly flat (the box
-    # case has translation-invariant rows) their rounding is amplified, so the
-    # bar there reflects that conditioning
-    assert _rel(lamN, lamN_ref) <= (1e-8 if case == "box2d" else 1e-11)
+    # lam^N passes through the PCHIP Jacobian of every u^n, whose derivative
+    # depends on the ratio of divided differences: where rows are nearly flat
+    # (the box case has translation-invariant rows) their rounding is
+    # amplified.  The bar is the oracle's own change of lam^N per unit relative
+    # perturbation of its states times the relative difference of the two
+    # state sequences (and never below 1e-11)
+    bar = max(1e-11, 4.0 * lamN_sensitivity(prob, lam0) * STATE_REL_DIFF)
+    print(case, "lamN bar", bar)
+    assert _rel(lamN, lamN_ref) <= bar
 
 
 def test_checkpoint_interval_does_not_change_result():

@@ -883,22 +883,6 @@ def test_flat_rule_makes_lamN_a_smooth_function_of_the_states():
     assert worst > 1e-3, worst
 
 
-def lamN_sensitivity(prob, lam0, rel=2.0 ** -44, trials=3, seed=7):
-    """Largest relative change of the oracle's dJ/du^N per unit relative
-    perturbation of its stored states (used to set the dJ/du^N bar of the GPU
-    comparison from the rounding difference of the two state sequences)."""
-    U = oracle.solve_all(prob)
-    _, l0 = oracle.adjoint_states(prob, U, lam0)
-    rng = np.random.default_rng(seed)
-    inner = (U > 0) & (U < 1)
-    worst = 0.0
-    for _ in range(trials):
-        Up = np.where(inner, U * (1 + rel * rng.uniform(-1, 1, size=U.shape)), U)
-        _, l = oracle.adjoint_states(prob, Up, lam0)
-        worst = max(worst, float(np.abs(l - l0).max() / np.abs(l0).max()) / rel)
-    return worst
-
-
 # ---------------------------------------------------------------------------
 # Algorithm 1 (Section 3.2): several horizons in one backward sweep
 # ---------------------------------------------------------------------------
