@@ -60,6 +60,7 @@ class _Problem(ctypes.Structure):
         ("dt", ctypes.c_double),
         ("n_steps", ctypes.c_int),
         ("t0", ctypes.c_double),
+        ("hermite", ctypes.c_int),
     ]
 
 
@@ -87,6 +88,7 @@ def _load():
             "fko_landing": (None, [P, ctypes.c_int, ctypes.c_long, ctypes.c_int, dp]),
             "fko_cell": (ctypes.c_int, [dp, ctypes.c_int, ctypes.c_double]),
             "fko_slopes": (None, [P, dp, dp]),
+            "fko_num_fields": (ctypes.c_int, [P]),
             "fko_interp": (ctypes.c_double, [P, dp, dp, dp]),
             "fko_interp_grad": (None, [P, dp, dp, dp, dp]),
             "fko_step": (ctypes.c_int, [P, ctypes.c_int, dp, dp]),
@@ -155,6 +157,7 @@ class OracleProblem:
         s.dt = float(prob.dt)
         s.n_steps = int(prob.n_steps)
         s.t0 = float(prob.t0)
+        s.hermite = 2 if getattr(prob, "hermite", "r1") == "r2" else 1
         self.s = s
         self.Q = q ** prob.d
         self.J = int(np.prod(prob.shape))
@@ -221,12 +224,16 @@ def is_exit_point(prob, z) -> bool:
 
 
 def slopes(prob, u: np.ndarray) -> np.ndarray:
-    """PCHIP slopes along every axis; shape (d,) + grid shape."""
+    """Derivative fields: the PCHIP slopes along every axis and, for the R2
+    interpolant, the twist fields ({0,1}, {0,2}, {1,2}, {0,1,2});
+    shape (fields,) + grid shape."""
     op = _op(prob)
+    lib = _load()
+    nf = int(lib.fko_num_fields(op.ptr))
     uu = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
-    g = np.zeros(op.J * op.prob.d)
-    _load().fko_slopes(op.ptr, _dp(uu), _dp(g))
-    return g.reshape((op.prob.d,) + tuple(op.shape))
+    g = np.zeros(op.J * nf)
+    lib.fko_slopes(op.ptr, _dp(uu), _dp(g))
+    return g.reshape((nf,) + tuple(op.shape))
 
 
 def interp(prob, u: np.ndarray, g: np.ndarray, z, grad: bool = False):

@@ -55,6 +55,8 @@ typedef struct {
     double dt;
     int n_steps;
     double t0;              /* step n evaluates coefficients at t0 + n dt */
+    int hermite;            /* 1: values and first derivatives (R1); 2: with the
+                               mixed derivatives (twist fields, R2) */
 } fko_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -353,26 +355,60 @@ static void slope_stencil(const fko_problem *P, int ax, int i, int *il, int *ic,
     }
 }
 
-/* g[a * J + j] = slope of u along axis a at node j. */
+/* PCHIP slope of the field f along axis ax at every node: out[j]. */
+static void slope_along(const fko_problem *P, int ax, const double *f, double *out)
+{
+    long J = fko_num_nodes(P);
+#pragma omp parallel for schedule(static)
+    for (long j = 0; j < J; j++) {
+        int i[3], il, ic, ir, kind;
+        double hl, hr;
+        node_index(P, j, i);
+        slope_stencil(P, ax, i[ax], &il, &ic, &ir, &hl, &hr, &kind);
+        int t[3];
+        memcpy(t, i, sizeof(t));
+        t[ax] = il; double ul = f[node_linear(P, t)];
+        t[ax] = ic; double uc = f[node_linear(P, t)];
+        t[ax] = ir; double ur = f[node_linear(P, t)];
+        double dl = (uc - ul) / hl;
+        double dr = (ur - uc) / hr;
+        out[j] = pchip_pair(dl, dr);
+    }
+}
+
+/* Derivative fields of the interpolant.  Field f = 0 .. d-1 is the slope
+ * along axis f.  With the mixed derivatives (R2) the fields that follow are
+ * the twist fields, one per set S of two or more axes, in the order
+ * {0,1}, {0,2}, {1,2}, {0,1,2} (2D: {0,1} only); the field of S is the PCHIP
+ * slope along the largest axis of S of the field of S without that axis, i.e.
+ * the one-dimensional rule composed in increasing axis order
+ * (u_xy = D_y(D_x u), u_xyz = D_z(D_y(D_x u))). */
+int fko_num_fields(const fko_problem *P)
+{
+    return P->hermite == 2 ? (1 << P->d) - 1 : P->d;
+}
+
+/* Axis set of derivative field f, as a bit mask (bit a: axis a). */
+static int field_mask(const fko_problem *P, int f)
+{
+    static const int twist3[4] = {3, 5, 6, 7};
+    if (f < P->d) return 1 << f;
+    return P->d == 2 ? 3 : twist3[f - 3];
+}
+
+/* g[f * J + j] = derivative field f (fko_num_fields) at node j. */
 void fko_slopes(const fko_problem *P, const double *u, double *g)
 {
     long J = fko_num_nodes(P);
-    for (int ax = 0; ax < P->d; ax++) {
-#pragma omp parallel for schedule(static)
-        for (long j = 0; j < J; j++) {
-            int i[3], il, ic, ir, kind;
-            double hl, hr;
-            node_index(P, j, i);
-            slope_stencil(P, ax, i[ax], &il, &ic, &ir, &hl, &hr, &kind);
-            int t[3];
-            memcpy(t, i, sizeof(t));
-            t[ax] = il; double ul = u[node_linear(P, t)];
-            t[ax] = ic; double uc = u[node_linear(P, t)];
-            t[ax] = ir; double ur = u[node_linear(P, t)];
-            double dl = (uc - ul) / hl;
-            double dr = (ur - uc) / hr;
-            g[ax * J + j] = pchip_pair(dl, dr);
-        }
+    for (int ax = 0; ax < P->d; ax++) slope_along(P, ax, u, g + (long)ax * J);
+    for (int f = P->d; f < fko_num_fields(P); f++) {
+        int m = field_mask(P, f), top = 0;
+        for (int a = 0; a < P->d; a++)
+            if (m & (1 << a)) top = a;
+        int base = m & ~(1 << top), fb = -1;
+        for (int k = 0; k < f; k++)
+            if (field_mask(P, k) == base) fb = k;
+        slope_along(P, top, g + (long)fb * J, g + (long)f * J);
     }
 }
 
@@ -408,6 +444,35 @@ static void locate(const fko_problem *P, const double *z, int *k, double *s, dou
     }
 }
 
+/* Value of the full tensor cubic Hermite interpolant (R2) of u and its
+ * derivative fields at z: per cell corner and per axis set S (S empty: u),
+ * the field of S times prod_{a in S} h_a H1(s_a) prod_{a not in S} H0(s_a). */
+static double interp_full(const fko_problem *P, const double *u, const double *g,
+                          const double *z)
+{
+    long J = fko_num_nodes(P);
+    int k[3], corner[3], bit[3];
+    double s[3], h[3];
+    locate(P, z, k, s, h);
+    int nf = fko_num_fields(P);
+    double val = 0.0;
+    for (int c = 0; c < (1 << P->d); c++) {
+        for (int a = 0; a < P->d; a++) {
+            bit[a] = (c >> (P->d - 1 - a)) & 1;
+            corner[a] = k[a] + bit[a];
+        }
+        long node = node_linear(P, corner);
+        for (int f = -1; f < nf; f++) {
+            int m = f < 0 ? 0 : field_mask(P, f);
+            double w = 1.0;
+            for (int a = 0; a < P->d; a++)
+                w = w * ((m & (1 << a)) ? h[a] * H1(bit[a], s[a]) : H0(bit[a], s[a]));
+            val += (f < 0 ? u[node] : g[(long)f * J + node]) * w;
+        }
+    }
+    return val;
+}
+
 /* Value of the interpolant of (u, g) at z; optionally its gradient. */
 static double interp(const fko_problem *P, const double *u, const double *g,
                      const double *z, double *grad)
@@ -415,6 +480,7 @@ static double interp(const fko_problem *P, const double *u, const double *g,
     long J = fko_num_nodes(P);
     int k[3], corner[3];
     double s[3], h[3];
+    if (P->hermite == 2) return interp_full(P, u, g, z);
     locate(P, z, k, s, h);
     double val = 0.0;
     if (grad) for (int a = 0; a < P->d; a++) grad[a] = 0.0;
@@ -535,7 +601,7 @@ int fko_step(const fko_problem *P, int n, const double *u_next, double *u_out)
     long J = fko_num_nodes(P);
     long Ja = fko_active_nodes(P, NULL);
     long *active = (long *)malloc(sizeof(long) * (Ja > 0 ? Ja : 1));
-    double *g = (double *)malloc(sizeof(double) * J * P->d);
+    double *g = (double *)malloc(sizeof(double) * J * fko_num_fields(P));
     if (!active || !g) { free(active); free(g); return -1; }
     fko_active_nodes(P, active);
     fko_slopes(P, u_next, g);
@@ -553,7 +619,7 @@ int fko_step_cells(const fko_problem *P, int n, const double *u_next, int *cells
     long J = fko_num_nodes(P);
     long Ja = fko_active_nodes(P, NULL);
     long *active = (long *)malloc(sizeof(long) * (Ja > 0 ? Ja : 1));
-    double *g = (double *)malloc(sizeof(double) * J * P->d);
+    double *g = (double *)malloc(sizeof(double) * J * fko_num_fields(P));
     double *tmp = (double *)malloc(sizeof(double) * J);
     if (!active || !g || !tmp) { free(active); free(g); free(tmp); return -1; }
     fko_active_nodes(P, active);
@@ -587,7 +653,7 @@ int fko_solve(const fko_problem *P, const int *snap, int n_snap, double *out,
     long *active = (long *)malloc(sizeof(long) * (Ja > 0 ? Ja : 1));
     double *u = (double *)malloc(sizeof(double) * J);
     double *v = (double *)malloc(sizeof(double) * J);
-    double *g = (double *)malloc(sizeof(double) * J * P->d);
+    double *g = (double *)malloc(sizeof(double) * J * fko_num_fields(P));
     if (!active || !u || !v || !g) { free(active); free(u); free(v); free(g); return -1; }
     fko_active_nodes(P, active);
     fko_chi(P, u);
@@ -628,7 +694,7 @@ int fko_solve_horizons(const fko_problem *P, const int *m, int n_h, double *out)
         if (m[h] > M) M = m[h];
     }
     long *active = (long *)malloc(sizeof(long) * (Ja > 0 ? Ja : 1));
-    double *g = (double *)malloc(sizeof(double) * J * P->d);
+    double *g = (double *)malloc(sizeof(double) * J * fko_num_fields(P));
     double *v = (double *)malloc(sizeof(double) * J);
     if (!active || !g || !v) { free(active); free(g); free(v); return -1; }
     fko_active_nodes(P, active);
@@ -655,6 +721,7 @@ int fko_solve_horizons(const fko_problem *P, const int *m, int n_h, double *out)
  * landing points, so that u^n_j = exit_mass + row . [u; g]. */
 int fko_assemble_row(const fko_problem *P, int n, long j, double *row, double *exit_mass)
 {
+    if (P->hermite == 2) return -3;   /* rows of the values and first derivatives only */
     long J = fko_num_nodes(P);
     int Q = 1;
     for (int a = 0; a < P->d; a++) Q *= P->gh_n;
@@ -752,6 +819,7 @@ static void slopes_transpose(const fko_problem *P, const double *u, const double
 int fko_adjoint_states(const fko_problem *P, const double *U, const double *lam0,
                        double *grad, double *lamN, const unsigned char *exit_use)
 {
+    if (P->hermite == 2) return -3;   /* the adjoint linearises the R1 interpolant */
     long J = fko_num_nodes(P);
     int N = P->n_steps;
     int nt = fko_num_theta(P);
@@ -759,7 +827,7 @@ int fko_adjoint_states(const fko_problem *P, const double *U, const double *lam0
     for (int a = 0; a < P->d; a++) Q *= P->gh_n;
     long Ja = fko_active_nodes(P, NULL);
     long *active = (long *)malloc(sizeof(long) * (Ja > 0 ? Ja : 1));
-    double *g = (double *)malloc(sizeof(double) * J * P->d);
+    double *g = (double *)malloc(sizeof(double) * J * fko_num_fields(P));
     double *lam = (double *)malloc(sizeof(double) * J);
     double *mu = (double *)malloc(sizeof(double) * J * (P->d + 1));
     char *cls = (char *)malloc((size_t)J);
@@ -873,7 +941,7 @@ int fko_solve_all(const fko_problem *P, double *U, const unsigned char *exit_use
     int N = P->n_steps;
     long Ja = fko_active_nodes(P, NULL);
     long *active = (long *)malloc(sizeof(long) * (Ja > 0 ? Ja : 1));
-    double *g = (double *)malloc(sizeof(double) * J * P->d);
+    double *g = (double *)malloc(sizeof(double) * J * fko_num_fields(P));
     if (!active || !g) { free(active); free(g); return -1; }
     fko_active_nodes(P, active);
     fko_chi(P, U + (long)N * J);

@@ -957,3 +957,116 @@ def test_algorithm1_exit_probability_grows_with_horizon():
     near = np.abs(np.hypot(X - 0.5, Y - 0.5) - prob.radius) <= 2.0 / 32
     assert inc[:, ~near].min() >= -1e-4, inc[:, ~near].min()
     assert inc.min() >= -1e-2, inc.min()
+
+
+# ---------------------------------------------------------------------------
+# The R2 interpolant: full tensor cubic Hermite with PCHIP-composed twist
+# fields (Section 3.1.2, "tensor product"; the mixed derivatives the R1
+# reading leaves out)
+# ---------------------------------------------------------------------------
+
+
+def _grid2d(r2=True):
+    prob = W.Problem(axes=[W.uniform_axis(0.0, 1.0, 9), W.uniform_axis(-1.0, 0.6, 7)],
+                     coef_kind="const", coef=(0.0, 0.0), D=0.0, region_kind="box",
+                     gh_q=1, dt=0.01, n_steps=1, hermite="r2" if r2 else "r1")
+    X, Y = np.meshgrid(prob.axes[0].nodes, prob.axes[1].nodes, indexing="ij")
+    return prob, X, Y
+
+
+def test_r2_exact_on_tensor_products_of_cubics():
+    """With exact value, slope and twist fields the R2 interpolant reproduces
+    p(x) q(y) (2D) and p(x) q(y) r(z) (3D) for cubics p, q, r to rounding."""
+    p = np.polynomial.Polynomial([0.3, -1.2, 0.7, 2.1])
+    q = np.polynomial.Polynomial([1.1, 0.4, -0.9, 0.5])
+    r = np.polynomial.Polynomial([-0.2, 0.8, 0.3, -0.6])
+    prob, X, Y = _grid2d()
+    u = p(X) * q(Y)
+    g = np.stack([p.deriv()(X) * q(Y), p(X) * q.deriv()(Y), p.deriv()(X) * q.deriv()(Y)])
+    rng = np.random.default_rng(31)
+    for _ in range(40):
+        z = [rng.uniform(0, 1), rng.uniform(-1, 0.6)]
+        assert abs(oracle.interp(prob, u, g, z) - p(z[0]) * q(z[1])) <= 1e-13
+    prob3 = W.Problem(axes=[W.uniform_axis(0, 1, 6), W.uniform_axis(0, 2, 5), W.uniform_axis(-1, 1, 7)],
+                      coef_kind="const", coef=(0.0, 0.0, 0.0), D=0.0, region_kind="box",
+                      gh_q=1, dt=0.01, n_steps=1, hermite="r2")
+    A, B, C = np.meshgrid(*[ax.nodes for ax in prob3.axes], indexing="ij")
+    P0, P1 = p(A), p.deriv()(A)
+    Q0, Q1 = q(B), q.deriv()(B)
+    R0, R1 = r(C), r.deriv()(C)
+    u3 = P0 * Q0 * R0
+    # fields: d/dx, d/dy, d/dz, then {x,y}, {x,z}, {y,z}, {x,y,z}
+    g3 = np.stack([P1 * Q0 * R0, P0 * Q1 * R0, P0 * Q0 * R1,
+                   P1 * Q1 * R0, P1 * Q0 * R1, P0 * Q1 * R1, P1 * Q1 * R1])
+    for _ in range(40):
+        z = [rng.uniform(0, 1), rng.uniform(0, 2), rng.uniform(-1, 1)]
+        assert abs(oracle.interp(prob3, u3, g3, z) - p(z[0]) * q(z[1]) * r(z[2])) <= 1e-12
+
+
+def test_r1_misses_exactly_the_twist_term_on_bilinear_data():
+    """u = a + b x + c y + d x y: the PCHIP slopes and the composed twist are
+    exact on bilinear data, so R2 reproduces u exactly, while R1 misses
+    d h_x h_y s(1-s)(1-2s) t(1-t)(1-2t) -- the closed form of the dropped
+    twist term (its sign and scale)."""
+    a, b, c, d = 0.2, -0.7, 0.4, 1.3
+    prob, X, Y = _grid2d()
+    u = a + b * X + c * Y + d * X * Y
+    g2 = oracle.slopes(prob, u)
+    assert g2.shape[0] == 3
+    np.testing.assert_allclose(g2[2], d, atol=1e-13)
+    prob1 = prob.replace(hermite="r1")
+    g1 = oracle.slopes(prob1, u)
+    assert g1.shape[0] == 2
+    hx = prob.axes[0].nodes[1] - prob.axes[0].nodes[0]
+    hy = prob.axes[1].nodes[1] - prob.axes[1].nodes[0]
+    rng = np.random.default_rng(32)
+    for _ in range(30):
+        z = [rng.uniform(0, 1), rng.uniform(-1, 0.6)]
+        exact = a + b * z[0] + c * z[1] + d * z[0] * z[1]
+        assert abs(oracle.interp(prob, u, g2, z) - exact) <= 1e-13
+        k0 = oracle.cell(prob.axes[0].nodes, z[0])
+        k1 = oracle.cell(prob.axes[1].nodes, z[1])
+        s = (z[0] - prob.axes[0].nodes[k0]) / hx
+        t = (z[1] - prob.axes[1].nodes[k1]) / hy
+        miss = d * hx * hy * s * (1 - s) * (1 - 2 * s) * t * (1 - t) * (1 - 2 * t)
+        assert abs((exact - oracle.interp(prob1, u, g1, z)) - miss) <= 1e-13
+
+
+def test_r2_step_translates_bilinear_data_exactly():
+    """sigma = 0, constant drift, no exit reachable: one step moves bilinear
+    data by b dt exactly with R2 (rounding), not with R1."""
+    a, b, c, d = 0.1, 0.5, -0.3, 0.9
+    axes = [W.uniform_axis(0.0, 1.0, 21), W.uniform_axis(0.0, 1.0, 17)]
+    prob = W.Problem(axes=axes, coef_kind="const", coef=(0.37, -0.21), D=0.0,
+                     region_kind="box", gh_q=1, dt=0.03, n_steps=1, hermite="r2")
+    X, Y = np.meshgrid(axes[0].nodes, axes[1].nodes, indexing="ij")
+    u = a + b * X + c * Y + d * X * Y
+    inner = (X > 0.2) & (X < 0.8) & (Y > 0.2) & (Y < 0.8)
+    Xs, Ys = X + 0.37 * 0.03, Y - 0.21 * 0.03
+    want = a + b * Xs + c * Ys + d * Xs * Ys
+    got2 = oracle.step(prob, 0, u)
+    got1 = oracle.step(prob.replace(hermite="r1"), 0, u)
+    assert np.abs(got2 - want)[inner].max() <= 1e-13
+    assert np.abs(got1 - want)[inner].max() > 1e-7
+
+
+def test_r2_twist_field_is_pchip_composed_x_then_y():
+    """The twist field is the PCHIP slope along y of the PCHIP slope along x
+    (reading: the one-dimensional rule composed in increasing axis order).
+    Pinned against scipy's PchipInterpolator, whose interior slopes on a
+    uniform axis are the paper's harmonic mean: at interior nodes whose
+    stencils stay interior, on data where the limiter acts (the two orders of
+    composition differ there)."""
+    from scipy.interpolate import PchipInterpolator
+    prob, X, Y = _grid2d()
+    rng = np.random.default_rng(33)
+    u = np.sin(2.5 * X) * np.cos(1.7 * Y) + 0.3 * rng.uniform(-1, 1, size=X.shape)
+    g = oracle.slopes(prob, u)
+    x, y = prob.axes[0].nodes, prob.axes[1].nodes
+    gx = np.stack([PchipInterpolator(x, u[:, j]).derivative()(x) for j in range(len(y))], axis=1)
+    gxy = np.stack([PchipInterpolator(y, gx[i, :]).derivative()(y) for i in range(len(x))], axis=0)
+    gy = np.stack([PchipInterpolator(y, u[i, :]).derivative()(y) for i in range(len(x))], axis=0)
+    gyx = np.stack([PchipInterpolator(x, gy[:, j]).derivative()(x) for j in range(len(y))], axis=1)
+    sl = (slice(2, -2), slice(2, -2))    # stencils of stencils stay interior
+    np.testing.assert_allclose(g[2][sl], gxy[sl], atol=1e-12)
+    assert np.abs(gxy - gyx)[sl].max() > 1e-3

@@ -90,6 +90,7 @@ class Problem:
     n_steps: int = 1
     t0: float = 0.0
     name: str = ""
+    hermite: str = "r1"   # "r1": values and first derivatives; "r2": also the mixed ones
 
     @property
     def d(self) -> int:
