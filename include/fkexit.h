@@ -86,6 +86,17 @@ enum { FK_REGION_BOX = 0, FK_REGION_BALL = 1 };
  * stored fields in FP32. */
 enum { FK_PREC_F64 = 0, FK_PREC_F32 = 1 };
 
+/* Interpolant (Section 3.1.2, a tensor product of cubic Hermite bases).
+ * FK_HERMITE_R1: values and first derivatives (the nodal slopes of Eq. (e300)
+ * along each axis; the column blocks of Psi^n in Eq. (e34)).
+ * FK_HERMITE_R2: also the mixed derivatives, the twist field of an axis set
+ * composed from the one-dimensional rule in increasing axis order
+ * (u_xy = D_y(D_x u)); exact on tensor products of cubics given exact fields.
+ * R2 is built for d <= 2 (1D: the same as R1), the fused form and the
+ * forward pass (fk_forward, fk_forward_from, fk_step, fk_forward_horizons);
+ * other combinations are FK_ERR_UNSUPPORTED. */
+enum { FK_HERMITE_R1 = 0, FK_HERMITE_R2 = 1 };
+
 /* FK_FORM_FUSED: matrix-free step (landing, weights and contraction in one
  * kernel).  FK_FORM_ELL: the step operator A_n = Q Psi^n (Eq. (e36)) is
  * assembled each step into ELL-like storage and then applied as a sparse
@@ -143,7 +154,7 @@ typedef struct {
     int columns;     /* fk_forward_horizons: most columns one launch of the
                         FK_FORM_ELL product takes (1..4; 0 = 1); the workspace
                         holds that many record planes */
-    int reserved;
+    int hermite;     /* FK_HERMITE_R1 (default) | FK_HERMITE_R2 */
 } fk_options;
 
 typedef struct {

@@ -420,8 +420,9 @@ __device__ inline void store_node(const DevInst &I, const int *idx, long long no
 }
 
 // Hermite value of the corner records p at one landing point; the value
-// entries enter as offsets (p.x - uref).
-template <typename T, int D, typename R>
+// entries enter as offsets (p.x - uref).  TW (2D): the R2 interpolant, whose
+// records carry the twist field in their fourth entry.
+template <typename T, int D, typename R, bool TW = false>
 __device__ inline T hermite_value(const R *p, const Basis<T> *B, T uref)
 {
     if constexpr (D == 1) {
@@ -432,8 +433,12 @@ __device__ inline T hermite_value(const R *p, const Basis<T> *B, T uref)
         const Basis<T> &X = B[0], &Y = B[1];
         const T A0 = (p[0].x - uref) * X.v0 + (p[2].x - uref) * X.v1 + p[0].y * X.d0 + p[2].y * X.d1;
         const T A1 = (p[1].x - uref) * X.v0 + (p[3].x - uref) * X.v1 + p[1].y * X.d0 + p[3].y * X.d1;
-        const T C0 = p[0].z * X.v0 + p[2].z * X.v1;
-        const T C1 = p[1].z * X.v0 + p[3].z * X.v1;
+        T C0 = p[0].z * X.v0 + p[2].z * X.v1;
+        T C1 = p[1].z * X.v0 + p[3].z * X.v1;
+        if constexpr (TW) {
+            C0 += p[0].w * X.d0 + p[2].w * X.d1;
+            C1 += p[1].w * X.d0 + p[3].w * X.d1;
+        }
         return Y.v0 * A0 + Y.v1 * A1 + Y.d0 * C0 + Y.d1 * C1;
     } else {
         // corners p[(a*2 + b)*2 + c]
@@ -567,6 +572,58 @@ __global__ void __launch_bounds__(kBlock) k_init_field(const unsigned char *cls,
         u[i] = (T)(cls[i] & 1);
 }
 
+// Stencil of the PCHIP slope along axis a at index i (Eq. (e300) and the end
+// rule after it): the three nodes along the axis and the two spacings.
+__device__ inline void slope_stencil(const DevInst &I, const double *coords, int a, int i,
+                                     int &il, int &ic, int &ir, double &hl, double &hr)
+{
+    const int na = I.n[a];
+    if (I.periodic[a]) {
+        ic = (i == na - 1) ? 0 : i;
+        il = (ic == 0) ? na - 2 : ic - 1;
+        ir = ic + 1;
+    } else if (i == 0) {
+        il = 0; ic = 1; ir = 2;
+    } else if (i == na - 1) {
+        il = na - 3; ic = na - 2; ir = na - 1;
+    } else {
+        il = i - 1; ic = i; ir = i + 1;
+    }
+    if (I.affine[a]) {
+        hl = I.step[a];
+        hr = I.step[a];
+    } else {
+        const double *x = coords + I.coord_off[a];
+        hl = (ic == 0) ? x[na - 1] - x[na - 2] : x[ic] - x[il];
+        hr = x[ir] - x[ic];
+    }
+}
+
+template <typename T>
+__device__ inline T pchip_slope(T dl, T dr)
+{
+    return (dl * dr > T(0)) ? T(2) * dl * dr / (dl + dr) : T(0);
+}
+
+// Twist field of the R2 interpolant at node idx of a 2D instance: the PCHIP
+// slope along axis 1 of the axis-0 slopes at the three nodes of its axis-1
+// stencil (each from the axis-0 stencil of that row).
+template <typename T>
+__device__ inline T twist_2d(const DevInst &I, const double *coords, const T *ui, const int *idx)
+{
+    int il0, ic0, ir0, il1, ic1, ir1;
+    double hl0, hr0, hl1, hr1;
+    slope_stencil(I, coords, 0, idx[0], il0, ic0, ir0, hl0, hr0);
+    slope_stencil(I, coords, 1, idx[1], il1, ic1, ir1, hl1, hr1);
+    const long long s0 = I.stride[0];
+    auto g0 = [&](int j) -> T {
+        const T ul = ui[il0 * s0 + j], uc = ui[ic0 * s0 + j], ur = ui[ir0 * s0 + j];
+        return pchip_slope<T>((uc - ul) / (T)hl0, (ur - uc) / (T)hr0);
+    };
+    const T gl = g0(il1), gc = g0(ic1), gr = g0(ir1);
+    return pchip_slope<T>((gc - gl) / (T)hl1, (gr - gc) / (T)hr1);
+}
+
 // Slope pass for step n over work items [first, first + count): table items
 // (kind 1 + a) fill the (sin, cos) table of axis a; node items (kind 0) write
 // record[node] = (u, g_0, .., g_{d-1}).
@@ -627,6 +684,11 @@ __global__ void __launch_bounds__(kBlock) k_slopes(PlanDev P, int n, int first, 
             const T dl = (uc - ul) / (T)hl;
             const T dr = (ur - uc) / (T)hr;
             out[1 + a] = (dl * dr > T(0)) ? T(2) * dl * dr / (dl + dr) : T(0);
+        }
+        if constexpr (D == 2) {
+            // R2 twist: the PCHIP slope along axis 1 of the axis-0 slope field
+            // (the one-dimensional rule composed in increasing axis order)
+            if (P.hermite2) out[3] = twist_2d<T>(I, P.coords, ui, idx);
         }
         R r;
         if constexpr (PS == 2) {
@@ -751,7 +813,10 @@ __global__ void __launch_bounds__(kBlock) k_step_fused(
                     }
                     R p[1 << D];
                     gather_corners<D, R>(rec, I, k, p);
-                    acc += wq[i] * hermite_value<T, D, R>(p, B, uref);
+                    if (D == 2 && P.hermite2)
+                        acc += wq[i] * hermite_value<T, D, R, true>(p, B, uref);
+                    else
+                        acc += wq[i] * hermite_value<T, D, R>(p, B, uref);
                 }
             }
         }
@@ -775,7 +840,7 @@ __global__ void __launch_bounds__(kBlock) k_step_fused(
 //
 // G > 1 (small plans): G lanes share a node, lane l taking the outermost
 // axis' indices l, l + G, ...; the lane sums are combined by a shuffle tree.
-template <typename T, int D, int QS, int G, bool AFF>
+template <typename T, int D, int QS, int G, bool AFF, bool TW = false>
 __global__ void __launch_bounds__(kBlock) k_step_node(
     const PlanDev P, int n, int n_work, const DevInst *__restrict__ insts,
     const WorkItem *__restrict__ work, const int *__restrict__ nodes,
@@ -848,8 +913,13 @@ __global__ void __launch_bounds__(kBlock) k_step_node(
                 const R p00 = ri[b], p01 = ri[b + 1], p10 = ri[b + s0], p11 = ri[b + s0 + 1];
                 const T A0 = (p00.x - uref) * X.v0 + (p10.x - uref) * X.v1 + p00.y * X.d0 + p10.y * X.d1;
                 const T A1 = (p01.x - uref) * X.v0 + (p11.x - uref) * X.v1 + p01.y * X.d0 + p11.y * X.d1;
-                const T C0 = p00.z * X.v0 + p10.z * X.v1;
-                const T C1 = p01.z * X.v0 + p11.z * X.v1;
+                T C0 = p00.z * X.v0 + p10.z * X.v1;
+                T C1 = p01.z * X.v0 + p11.z * X.v1;
+                if constexpr (TW) {
+                    // R2: the twist field times the slope bases of both axes
+                    C0 += p00.w * X.d0 + p10.w * X.d1;
+                    C1 += p01.w * X.d0 + p11.w * X.d1;
+                }
                 return w1[q1] * (bin[q1][0] * A0 + bin[q1][1] * A1 + bin[q1][2] * C0 + bin[q1][3] * C1);
             };
             if (interior) {
@@ -1046,7 +1116,7 @@ __device__ inline int wrap_index(int i, int n, int per)
 // the records, with per-axis vector sets (Va, Sa) for each axis.
 template <typename T, int D, int L, typename R>
 __device__ inline T box_contract(const R *rec, const DevInst &I, const int *o, T uref,
-                                 const T (*V)[L], const T (*Sv)[L])
+                                 const T (*V)[L], const T (*Sv)[L], bool tw = false)
 {
     if constexpr (D == 1) {
         T acc = T(0);
@@ -1071,6 +1141,7 @@ __device__ inline T box_contract(const R *rec, const DevInst &I, const int *o, T
                 const R r = rec[row + j1[j]];
                 tv += V[1][j] * (r.x - uref) + Sv[1][j] * r.z;
                 tg += V[1][j] * r.y;
+                if (tw) tg += Sv[1][j] * r.w;   // R2 twist
             }
             acc += V[0][i] * tv + Sv[0][i] * tg;
         }
@@ -1147,7 +1218,7 @@ __global__ void __launch_bounds__(kBlock) k_step_box(
 #pragma unroll
         for (int a = 1; a < D; ++a) { prod *= m[a]; wd *= wsum; }
         const T emass = wd - prod;
-        const T acc = box_contract<T, D, L, R>(rec, I, o, uref, V, Sv);
+        const T acc = box_contract<T, D, L, R>(rec, I, o, uref, V, Sv, P.hermite2 != 0);
         const T v = uref + acc + emass * (T(1) - uref);
         flag_nonfinite(P.flags, v);
         store_node<D, T>(I, idx, node, v, u_out);

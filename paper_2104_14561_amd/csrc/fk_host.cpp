@@ -1084,6 +1084,7 @@ void fill_dev(fk_plan *p)
     D.n_steps = p->N;
     D.block = kBlock;
     D.group = p->G;
+    D.hermite2 = (p->opt.hermite == FK_HERMITE_R2 && p->d == 2) ? 1 : 0;
     D.all_affine = 1;
     for (const fk::DevInst &I : p->inst)
         for (int a = 0; a < p->d; ++a)
@@ -1338,6 +1339,13 @@ fk_status fk_plan_create(const fk_problem *probs, int n_inst, const fk_options *
     if (o.block != 0 && o.block != kBlock) return fail(FK_ERR_UNSUPPORTED, "block must be 0 or 256");
     if (o.step_kernel < 0 || o.step_kernel > 4) return fail(FK_ERR_ARG, "step_kernel must be 0..4");
     if (o.columns < 0 || o.columns > 4) return fail(FK_ERR_ARG, "columns must be 0..4");
+    if (o.hermite != FK_HERMITE_R1 && o.hermite != FK_HERMITE_R2)
+        return fail(FK_ERR_ARG, "hermite must be FK_HERMITE_R1 or FK_HERMITE_R2");
+    if (o.hermite == FK_HERMITE_R2) {
+        if (probs[0].d > 2) return fail(FK_ERR_UNSUPPORTED, "the R2 interpolant is built for d <= 2");
+        if (o.form != FK_FORM_FUSED) return fail(FK_ERR_UNSUPPORTED, "the R2 interpolant needs the fused form");
+        if (o.ckpt_every > 0) return fail(FK_ERR_UNSUPPORTED, "no adjoint of the R2 interpolant");
+    }
     if ((o.step_kernel == 1 || o.step_kernel == 3 || o.step_kernel == 4) &&
         !fk::step_node_compiled(probs[0].d, probs[0].gh_q))
         return fail(FK_ERR_UNSUPPORTED, "no thread-per-node kernel compiled for d=%d, gh_q=%d",

@@ -117,6 +117,7 @@ struct PlanDev {
     int group;                  // lanes per active node in the step passes
     int step_kind;              // 0: thread per node, 1: lane group, 2: split node
     int all_affine;             // every axis of every instance is affine
+    int hermite2;               // R2 interpolant (2D): twist field in the records
     // forward step work: nodes handled per landing point (fw) and separable
     // nodes handled in box form, by box class
     const int *fw_nodes;

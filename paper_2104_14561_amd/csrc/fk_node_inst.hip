@@ -37,9 +37,17 @@ template <typename T, int D, int QS>
 void step_node_launch(const PlanDev &P, int n, const void *packed, void *u_out, hipStream_t s)
 {
     constexpr int GS = (QS <= 2) ? 2 : (QS <= 4) ? 4 : (QS <= 8) ? 8 : 16;
-#define FK_NODE(G_, AFF_, grid_, nw_, wl_)                                                     \
-    k_step_node<T, D, QS, G_, AFF_><<<grid_, kBlock, 0, s>>>(                                  \
+    // TW: the R2 interpolant (2D), whose records carry the twist field
+#define FK_NODE_TW(G_, AFF_, TW_, grid_, nw_, wl_)                                             \
+    k_step_node<T, D, QS, G_, AFF_, TW_><<<grid_, kBlock, 0, s>>>(                             \
         P, n, nw_, P.inst, wl_, P.fw_nodes, P.trig, P.coords, (const T *)packed, (T *)u_out)
+#define FK_NODE(G_, AFF_, grid_, nw_, wl_)                                                     \
+    do {                                                                                       \
+        if constexpr (D == 2) {                                                                \
+            if (P.hermite2) { FK_NODE_TW(G_, AFF_, true, grid_, nw_, wl_); break; }            \
+        }                                                                                      \
+        FK_NODE_TW(G_, AFF_, false, grid_, nw_, wl_);                                          \
+    } while (0)
     if (P.n_fw_work > 0) {
         if (P.step_kind == 2) {
             if (P.all_affine) FK_NODE(GS, true, P.fw_split_grid, P.n_fw_split_work, P.fw_split_work);
@@ -50,6 +58,7 @@ void step_node_launch(const PlanDev &P, int n, const void *packed, void *u_out, 
         }
     }
 #undef FK_NODE
+#undef FK_NODE_TW
     if constexpr (D >= 2) {
         // separable nodes, one launch per footprint class
 #define FK_BOX(c_, L_)                                                                         \

@@ -23,6 +23,7 @@ COEF = {"const": 0, "cellular2d": 1, "abc3d": 2, "rolls2d": 3}
 REGION = {"box": 0, "ball": 1}
 PREC = {"f64": 0, "f32": 1}
 FORM = {"fused": 0, "ell": 1}
+HERMITE = {"r1": 0, "r2": 1}
 STEP_KERNEL = {"auto": 0, "node": 1, "group": 2, "split": 3, "box": 4}
 MAX_THETA = 8
 
@@ -57,7 +58,7 @@ class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("form", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("ckpt_every", ctypes.c_int), ("block", ctypes.c_int),
                 ("step_kernel", ctypes.c_int), ("columns", ctypes.c_int),
-                ("reserved", ctypes.c_int)]
+                ("hermite", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -193,13 +194,15 @@ class Plan:
     size, node counts); calls need a workspace.  force_f64: per-instance
     flags (an FP32 plan computes the flagged instances in FP64; see
     precision_probe).  columns: columns per launch of the assembled
-    product in forward_horizons (1..4).
+    product in forward_horizons (1..4).  hermite: "r1" (values and first
+    derivatives) or "r2" (also the mixed derivatives; d <= 2, fused form,
+    forward calls).
     """
 
     def __init__(self, problems, precision: str = "f64", form: str = "fused",
                  use_graph: bool = False, ckpt_every: int = 0, device: str = "cuda",
                  step_kernel: str = "auto", allocate: bool = True, force_f64=None,
-                 columns: int = 1):
+                 columns: int = 1, hermite: str = "r1"):
         import torch
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
@@ -219,6 +222,7 @@ class Plan:
         opt.ckpt_every = int(ckpt_every)
         opt.step_kernel = STEP_KERNEL[step_kernel]
         opt.columns = int(columns)
+        opt.hermite = HERMITE[hermite]
         h = ctypes.c_void_p()
         _check(lib.fk_plan_create(arr, len(self.problems), ctypes.byref(opt), ctypes.byref(h)))
         del keep
