@@ -28,7 +28,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fkoracle.c")
 _LIB = os.path.join(_HERE, "libfkoracle.so")
 
-COEF = {"const": 0, "cellular2d": 1, "abc3d": 2, "rolls2d": 3}
+COEF = {"const": 0, "cellular2d": 1, "abc3d": 2, "rolls2d": 3, "runaway3d": 4}
+FACE = {"exit1": 0, "exit0": 1, "reflect": 2}
 REGION = {"box": 0, "ball": 1}
 
 
@@ -49,7 +50,7 @@ class _Problem(ctypes.Structure):
         ("x", ctypes.POINTER(ctypes.c_double) * 3),
         ("periodic", ctypes.c_int * 3),
         ("coef_kind", ctypes.c_int),
-        ("p", ctypes.c_double * 8),
+        ("p", ctypes.c_double * 16),
         ("D", ctypes.c_double),
         ("region_kind", ctypes.c_int),
         ("c", ctypes.c_double * 3),
@@ -61,6 +62,7 @@ class _Problem(ctypes.Structure):
         ("n_steps", ctypes.c_int),
         ("t0", ctypes.c_double),
         ("hermite", ctypes.c_int),
+        ("face", (ctypes.c_int * 2) * 3),
     ]
 
 
@@ -84,6 +86,9 @@ def _load():
             "fko_node_class": (ctypes.c_int, [P, ctypes.c_long]),
             "fko_active_nodes": (ctypes.c_long, [P, lp]),
             "fko_drift": (None, [P, ctypes.c_double, dp, dp]),
+            "fko_sigma": (None, [P, ctypes.c_double, dp, dp]),
+            "fko_re_coeffs": (None, [P, ctypes.c_double, ctypes.c_double, dp]),
+            "fko_exit_value": (ctypes.c_int, [P, dp]),
             "fko_num_theta": (ctypes.c_int, [P]),
             "fko_landing": (None, [P, ctypes.c_int, ctypes.c_long, ctypes.c_int, dp]),
             "fko_cell": (ctypes.c_int, [dp, ctypes.c_int, ctypes.c_double]),
@@ -144,7 +149,7 @@ class OracleProblem:
             s.x[i] = _dp(self.nodes[i]) if i < prob.d else None
         s.coef_kind = COEF[prob.coef_kind]
         cf = list(prob.coef if coef is None else coef)
-        for i in range(8):
+        for i in range(16):
             s.p[i] = float(cf[i]) if i < len(cf) else 0.0
         s.D = float(prob.D if D is None else D)
         s.region_kind = REGION[prob.region_kind]
@@ -158,6 +163,10 @@ class OracleProblem:
         s.n_steps = int(prob.n_steps)
         s.t0 = float(prob.t0)
         s.hermite = 2 if getattr(prob, "hermite", "r1") == "r2" else 1
+        faces = getattr(prob, "faces", None)
+        for a in range(3):
+            for side in range(2):
+                s.face[a][side] = FACE[faces[a][side]] if faces and a < len(faces) else 0
         self.s = s
         self.Q = q ** prob.d
         self.J = int(np.prod(prob.shape))
@@ -202,6 +211,33 @@ def drift(prob, t: float, x: Sequence[float]) -> np.ndarray:
     b = np.zeros(3)
     _load().fko_drift(op.ptr, float(t), _dp(xx), _dp(b))
     return b[: op.prob.d]
+
+
+def sigma(prob, t: float, x: Sequence[float]) -> np.ndarray:
+    """Diffusion coefficient of each axis (the SDE's dW factor) at (t, x)."""
+    op = _op(prob)
+    xx = np.zeros(3)
+    xx[: len(x)] = x
+    sg = np.zeros(3)
+    _load().fko_sigma(op.ptr, float(t), _dp(xx), _dp(sg))
+    return sg[: op.prob.d]
+
+
+def re_coeffs(prob, t: float, p: float) -> np.ndarray:
+    """Runaway-electron collision functions (C_A, C_B, C_F, dC_A/dp) at
+    momentum p and time t."""
+    op = _op(prob)
+    out = np.zeros(4)
+    _load().fko_re_coeffs(op.ptr, float(t), float(p), _dp(out))
+    return out
+
+
+def exit_value(prob, z) -> int:
+    """-1 if z does not exit, else the value it takes (1 or 0)."""
+    op = _op(prob)
+    zz = np.zeros(3)
+    zz[: len(z)] = z
+    return int(_load().fko_exit_value(op.ptr, _dp(zz)))
 
 
 def cell(nodes: np.ndarray, z: float) -> int:

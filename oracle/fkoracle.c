@@ -35,6 +35,10 @@
 #define FKO_COEF_CELLULAR2D 1
 #define FKO_COEF_ABC3D 2
 #define FKO_COEF_ROLLS2D 3
+#define FKO_COEF_RUNAWAY3D 4
+#define FKO_FACE_EXIT1 0        /* a point on or beyond the face exits, value 1 */
+#define FKO_FACE_EXIT0 1        /* it exits with value 0 */
+#define FKO_FACE_REFLECT 2      /* it is reflected back into the domain */
 #define FKO_REGION_BOX 0
 #define FKO_REGION_BALL 1
 
@@ -44,7 +48,7 @@ typedef struct {
     const double *x[3];     /* node coordinates per axis, increasing */
     int periodic[3];        /* node n-1 is the image of node 0 */
     int coef_kind;          /* FKO_COEF_* */
-    double p[8];            /* drift parameters */
+    double p[16];           /* drift (and, for the runaway model, diffusion) parameters */
     double D;               /* diffusion: sigma = sqrt(2 D) I */
     int region_kind;        /* FKO_REGION_* */
     double c[3];            /* ball centre */
@@ -57,6 +61,7 @@ typedef struct {
     double t0;              /* step n evaluates coefficients at t0 + n dt */
     int hermite;            /* 1: values and first derivatives (R1); 2: with the
                                mixed derivatives (twist fields, R2) */
+    int face[3][2];         /* per non-periodic axis, low and high face: FKO_FACE_* */
 } fko_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -85,14 +90,20 @@ static long node_linear(const fko_problem *P, const int *i)
     return j;
 }
 
-/* Exit region test for a point (the paper's domain D is an open box,
- * Section 2; points on or beyond a non-periodic face have exited.  For a ball
- * target the exit region also holds every point with |z - c| >= r). */
-int fko_is_exit_point(const fko_problem *P, const double *z)
+/* Exit test for a point (the paper's domain D is an open box, Section 2;
+ * points on or beyond a non-periodic face have exited.  For a ball target the
+ * exit region also holds every point with |z - c| >= r).  Returns -1 if z
+ * does not exit, else the value it takes: 1 through an FKO_FACE_EXIT1 face or
+ * the ball, 0 through an FKO_FACE_EXIT0 face (the face of the lowest axis
+ * decides, low face before high face); reflecting faces never exit. */
+int fko_exit_value(const fko_problem *P, const double *z)
 {
     for (int a = 0; a < P->d; a++) {
         if (P->periodic[a]) continue;
-        if (z[a] <= P->x[a][0] || z[a] >= P->x[a][P->n[a] - 1]) return 1;
+        if (P->face[a][0] != FKO_FACE_REFLECT && z[a] <= P->x[a][0])
+            return P->face[a][0] == FKO_FACE_EXIT0 ? 0 : 1;
+        if (P->face[a][1] != FKO_FACE_REFLECT && z[a] >= P->x[a][P->n[a] - 1])
+            return P->face[a][1] == FKO_FACE_EXIT0 ? 0 : 1;
     }
     if (P->region_kind == FKO_REGION_BALL) {
         double s = 0.0;
@@ -102,7 +113,12 @@ int fko_is_exit_point(const fko_problem *P, const double *z)
         }
         if (s >= P->r * P->r) return 1;
     }
-    return 0;
+    return -1;
+}
+
+int fko_is_exit_point(const fko_problem *P, const double *z)
+{
+    return fko_exit_value(P, z) >= 0;
 }
 
 /* 0 = active node, 1 = exit node (u = 1 for all n, terminal value chi = 1),
@@ -141,7 +157,93 @@ long fko_active_nodes(const fko_problem *P, long *out)
 
 /* ------------------------------------------------------------------------ */
 /* Coefficients b(t, x), sigma (paper Eq. (e1)); sigma = sqrt(2 D) I         */
+/* except for the runaway-electron model of Section 4.3                      */
 /* ------------------------------------------------------------------------ */
+
+/* Runaway-electron model (Section 4.3, Eq. (ex32d)): state (p, xi, r),
+ * parameters p[] = (E, tau, Z, delta, nu_ee, v_T, r_D, W, Delta_p, V_0, D_0,
+ * t_*, That_0, That_f, Ttilde, m c^2).  With t_* > 0 the electric field and
+ * the collision parameters follow the thermal-quench model of Section 4.3:
+ * That(t) = That_f + (That_0 - That_f) exp(-t / t_*), v_T = sqrt(That /
+ * Ttilde), nu_ee = (Ttilde / That)^(3/2) lnLambda(That) / lnLambda(Ttilde),
+ * lnLambda(T) = 14.9 - ln(0.28) / 2 + ln T, delta = sqrt(2 That / m c^2),
+ * E = E_0 (That_0 / That)^(3/2) (p[0] is then E_0). */
+typedef struct { double E, nu, vT, delta; } re_params;
+
+static re_params re_at(const fko_problem *P, double t)
+{
+    const double *p = P->p;
+    re_params q;
+    if (p[11] > 0.0) {
+        double Th = p[13] + (p[12] - p[13]) * exp(-t / p[11]);
+        double lnh = 14.9 - 0.5 * log(0.28) + log(Th);
+        double lnt = 14.9 - 0.5 * log(0.28) + log(p[14]);
+        q.vT = sqrt(Th / p[14]);
+        q.nu = pow(p[14] / Th, 1.5) * lnh / lnt;
+        q.delta = sqrt(2.0 * Th / p[15]);
+        q.E = p[0] * pow(p[12] / Th, 1.5);
+    } else {
+        q.E = p[0]; q.delta = p[3]; q.nu = p[4]; q.vT = p[5];
+    }
+    return q;
+}
+
+/* Collision functions at momentum pm (Section 4.3): phi(y) = erf(y),
+ * psi(y) = (phi - y phi') / (2 y^2), y = p / gamma, gamma = sqrt(1 +
+ * (delta p)^2); C_A = nu v_T^2 psi / y, C_B = nu v_T^2 (Z + phi - psi +
+ * y^2 delta^4 / 2) / (2 y), C_F = 2 nu v_T psi, and dC_A/dp (psi' =
+ * phi' - 2 psi / y, dy/dp = gamma^-3).  out = (C_A, C_B, C_F, dC_A/dp). */
+static void re_collisions(const fko_problem *P, const re_params *q, double pm, double *out)
+{
+    double Z = P->p[2];
+    double gam = sqrt(1.0 + (q->delta * pm) * (q->delta * pm));
+    double y = pm / gam;
+    double phi = erf(y);
+    double dphi = 2.0 / sqrt(M_PI) * exp(-y * y);
+    double psi = (phi - y * dphi) / (2.0 * y * y);
+    double dpsi = dphi - 2.0 * psi / y;
+    double k2 = q->nu * q->vT * q->vT;
+    out[0] = k2 * psi / y;
+    out[1] = 0.5 * k2 / y * (Z + phi - psi + 0.5 * y * y * pow(q->delta, 4));
+    out[2] = 2.0 * q->nu * q->vT * psi;
+    out[3] = k2 * (dpsi * y - psi) / (y * y) / (gam * gam * gam);
+}
+
+void fko_re_coeffs(const fko_problem *P, double t, double pm, double *out)
+{
+    re_params q = re_at(P, t);
+    re_collisions(P, &q, pm, out);
+}
+
+/* Radial diffusivity D(r, p) = D_0 / 2 (1 + tanh((r - r_D) / W)) exp(-(p /
+ * Delta_p)^2) and its r-derivative. */
+static void re_radial(const fko_problem *P, double pm, double r, double *D, double *dD)
+{
+    const double *p = P->p;
+    double th = tanh((r - p[6]) / p[7]);
+    double e = exp(-(pm / p[8]) * (pm / p[8]));
+    *D = 0.5 * p[10] * (1.0 + th) * e;
+    *dD = 0.5 * p[10] * (1.0 - th * th) / p[7] * e;
+}
+
+/* Diffusion coefficient of each axis at (t, x): sigma_a (the SDE's dW
+ * factor; sigma = sqrt(2 D) for the other models). */
+void fko_sigma(const fko_problem *P, double t, const double *x, double *sig)
+{
+    if (P->coef_kind == FKO_COEF_RUNAWAY3D) {
+        re_params q = re_at(P, t);
+        double c[4], D, dD;
+        re_collisions(P, &q, x[0], c);
+        re_radial(P, x[0], x[2], &D, &dD);
+        double om = 1.0 - x[1] * x[1];
+        sig[0] = sqrt(2.0 * c[0]);
+        sig[1] = sqrt(2.0 * c[1]) / x[0] * sqrt(om > 0.0 ? om : 0.0);
+        sig[2] = sqrt(2.0 * D);
+        return;
+    }
+    double s = sqrt(2.0 * P->D);
+    for (int a = 0; a < P->d; a++) sig[a] = s;
+}
 
 void fko_drift(const fko_problem *P, double t, const double *x, double *b)
 {
@@ -158,6 +260,20 @@ void fko_drift(const fko_problem *P, double t, const double *x, double *b)
         double Api = p[0] * M_PI;
         b[0] = -(Api * sa * cy);
         b[1] = Api * ca * sy;
+    } else if (P->coef_kind == FKO_COEF_RUNAWAY3D) {
+        /* Eq. (ex32d): the p drift includes (1/p^2) d/dp (p^2 C_A) =
+         * 2 C_A / p + dC_A/dp; the r drift V(r) + dD/dr with
+         * V = V_0 [r > r_D] */
+        re_params q = re_at(P, t);
+        double c[4], D, dD;
+        double pm = x[0], xi = x[1], r = x[2];
+        double gam = sqrt(1.0 + (q.delta * pm) * (q.delta * pm));
+        double om = 1.0 - xi * xi;
+        re_collisions(P, &q, pm, c);
+        re_radial(P, pm, r, &D, &dD);
+        b[0] = q.E * xi - gam * pm / p[1] * om - c[2] + 2.0 * c[0] / pm + c[3];
+        b[1] = q.E * om / pm - xi * om / (p[1] * gam) - 2.0 * xi * c[1] / (pm * pm);
+        b[2] = (r > p[6] ? p[9] : 0.0) + dD;
     } else if (P->coef_kind == FKO_COEF_ROLLS2D) {
         /* Section 4.2: Pe v with v_1 = -pi cos(pi x_2) [sin(n x_1) + eps f(t) cos(n x_1)],
          * v_2 = n sin(pi x_2) [cos(n x_1) - eps f(t) sin(n x_1)], f(t) = cos(omega t);
@@ -183,6 +299,7 @@ int fko_num_theta(const fko_problem *P)
     if (P->coef_kind == FKO_COEF_CONST) return P->d + 1;
     if (P->coef_kind == FKO_COEF_CELLULAR2D) return 4;
     if (P->coef_kind == FKO_COEF_ROLLS2D) return 4;   /* (Pe, eps, omega, D); n is a count */
+    if (P->coef_kind == FKO_COEF_RUNAWAY3D) return 1; /* no adjoint for this model */
     return 5;
 }
 
@@ -277,22 +394,28 @@ static double tensor_weight(const fko_problem *P, const int *qi)
 void fko_landing(const fko_problem *P, int n, long j, int q, double *z)
 {
     int i[3], qi[3];
-    double x[3], b[3];
+    double x[3], b[3], sig[3];
     double t = P->t0 + (double)n * P->dt;
     double sq = sqrt(2.0 * P->dt);
-    double S = sqrt(2.0 * P->D) * sq;
     node_index(P, j, i);
     for (int a = 0; a < P->d; a++) x[a] = P->x[a][i[a]];
     fko_drift(P, t, x, b);
+    fko_sigma(P, t, x, sig);
     split_q(P, q, qi);
     for (int a = 0; a < P->d; a++) {
+        double S = sig[a] * sq;
         double c = x[a] + b[a] * P->dt;
         z[a] = c + S * P->gh_a[qi[a]];
+        const double *xa = P->x[a];
+        double lo = xa[0], hi = xa[P->n[a] - 1];
         if (P->periodic[a]) {
-            const double *xa = P->x[a];
-            double L = xa[P->n[a] - 1] - xa[0];
-            if (z[a] >= xa[P->n[a] - 1]) z[a] = z[a] - L;
-            else if (z[a] < xa[0]) z[a] = z[a] + L;
+            double L = hi - lo;
+            if (z[a] >= hi) z[a] = z[a] - L;
+            else if (z[a] < lo) z[a] = z[a] + L;
+        } else {
+            /* a reflecting face mirrors the point back into the domain */
+            if (P->face[a][0] == FKO_FACE_REFLECT && z[a] < lo) z[a] = lo + (lo - z[a]);
+            if (P->face[a][1] == FKO_FACE_REFLECT && z[a] > hi) z[a] = hi - (z[a] - hi);
         }
     }
 }
@@ -556,7 +679,14 @@ static void step_impl(const fko_problem *P, int n, const long *active, long Ja,
     for (int a = 0; a < P->d; a++) Q *= P->gh_n;
     for (long j = 0; j < J; j++) {
         int cls = fko_node_class(P, j);
-        if (cls == 1) u_out[j] = 1.0;
+        if (cls == 1) {
+            /* exit nodes keep their exit value (1, or 0 on an FKO_FACE_EXIT0 face) */
+            int i[3];
+            double x[3];
+            node_index(P, j, i);
+            for (int a = 0; a < P->d; a++) x[a] = P->x[a][i[a]];
+            u_out[j] = (double)fko_exit_value(P, x);
+        }
     }
 #pragma omp parallel for schedule(dynamic, 64)
     for (long r = 0; r < Ja; r++) {
@@ -569,11 +699,12 @@ static void step_impl(const fko_problem *P, int n, const long *active, long Ja,
             double w = tensor_weight(P, qi);
             fko_landing(P, n, j, q, z);
             int ex;
+            int ev = fko_exit_value(P, z);
             if (exit_use) {
                 long bi = exit_bit_index(P, Ja, n, r, q);
                 ex = (exit_use[bi >> 3] >> (bi & 7)) & 1;
             } else {
-                ex = fko_is_exit_point(P, z);
+                ex = ev >= 0;
             }
             if (exit_rec && ex) {
                 long bi = exit_bit_index(P, Ja, n, r, q);
@@ -586,7 +717,7 @@ static void step_impl(const fko_problem *P, int n, const long *active, long Ja,
                         ex ? -1 : fko_cell(P->x[a], P->n[a], z[a]);
                 exitf[r * Q + q] = (unsigned char)ex;
             }
-            double v = ex ? 1.0 : interp(P, u_next, g_next, z, NULL);
+            double v = ex ? (ev == 0 ? 0.0 : 1.0) : interp(P, u_next, g_next, z, NULL);
             sum += w * v;
         }
         u_out[j] = sum;
@@ -635,7 +766,15 @@ void fko_chi(const fko_problem *P, double *u)
     long J = fko_num_nodes(P);
     for (long j = 0; j < J; j++) {
         long rj = representative(P, j);
-        u[j] = (fko_node_class(P, rj) == 1) ? 1.0 : 0.0;
+        if (fko_node_class(P, rj) != 1) {
+            u[j] = 0.0;
+        } else {
+            int i[3];
+            double x[3];
+            node_index(P, rj, i);
+            for (int a = 0; a < P->d; a++) x[a] = P->x[a][i[a]];
+            u[j] = (double)fko_exit_value(P, x);
+        }
     }
 }
 
@@ -733,7 +872,11 @@ int fko_assemble_row(const fko_problem *P, int n, long j, double *row, double *e
         split_q(P, q, qi);
         double w = tensor_weight(P, qi);
         fko_landing(P, n, j, q, z);
-        if (fko_is_exit_point(P, z)) { *exit_mass += w; continue; }
+        int ev = fko_exit_value(P, z);
+        if (ev >= 0) {
+            if (ev == 1) *exit_mass += w;   /* value-0 exits carry nothing */
+            continue;
+        }
         locate(P, z, k, s, h);
         for (int c = 0; c < (1 << P->d); c++) {
             for (int a = 0; a < P->d; a++) {
@@ -819,6 +962,9 @@ static void slopes_transpose(const fko_problem *P, const double *u, const double
 int fko_adjoint_states(const fko_problem *P, const double *U, const double *lam0,
                        double *grad, double *lamN, const unsigned char *exit_use)
 {
+    if (P->coef_kind == FKO_COEF_RUNAWAY3D) return -3;   /* state-dependent sigma: not linearised */
+    for (int a = 0; a < P->d; a++)
+        if (P->face[a][0] != FKO_FACE_EXIT1 || P->face[a][1] != FKO_FACE_EXIT1) return -3;
     if (P->hermite == 2) return -3;   /* the adjoint linearises the R1 interpolant */
     long J = fko_num_nodes(P);
     int N = P->n_steps;

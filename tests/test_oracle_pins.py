@@ -1070,3 +1070,180 @@ def test_r2_twist_field_is_pchip_composed_x_then_y():
     sl = (slice(2, -2), slice(2, -2))    # stencils of stencils stay interior
     np.testing.assert_allclose(g[2][sl], gxy[sl], atol=1e-12)
     assert np.abs(gxy - gyx)[sl].max() > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# Boundary faces: exit with value 1, exit with value 0, reflecting (the
+# runaway-electron model of Section 4.3 leaves through p_max with value 1,
+# through p_min and the wall r = 1 with value 0, and reflects at xi = +-1 and
+# on the axis r = 0)
+# ---------------------------------------------------------------------------
+
+
+def _bm_faces(faces, n=201, D=0.1, dt=1e-4, T=0.4, gh_q=8):
+    return W.Problem(axes=[W.uniform_axis(0.0, 1.0, n)], coef_kind="const", coef=(0.0,), D=D,
+                     region_kind="box", gh_q=gh_q, dt=dt, n_steps=int(round(T / dt)),
+                     faces=(faces,))
+
+
+def _series_exit0_exit1(x, D, T, K=200):
+    k = np.arange(1, K + 1)[:, None]
+    return x + np.sum(2 * (-1.0) ** k / (k * np.pi) * np.sin(k * np.pi * x) *
+                      np.exp(-D * (k * np.pi) ** 2 * T), axis=0)
+
+
+def _series_reflect_exit1(x, D, T, K=200):
+    k = np.arange(0, K)[:, None]
+    lam = (k + 0.5) * np.pi
+    return 1 - np.sum(2 * (-1.0) ** k / lam * np.cos(lam * x) * np.exp(-D * lam ** 2 * T), axis=0)
+
+
+@pytest.mark.parametrize("faces", [("exit0", "exit1"), ("reflect", "exit1")])
+def test_faces_brownian_exit_through_one_face_vs_series(faces):
+    """Brownian motion on (0, 1) with D = 0.1 up to T = 0.4: the probability of
+    leaving through x = 1 when x = 0 counts 0 (Dirichlet 0) or reflects
+    (Neumann), against the closed-form sine / cosine series of the heat
+    equation; the discrete monitoring of the chain biases the result by
+    about 0.58 sigma sqrt(dt) near the faces (0.003 here)."""
+    prob = _bm_faces(faces)
+    u0 = oracle.solve(prob, snaps=[0])[0]
+    x = prob.axes[0].nodes
+    ref = (_series_exit0_exit1 if faces[0] == "exit0" else _series_reflect_exit1)(x, 0.1, 0.4)
+    err = np.abs(u0 - ref)
+    print(faces, "max err", err.max())
+    assert err.max() <= 6e-3
+    assert u0[-1] == 1.0
+    if faces[0] == "exit0":
+        assert u0[0] == 0.0
+    else:
+        assert oracle.node_class(prob)[0] == 0   # the reflecting face is an active node
+
+
+def test_reflecting_face_translates_linear_data_exactly():
+    """sigma = 0, drift toward a reflecting face: a landing point beyond it is
+    mirrored, so one step maps linear data u = a + b x to a + b z with
+    z = lo + (lo - (x + b_drift dt)) near the face."""
+    axes = [W.uniform_axis(0.0, 1.0, 41)]
+    prob = W.Problem(axes=axes, coef_kind="const", coef=(-2.0,), D=0.0, region_kind="box",
+                     gh_q=1, dt=0.01, n_steps=1, faces=(("reflect", "exit1"),))
+    x = axes[0].nodes
+    u = 0.3 + 0.5 * x
+    got = oracle.step(prob, 0, u)
+    z = x - 0.02
+    z = np.where(z < 0.0, 0.0 + (0.0 - z), z)
+    want = 0.3 + 0.5 * z
+    assert np.abs(got[:-1] - want[:-1]).max() <= 1e-14
+    assert got[-1] == 1.0
+
+
+def _re(**kw):
+    kw.setdefault("n_p", 13)
+    kw.setdefault("n_xi", 9)
+    kw.setdefault("r_axis", W.remark2_axis(0.0, 0.7, 1.0, 0.1, 0.05))
+    return W.runaway3d(**kw)
+
+
+def test_runaway_collision_functions_from_their_definitions():
+    """Section 4.3: psi(y) = (phi - y phi') / (2 y^2) with phi(y) =
+    2/sqrt(pi) int_0^y exp(-s^2) ds, evaluated here by quadrature (scipy),
+    gives C_A, C_B, C_F; the small- and large-y limits psi ~ 2y/(3 sqrt(pi))
+    and psi ~ 1/(2 y^2) hold; dC_A/dp equals central differences of C_A."""
+    from scipy.integrate import quad
+    prob = _re()
+    delta, Z = 0.042, 1.0
+    for pm in (2.0, 5.5, 13.0, 31.0, 50.0):
+        gam = math.sqrt(1 + (delta * pm) ** 2)
+        y = pm / gam
+        phi = 2 / math.sqrt(math.pi) * quad(lambda s: math.exp(-s * s), 0, y)[0]
+        dphi = 2 / math.sqrt(math.pi) * math.exp(-y * y)
+        psi = (phi - y * dphi) / (2 * y * y)
+        CA, CB, CF, dCA = oracle.re_coeffs(prob, 0.0, pm)
+        np.testing.assert_allclose([CA, CB, CF],
+                                   [psi / y, 0.5 / y * (Z + phi - psi + 0.5 * y * y * delta ** 4),
+                                    2 * psi], rtol=1e-10)
+        h = 1e-5 * pm
+        fd = (oracle.re_coeffs(prob, 0.0, pm + h)[0] - oracle.re_coeffs(prob, 0.0, pm - h)[0]) / (2 * h)
+        assert abs(dCA - fd) <= 1e-7 * abs(fd) + 1e-12
+    # limits of psi through C_A = psi / y (nu = v_T = 1)
+    tiny = W.runaway3d(delta=0.0, p_min=1e-3, n_p=4, n_xi=4, r_axis=W.uniform_axis(0, 1, 4))
+    y = 1e-3
+    assert abs(oracle.re_coeffs(tiny, 0.0, y)[0] * y / (2 * y / (3 * math.sqrt(math.pi))) - 1) < 1e-5
+    y = 30.0
+    assert abs(oracle.re_coeffs(tiny, 0.0, y)[0] * y / (1 / (2 * y * y)) - 1) < 1e-12
+
+
+def test_runaway_drift_and_diffusion_follow_eq_ex32d():
+    """The p drift holds (1/p^2) d(p^2 C_A)/dp (checked by central differences
+    of p^2 C_A), the xi drift and the diffusion coefficients follow
+    Eq. (ex32d), the r drift is V(r) + dD/dr (central differences of D)."""
+    prob = _re()
+    E, tau, delta = 0.3, 1e5, 0.042
+    rng = np.random.default_rng(41)
+    for _ in range(12):
+        pm, xi, r = rng.uniform(2.5, 49), rng.uniform(-0.99, 0.99), rng.uniform(0.01, 0.99)
+        CA, CB, CF, _ = oracle.re_coeffs(prob, 0.0, pm)
+        gam = math.sqrt(1 + (delta * pm) ** 2)
+        h = 1e-5 * pm
+        dp2CA = ((pm + h) ** 2 * oracle.re_coeffs(prob, 0.0, pm + h)[0]
+                 - (pm - h) ** 2 * oracle.re_coeffs(prob, 0.0, pm - h)[0]) / (2 * h)
+        b = oracle.drift(prob, 0.0, [pm, xi, r])
+        bp = E * xi - gam * pm / tau * (1 - xi * xi) - CF + dp2CA / (pm * pm)
+        bxi = E * (1 - xi * xi) / pm - xi * (1 - xi * xi) / (tau * gam) - 2 * xi * CB / (pm * pm)
+        Dr = lambda rr: 0.5e-4 * (1 + math.tanh((rr - 0.7) / 1e-2)) * math.exp(-(pm / 20) ** 2)  # noqa: E731
+        hr = 1e-7
+        br = (0.003 if r > 0.7 else 0.0) + (Dr(r + hr) - Dr(r - hr)) / (2 * hr)
+        np.testing.assert_allclose(b, [bp, bxi, br], rtol=1e-6, atol=1e-12)
+        sg = oracle.sigma(prob, 0.0, [pm, xi, r])
+        np.testing.assert_allclose(sg, [math.sqrt(2 * CA), math.sqrt(2 * CB) / pm * math.sqrt(1 - xi * xi),
+                                        math.sqrt(2 * Dr(r))], rtol=1e-12)
+
+
+def test_runaway_probability_faces_and_monotone_in_field():
+    """On the runaway model: nodes on p = p_max hold 1, on p_min and the
+    wall r = 1 hold 0 (exit faces), xi = +-1 and r = 0 are active (reflecting);
+    0 <= P_RE <= 1 up to the interpolant's overshoot; without electric field
+    hardly anything runs away, and P_RE grows with E (its mean, and at nearly
+    every node where the electron moves along the field)."""
+    base = _re(dt=1.0, T=20.0)
+    cls = oracle.node_class(base)
+    assert np.all(cls[-1] == 1) and np.all(cls[0] == 1) and np.all(cls[:, :, -1] == 1)
+    assert np.all(cls[1:-1, :, :-1] == 0)
+    u = {E: oracle.solve(_re(dt=1.0, T=20.0, E=E), snaps=[0])[0] for E in (0.0, 0.15, 0.3)}
+    for v in u.values():
+        # the corner of p_max and the wall belongs to p_max (the lowest axis decides)
+        assert np.all(v[-1] == 1.0) and np.all(v[0] == 0.0) and np.all(v[:-1, :, -1] == 0.0)
+        assert v.min() >= -1e-3 and v.max() <= 1 + 1e-3
+    inner = (slice(1, -1), slice(None), slice(0, -1))
+    assert u[0.0][inner].mean() < 0.1 * u[0.3][inner].mean()
+    assert u[0.0][inner].mean() < u[0.15][inner].mean() < u[0.3][inner].mean()
+    # the field accelerates electrons moving along it (dp = E xi dt): where
+    # xi >= 1/2 the runaway probability grows with E at nearly every node
+    # (pointwise order is not a theorem of the discrete scheme: the PCHIP
+    # interpolant does not preserve order in the data); where xi < 0 the
+    # field decelerates and no order is expected
+    xi = base.axes[1].nodes
+    fwd = (slice(1, -1), xi >= 0.5, slice(0, -1))
+    for lo, hi in ((0.0, 0.15), (0.15, 0.3)):
+        assert np.mean(u[lo][fwd] <= u[hi][fwd] + 1e-9) >= 0.99, (lo, hi)
+
+
+def test_runaway_thermal_quench_parameters():
+    """t_* > 0: That(0) = That_0 gives v_T = 1 (That_0 = Ttilde), nu = 1 and
+    E = E_0 at t = 0; as the plasma cools, E grows like That^(-3/2)."""
+    tq = W.runaway3d(n_p=5, n_xi=5, r_axis=W.uniform_axis(0, 1, 5), t_star=10.0, E0=1e-3,
+                     That0=3.0, Thatf=0.005, Ttilde=3.0, tau=6000.0, r_D=0.0, W=1e-4,
+                     Delta_p=2.0, V0=0.0)
+    c0 = oracle.re_coeffs(tq, 0.0, 10.0)
+    ref = _re()
+    cr = oracle.re_coeffs(ref.replace(coef=(1e-3, 6000.0, 1.0, math.sqrt(6 / 511.0), 1.0, 1.0) +
+                                      ref.coef[6:]), 0.0, 10.0)
+    np.testing.assert_allclose(c0, cr, rtol=1e-12)
+    b0 = oracle.drift(tq, 0.0, [10.0, 1.0, 0.5])
+    b1 = oracle.drift(tq, 30.0, [10.0, 1.0, 0.5])
+    Th = 0.005 + (3.0 - 0.005) * math.exp(-3.0)
+    assert b1[1] < 0 and b0[0] != b1[0]
+    # at xi = 1 the p drift is E - C_F + (1/p^2) d(p^2 C_A)/dp: its E part scales
+    c1 = oracle.re_coeffs(tq, 30.0, 10.0)
+    e_part0 = b0[0] - (-c0[2] + 2 * c0[0] / 10.0 + c0[3])
+    e_part1 = b1[0] - (-c1[2] + 2 * c1[0] / 10.0 + c1[3])
+    np.testing.assert_allclose([e_part0, e_part1], [1e-3, 1e-3 * (3.0 / Th) ** 1.5], rtol=1e-9)

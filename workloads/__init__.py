@@ -91,6 +91,10 @@ class Problem:
     t0: float = 0.0
     name: str = ""
     hermite: str = "r1"   # "r1": values and first derivatives; "r2": also the mixed ones
+    # per axis (low face, high face) of the box: "exit1" (a point on or beyond
+    # it exits with value 1, the default), "exit0" (exits with value 0) or
+    # "reflect"; None: every face "exit1"
+    faces: Optional[Tuple[Tuple[str, str], ...]] = None
 
     @property
     def d(self) -> int:
@@ -204,6 +208,45 @@ def paper2d(n1: int = 129, n2: int = 33, Pe: float = 10.0, eps: float = 0.15,
                    coef_kind=COEF_ROLLS2D, coef=(Pe, eps, omega, float(n)), D=0.5,
                    region_kind=REGION_BOX, gh_q=gh_q, dt=dt,
                    n_steps=int(round(T / dt)), name="paper2d")
+
+
+COEF_RUNAWAY3D = "runaway3d"
+
+# Section 4.3, Eq. (parameters): the time-independent runaway-electron model
+RE_PARAMS = dict(E=0.3, tau=1e5, Z=1.0, delta=0.042, nu_ee=1.0, v_T=1.0, r_D=0.7, W=1e-2,
+                 Delta_p=20.0, V0=0.003, D0=1e-4)
+
+
+def remark2_axis(lo: float, mid: float, hi: float, h_coarse: float, h_fine: float) -> Axis:
+    """Piecewise-uniform axis: spacing h_coarse on [lo, mid], h_fine on
+    [mid, hi] (the non-uniform radial grid of Section 4.3)."""
+    a = np.linspace(lo, mid, int(round((mid - lo) / h_coarse)) + 1)
+    b = np.linspace(mid, hi, int(round((hi - mid) / h_fine)) + 1)
+    return Axis(np.concatenate([a, b[1:]]))
+
+
+def runaway3d(n_p: int = 49, n_xi: int = 41, r_axis: Optional[Axis] = None,
+              p_min: float = 2.0, p_max: float = 50.0, dt: float = 0.5, T: float = 120.0,
+              gh_q: int = 4, t_star: float = 0.0, name: str = "runaway3d", **params) -> Problem:
+    """The runaway-electron model of Section 4.3 (Eq. (ex32d)): state (p, xi,
+    r), xi = cos(theta); p in (p_min, p_max), xi in [-1, 1], r in [0, 1].
+    Runaway means leaving through p = p_max (value 1); leaving through p_min
+    (thermalised) or the wall r = 1 counts 0; xi = +-1 and the axis r = 0
+    reflect.  Default r grid: the paper's non-uniform one, spacing 0.1 on
+    [0, r_D] and 0.0025 on [r_D, 1].  The p and xi grids, dt and Q* are not
+    given in the paper (49 x 41 nodes, dt = 0.5, Q* = 4).  t_star > 0 gives
+    the thermal-quench model (then pass E0, That0, Thatf, Ttilde)."""
+    q = dict(RE_PARAMS)
+    q.update(params)
+    if r_axis is None:
+        r_axis = remark2_axis(0.0, q["r_D"], 1.0, 0.1, 0.0025)
+    coef = (q["E"] if t_star <= 0 else q.get("E0", 1e-3), q["tau"], q["Z"], q["delta"], q["nu_ee"],
+            q["v_T"], q["r_D"], q["W"], q["Delta_p"], q["V0"], q["D0"], t_star,
+            q.get("That0", 3.0), q.get("Thatf", 0.005), q.get("Ttilde", 3.0), q.get("mc2", 511.0))
+    return Problem(axes=[uniform_axis(p_min, p_max, n_p), uniform_axis(-1.0, 1.0, n_xi), r_axis],
+                   coef_kind=COEF_RUNAWAY3D, coef=coef, D=0.0, region_kind=REGION_BOX,
+                   gh_q=gh_q, dt=dt, n_steps=int(round(T / dt)), name=name,
+                   faces=(("exit0", "exit1"), ("reflect", "reflect"), ("reflect", "exit0")))
 
 
 def region_mean_weights(prob: "Problem") -> np.ndarray:
