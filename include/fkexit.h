@@ -69,8 +69,26 @@ typedef enum {
  *                      v_2 = n sin(pi y) (cos(n x) - e(t) sin(n x)), e(t) = eps cos(omega t)
  *                      (2n Rayleigh-Benard rolls on x in [-pi, pi], periodic, exit
  *                      through y = 0, 1 with a box region); coef = (Pe, eps, omega, n);
- *                      np = 3 (n, a count, is not differentiated) */
-enum { FK_COEF_CONST = 0, FK_COEF_CELLULAR2D = 1, FK_COEF_ABC3D = 2, FK_COEF_ROLLS2D = 3 };
+ *                      np = 3 (n, a count, is not differentiated)
+ *  FK_COEF_RUNAWAY3D   the runaway-electron model of Section 4.3, Eq. (ex32d): state
+ *                      (p, xi, r), drift and diagonal diffusion both depend on the node
+ *                      (sigma = (sqrt(2 C_A(p)), sqrt(2 C_B(p))/p sqrt(1 - xi^2),
+ *                      sqrt(2 D(r, p))); D of fk_problem is not used); coef = (E, tau, Z,
+ *                      delta, nu_ee, v_T, r_D, W, Delta_p, V_0, D_0, t_*, That_0, That_f,
+ *                      Ttilde, m c^2); t_* > 0: the thermal-quench model of Section 4.3
+ *                      (coef[0] is then E_0).  Forward calls only (no adjoint) */
+enum { FK_COEF_CONST = 0, FK_COEF_CELLULAR2D = 1, FK_COEF_ABC3D = 2, FK_COEF_ROLLS2D = 3,
+       FK_COEF_RUNAWAY3D = 4 };
+
+/* Face kinds of the box (fk_problem.face[a][side], side 0 the low face):
+ * FK_FACE_EXIT1 (default): a point on or beyond the face exits with value 1;
+ * FK_FACE_EXIT0: it exits with value 0 (absorbed without counting);
+ * FK_FACE_REFLECT: it is mirrored back into the domain, z -> lo + (lo - z).
+ * Exit nodes hold their face's value for every n; at a corner the lowest axis
+ * decides (low face before high face), then the ball.  Plans with a face other
+ * than FK_FACE_EXIT1 (and FK_COEF_RUNAWAY3D plans) run the lane-group step,
+ * the fused form and the forward calls only. */
+enum { FK_FACE_EXIT1 = 0, FK_FACE_EXIT0 = 1, FK_FACE_REFLECT = 2 };
 
 /* Exit region (paper Section 2: D is an open box; the benchmark spec's targets add
  * a ball).  FK_REGION_BOX: a point exits when a coordinate on a non-periodic
@@ -117,7 +135,7 @@ typedef struct {
     int d;                 /* 1..3 */
     fk_axis ax[FK_MAX_DIM];
     int coef_kind;         /* FK_COEF_* */
-    double coef[7];        /* drift parameters, see FK_COEF_* */
+    double coef[16];       /* drift parameters, see FK_COEF_* */
     double D;              /* diffusion coefficient, sigma = sqrt(2 D) I, D >= 0 */
     int region_kind;       /* FK_REGION_* */
     double center[FK_MAX_DIM];
@@ -131,6 +149,7 @@ typedef struct {
                               delivered and taken in FP32); ignored in FP64
                               plans.  fk_probe_precision picks the instances
                               whose FP32 result misses a tolerance. */
+    int face[FK_MAX_DIM][2];  /* FK_FACE_* per non-periodic axis, low and high face */
 } fk_problem;
 
 typedef struct {

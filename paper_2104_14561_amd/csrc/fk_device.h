@@ -130,6 +130,7 @@ struct AxisEval {
     double dz2;    // (z - centre)^2 for the ball test
     int k;         // cell
     bool ex;       // z left the box on this (non-periodic) axis
+    double exv;    // the value it takes then (1, or 0 through an exit-0 face)
 };
 
 __device__ inline AxisEval eval_axis(const DevInst &I, const double *coords, int a, double c,
@@ -187,6 +188,48 @@ __device__ inline AxisEval eval_axis_affine(const DevInst &I, int a, double c, d
     e.k = k;
     e.h = step;
     e.s = (z - xk) * I.inv_h[a];
+    return e;
+}
+
+// Axis evaluation with the node's own scale S (S = sigma_a sqrt(2 dt)) and
+// the instance's face kinds: a reflecting face mirrors z back into the
+// domain (z -> lo + (lo - z)); an exit face records the value it gives.
+__device__ inline AxisEval eval_axis_faces(const DevInst &I, const double *coords, int a,
+                                           double c, double ga, double S)
+{
+#pragma clang fp contract(off)
+    double z = c + S * ga;
+    const double lo = I.lo[a], hi = I.hi[a];
+    AxisEval e;
+    e.ex = false;
+    e.exv = 1.0;
+    if (I.periodic[a]) {
+        if (z >= hi) z = z - I.period[a];
+        else if (z < lo) z = z + I.period[a];
+    } else {
+        const int fl = I.face[a][0], fh = I.face[a][1];
+        if (fl == 2 && z < lo) z = lo + (lo - z);
+        if (fh == 2 && z > hi) z = hi - (z - hi);
+        if (fl != 2 && z <= lo) {
+            e.ex = true;
+            e.exv = fl == 1 ? 0.0 : 1.0;
+        } else if (fh != 2 && z >= hi) {
+            e.ex = true;
+            e.exv = fh == 1 ? 0.0 : 1.0;
+        }
+    }
+    const double t = z - I.center[a];
+    e.dz2 = t * t;
+    const int k = locate(I, coords, a, z);
+    const double xk = coord(I, coords, a, k);
+    if (I.affine[a]) {
+        e.h = I.step[a];
+        e.s = (z - xk) * I.inv_h[a];
+    } else {
+        e.h = coord(I, coords, a, k + 1) - xk;
+        e.s = (z - xk) / e.h;
+    }
+    e.k = k;
     return e;
 }
 
@@ -350,6 +393,66 @@ __device__ inline void node_centre(const DevInst &I, const double *coords, const
     double b[3];
     drift<D>(I, tf, trig, idx, b);
     for (int a = 0; a < D; ++a) c[a] = coord(I, coords, a, idx[a]) + b[a] * dt;
+}
+
+// Runaway-electron model (Section 4.3, Eq. (ex32d)) at node idx: the
+// landing-point centre c = x + b dt and the per-axis scales S_a = sigma_a
+// sqrt(2 dt), with the collision functions of phi = erf, psi = (phi - y phi')
+// / (2 y^2), y = p / gamma, and the radial tanh transition.  tf = (E, nu_ee,
+// v_T, delta) at t_n (tabulated on the host).  Operation order as written
+// (no contraction).
+__device__ inline void runaway_centre(const DevInst &I, const double *coords, const double *tf,
+                                      const int *idx, double dt, double *c, double *S)
+{
+#pragma clang fp contract(off)
+    const double *p = I.coef;
+    const double E = tf[0], nu = tf[1], vT = tf[2], delta = tf[3];
+    const double pm = coord(I, coords, 0, idx[0]);
+    const double xi = coord(I, coords, 1, idx[1]);
+    const double r = coord(I, coords, 2, idx[2]);
+    const double gam = sqrt(1.0 + (delta * pm) * (delta * pm));
+    const double om = 1.0 - xi * xi;
+    const double y = pm / gam;
+    const double phi = erf(y);
+    const double dphi = 2.0 / sqrt(M_PI) * exp(-y * y);
+    const double psi = (phi - y * dphi) / (2.0 * y * y);
+    const double dpsi = dphi - 2.0 * psi / y;
+    const double k2 = nu * vT * vT;
+    const double CA = k2 * psi / y;
+    const double CB = 0.5 * k2 / y * (p[2] + phi - psi + 0.5 * y * y * pow(delta, 4.0));
+    const double CF = 2.0 * nu * vT * psi;
+    const double dCA = k2 * (dpsi * y - psi) / (y * y) / (gam * gam * gam);
+    const double th = tanh((r - p[6]) / p[7]);
+    const double ep = exp(-(pm / p[8]) * (pm / p[8]));
+    const double Dr = 0.5 * p[10] * (1.0 + th) * ep;
+    const double dDr = 0.5 * p[10] * (1.0 - th * th) / p[7] * ep;
+    double b[3];
+    b[0] = E * xi - gam * pm / p[1] * om - CF + 2.0 * CA / pm + dCA;
+    b[1] = E * om / pm - xi * om / (p[1] * gam) - 2.0 * xi * CB / (pm * pm);
+    b[2] = (r > p[6] ? p[9] : 0.0) + dDr;
+    const double x[3] = {pm, xi, r};
+    for (int a = 0; a < 3; ++a) c[a] = x[a] + b[a] * dt;
+    const double sq = sqrt(2.0 * dt);
+    S[0] = sqrt(2.0 * CA) * sq;
+    S[1] = sqrt(2.0 * CB) / pm * sqrt(om > 0.0 ? om : 0.0) * sq;
+    S[2] = sqrt(2.0 * Dr) * sq;
+}
+
+// Centre and per-axis scales of any model (S_a = the instance's S unless the
+// diffusion depends on the node).
+template <int D>
+__device__ inline void node_centre_s(const DevInst &I, const double *coords, const double *tf,
+                                     const double2 *trig, const int *idx, double dt, double *c,
+                                     double *S)
+{
+    if constexpr (D == 3) {
+        if (I.sdiff) {
+            runaway_centre(I, coords, tf, idx, dt, c, S);
+            return;
+        }
+    }
+    node_centre<D>(I, coords, tf, trig, idx, dt, c);
+    for (int a = 0; a < D; ++a) S[a] = I.S;
 }
 
 // ---------------------------------------------------------------------------
@@ -569,7 +672,7 @@ __global__ void __launch_bounds__(kBlock) k_init_field(const unsigned char *cls,
 {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x)
-        u[i] = (T)(cls[i] & 1);
+        u[i] = (T)((cls[i] & 5) == 1 ? 1 : 0);   // bit 2: an exit node of value 0
 }
 
 // Stencil of the PCHIP slope along axis a at index i (Eq. (e300) and the end
@@ -705,7 +808,7 @@ __global__ void __launch_bounds__(kBlock) k_slopes(PlanDev P, int n, int first, 
 // (axis, 1D Gauss-Hermite index), so a node needs d Q* of these, not d Q.
 template <typename T> struct AxisRec {
     int k;        // cell
-    int ex;       // left the box on this axis
+    int ex;       // left the box on this axis: 0 no, 1 with value 1, 2 with value 0
     double dz2;   // (z - centre)^2
     T v0, v1, d0, d1;
 };
@@ -714,16 +817,19 @@ template <typename T> struct AxisRec {
 // index l % Q*.
 template <typename T, int D>
 __device__ inline void stage_axes(const DevInst &I, const double *coords, const double *gh_a,
-                                  int qs, const double *c, int lane, AxisRec<T> *tab)
+                                  int qs, const double *c, int lane, AxisRec<T> *tab,
+                                  const double *S, bool faces)
 {
     if (lane < D * qs) {
         const int a = lane / qs, qa = lane - a * qs;
         const double ca = (D == 1 || a == 0) ? c[0] : (a == 1 ? c[1] : c[2]);
-        const AxisEval e = eval_axis(I, coords, a, ca, gh_a[qa]);
+        const double Sa = (D == 1 || a == 0) ? S[0] : (a == 1 ? S[1] : S[2]);
+        const AxisEval e = faces ? eval_axis_faces(I, coords, a, ca, gh_a[qa], Sa)
+                                 : eval_axis(I, coords, a, ca, gh_a[qa]);
         const Basis<T> B = hermite<T>(e.s, e.h);
         AxisRec<T> r;
         r.k = e.k;
-        r.ex = e.ex ? 1 : 0;
+        r.ex = e.ex ? (e.exv == 0.0 ? 2 : 1) : 0;
         r.dz2 = e.dz2;
         r.v0 = B.v0; r.v1 = B.v1; r.d0 = B.d0; r.d1 = B.d1;
         tab[lane] = r;
@@ -780,9 +886,9 @@ __global__ void __launch_bounds__(kBlock) k_step_fused(
             node = active[I.act_off + it.first + slot];
             split_node<D>(I, node, idx);
             uref = rec[I.node_off + node].x;
-            double c[3];
-            node_centre<D>(I, coords, time_factors(P, n, it.inst), trig, idx, P.dt, c);
-            stage_axes<T, D>(I, coords, P.gh_a, qs, c, lane, tab);
+            double c[3], S[3];
+            node_centre_s<D>(I, coords, time_factors(P, n, it.inst), trig, idx, P.dt, c, S);
+            stage_axes<T, D>(I, coords, P.gh_a, qs, c, lane, tab, S, P.faces != 0);
         }
         __syncthreads();
         if (valid) {
@@ -792,16 +898,18 @@ __global__ void __launch_bounds__(kBlock) k_step_fused(
                 if (!has[i]) continue;
                 AxisRec<T> ar[3];
                 bool ex = false;
+                T xv = T(1);   // value of an exit: the lowest exiting axis decides
                 double dz2[3];
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
                     ar[a] = tab[qa[i][a]];
+                    if (!ex && ar[a].ex == 2) xv = T(0);
                     ex = ex || ar[a].ex;
                     dz2[a] = ar[a].dz2;
                 }
                 if (ball) ex = ex || ball_exit(dz2, D, I.r2);
                 if (ex) {
-                    acc += wq[i] * (T(1) - uref);
+                    acc += wq[i] * (xv - uref);
                 } else {
                     Basis<T> B[3];
                     int k[3];
@@ -1239,11 +1347,26 @@ __global__ void __launch_bounds__(kBlock) k_export_cells(PlanDev P, int inst, in
         const int node = P.active[I.act_off + r];
         int idx[3];
         split_node<D>(I, node, idx);
-        double c[3];
-        node_centre<D>(I, P.coords, time_factors(P, n, inst), P.trig, idx, P.dt, c);
+        double c[3], S[3];
+        node_centre_s<D>(I, P.coords, time_factors(P, n, inst), P.trig, idx, P.dt, c, S);
         int k[3];
         double s[3], h[3];
-        const bool ex = landing_point<D>(I, P.coords, P.gh_a, P.qs, c, q, k, s, h);
+        bool ex;
+        if (P.faces) {
+            int qq = q;
+            ex = false;
+            double dz2[3];
+            for (int a = D - 1; a >= 0; --a) {
+                const AxisEval e = eval_axis_faces(I, P.coords, a, c[a], P.gh_a[qq % P.qs], S[a]);
+                qq /= P.qs;
+                ex = ex || e.ex;
+                dz2[a] = e.dz2;
+                k[a] = e.k;
+            }
+            if (I.region_kind == 1) ex = ex || ball_exit(dz2, D, I.r2);
+        } else {
+            ex = landing_point<D>(I, P.coords, P.gh_a, P.qs, c, q, k, s, h);
+        }
         exitf[t] = ex ? 1 : 0;
         for (int a = 0; a < D; ++a) cells[t * D + a] = ex ? -1 : k[a];
     }

@@ -181,6 +181,7 @@ struct fk_plan {
     std::vector<fk::WorkItem> fw_work, fw_split_work, box_work;
     int box_work_off[fk::kBoxClasses] = {0}, n_box_work[fk::kBoxClasses] = {0};
     bool use_box = false;
+    bool faces = false;   // face kinds other than exit-1, or node-dependent diffusion
     int step_kind = 0;
     int n_table_work = 0;
     std::vector<int64_t> node_off, act_count;
@@ -245,14 +246,27 @@ fk_status validate(const fk_problem &pr, int i)
     long long J = 1;
     for (int a = 0; a < pr.d; ++a) J *= pr.ax[a].n;
     if (J > (1LL << 29)) return fail(FK_ERR_UNSUPPORTED, "instance %d: more than 2^29 nodes", i);
-    if (pr.coef_kind < 0 || pr.coef_kind > 3) return fail(FK_ERR_ARG, "instance %d: coef_kind", i);
+    if (pr.coef_kind < 0 || pr.coef_kind > 4) return fail(FK_ERR_ARG, "instance %d: coef_kind", i);
+    if (pr.coef_kind == FK_COEF_RUNAWAY3D && pr.d != 3)
+        return fail(FK_ERR_ARG, "instance %d: the runaway model needs d = 3", i);
+    if (pr.coef_kind == FK_COEF_RUNAWAY3D &&
+        !(pr.ax[0].nodes[0] > 0 && pr.ax[1].nodes[0] >= -1 && pr.ax[1].nodes[pr.ax[1].n - 1] <= 1))
+        return fail(FK_ERR_ARG, "instance %d: the runaway model needs p > 0 and xi in [-1, 1]", i);
+    for (int a = 0; a < pr.d; ++a)
+        for (int sd = 0; sd < 2; ++sd) {
+            const int f = pr.face[a][sd];
+            if (f < FK_FACE_EXIT1 || f > FK_FACE_REFLECT)
+                return fail(FK_ERR_ARG, "instance %d axis %d: face kind %d", i, a, f);
+            if (f != FK_FACE_EXIT1 && pr.ax[a].periodic)
+                return fail(FK_ERR_ARG, "instance %d axis %d: a periodic axis has no faces", i, a);
+        }
     if (pr.coef_kind == FK_COEF_ROLLS2D && pr.d != 2)
         return fail(FK_ERR_ARG, "instance %d: roll flow needs d = 2", i);
     if (pr.coef_kind == FK_COEF_CELLULAR2D && pr.d != 2)
         return fail(FK_ERR_ARG, "instance %d: cellular flow needs d = 2", i);
     if (pr.coef_kind == FK_COEF_ABC3D && pr.d != 3)
         return fail(FK_ERR_ARG, "instance %d: ABC flow needs d = 3", i);
-    for (int k = 0; k < 7; ++k)
+    for (int k = 0; k < 16; ++k)
         if (!is_finite(pr.coef[k])) return fail(FK_ERR_NONFINITE, "instance %d: non-finite coef", i);
     if (!is_finite(pr.D) || !is_finite(pr.dt) || !is_finite(pr.t0))
         return fail(FK_ERR_NONFINITE, "instance %d: non-finite D, dt or t0", i);
@@ -312,12 +326,16 @@ double drift_bound(const fk_problem &pr, int a)
     return (std::fabs(c[2]) + std::fabs(c[1])) * f;
 }
 
-// Exit test of a point, the same comparisons as the kernels.
-bool exit_point(const fk_problem &pr, const double *z)
+// Exit value of a point (-1: none), the same comparisons as the kernels:
+// faces by the lowest axis, low face first, then the ball (value 1).
+int exit_value(const fk_problem &pr, const double *z)
 {
     for (int a = 0; a < pr.d; ++a) {
         if (pr.ax[a].periodic) continue;
-        if (z[a] <= pr.ax[a].nodes[0] || z[a] >= pr.ax[a].nodes[pr.ax[a].n - 1]) return true;
+        const int fl = pr.face[a][0], fh = pr.face[a][1];
+        if (fl != FK_FACE_REFLECT && z[a] <= pr.ax[a].nodes[0]) return fl == FK_FACE_EXIT0 ? 0 : 1;
+        if (fh != FK_FACE_REFLECT && z[a] >= pr.ax[a].nodes[pr.ax[a].n - 1])
+            return fh == FK_FACE_EXIT0 ? 0 : 1;
     }
     if (pr.region_kind == FK_REGION_BALL) {
         double s = 0.0;
@@ -326,9 +344,83 @@ bool exit_point(const fk_problem &pr, const double *z)
             const double t2 = t * t;
             s = s + t2;
         }
-        if (s >= pr.radius * pr.radius) return true;
+        if (s >= pr.radius * pr.radius) return 1;
     }
-    return false;
+    return -1;
+}
+
+// Runaway-electron model (Section 4.3): the time factors (E, nu_ee, v_T,
+// delta) at t -- constants, or the thermal-quench model when t_* > 0 --
+// and, at node x, the drift and the per-axis diffusion coefficients (the
+// formulas of the kernels' runaway_centre; used for the reach bound).
+void runaway_time_factors(const fk_problem &pr, double t, double *tf)
+{
+    const double *p = pr.coef;
+    if (p[11] > 0.0) {
+        const double Th = p[13] + (p[12] - p[13]) * std::exp(-t / p[11]);
+        const double lnh = 14.9 - 0.5 * std::log(0.28) + std::log(Th);
+        const double lnt = 14.9 - 0.5 * std::log(0.28) + std::log(p[14]);
+        tf[2] = std::sqrt(Th / p[14]);
+        tf[1] = std::pow(p[14] / Th, 1.5) * lnh / lnt;
+        tf[3] = std::sqrt(2.0 * Th / p[15]);
+        tf[0] = p[0] * std::pow(p[12] / Th, 1.5);
+    } else {
+        tf[0] = p[0]; tf[1] = p[4]; tf[2] = p[5]; tf[3] = p[3];
+    }
+}
+
+void runaway_coefficients(const fk_problem &pr, const double *tf, const double *x, double *b,
+                          double *sig)
+{
+    const double *p = pr.coef;
+    const double E = tf[0], nu = tf[1], vT = tf[2], delta = tf[3];
+    const double pm = x[0], xi = x[1], r = x[2];
+    const double gam = std::sqrt(1.0 + (delta * pm) * (delta * pm));
+    const double om = 1.0 - xi * xi;
+    const double y = pm / gam;
+    const double phi = std::erf(y);
+    const double dphi = 2.0 / std::sqrt(M_PI) * std::exp(-y * y);
+    const double psi = (phi - y * dphi) / (2.0 * y * y);
+    const double dpsi = dphi - 2.0 * psi / y;
+    const double k2 = nu * vT * vT;
+    const double CA = k2 * psi / y;
+    const double CB = 0.5 * k2 / y * (p[2] + phi - psi + 0.5 * y * y * std::pow(delta, 4.0));
+    const double CF = 2.0 * nu * vT * psi;
+    const double dCA = k2 * (dpsi * y - psi) / (y * y) / (gam * gam * gam);
+    const double th = std::tanh((r - p[6]) / p[7]);
+    const double ep = std::exp(-(pm / p[8]) * (pm / p[8]));
+    const double Dr = 0.5 * p[10] * (1.0 + th) * ep;
+    const double dDr = 0.5 * p[10] * (1.0 - th * th) / p[7] * ep;
+    b[0] = E * xi - gam * pm / p[1] * om - CF + 2.0 * CA / pm + dCA;
+    b[1] = E * om / pm - xi * om / (p[1] * gam) - 2.0 * xi * CB / (pm * pm);
+    b[2] = (r > p[6] ? p[9] : 0.0) + dDr;
+    sig[0] = std::sqrt(2.0 * CA);
+    sig[1] = std::sqrt(2.0 * CB) / pm * std::sqrt(om > 0.0 ? om : 0.0);
+    sig[2] = std::sqrt(2.0 * Dr);
+}
+
+// Largest |b_a| and sigma_a of the runaway model over the instance's nodes,
+// at the first and the last step, doubled (bounds the reach of its landing
+// points; the active region of this model is the whole grid anyway).
+void runaway_bounds(const fk_problem &pr, double *bmax, double *smax)
+{
+    for (int a = 0; a < 3; ++a) bmax[a] = smax[a] = 0.0;
+    for (int e = 0; e < 2; ++e) {
+        double tf[4];
+        runaway_time_factors(pr, pr.t0 + (e ? pr.n_steps - 1 : 0) * pr.dt, tf);
+        double x[3], b[3], sg[3];
+        for (int i = 0; i < pr.ax[0].n; ++i)
+            for (int j = 0; j < pr.ax[1].n; ++j)
+                for (int k = 0; k < pr.ax[2].n; ++k) {
+                    x[0] = pr.ax[0].nodes[i]; x[1] = pr.ax[1].nodes[j]; x[2] = pr.ax[2].nodes[k];
+                    runaway_coefficients(pr, tf, x, b, sg);
+                    for (int a = 0; a < 3; ++a) {
+                        bmax[a] = std::max(bmax[a], std::fabs(b[a]));
+                        smax[a] = std::max(smax[a], sg[a]);
+                    }
+                }
+    }
+    for (int a = 0; a < 3; ++a) { bmax[a] *= 2.0; smax[a] *= 2.0; }
 }
 
 void add_region(fk_plan *p, const char *name, size_t bytes)
@@ -377,7 +469,13 @@ fk_status build_plan(fk_plan *p)
     p->G = std::max(4, std::min(64, group_of(p->Q)));
     if (p->d * p->qs > p->G) return fail(FK_ERR_UNSUPPORTED, "d * gh_q above the lane group");
     p->n_theta = (p0.coef_kind == FK_COEF_CONST) ? p->d + 1
-               : (p0.coef_kind == FK_COEF_ABC3D ? 5 : 4);
+               : (p0.coef_kind == FK_COEF_ABC3D ? 5
+               : (p0.coef_kind == FK_COEF_RUNAWAY3D ? 1 : 4));
+    for (const fk_problem &pr : p->probs) {
+        p->faces = p->faces || pr.coef_kind == FK_COEF_RUNAWAY3D;
+        for (int a = 0; a < pr.d; ++a)
+            p->faces = p->faces || pr.face[a][0] != FK_FACE_EXIT1 || pr.face[a][1] != FK_FACE_EXIT1;
+    }
     if ((long long)p->Q > 256) return fail(FK_ERR_UNSUPPORTED, "Q = gh_q^d above 256");
 
     p->gh_a.assign(p->qs, 0.0);
@@ -446,13 +544,22 @@ fk_status build_plan(fk_plan *p)
         }
         I.coef_kind = pr.coef_kind;
         I.region_kind = pr.region_kind;
-        for (int k = 0; k < 7; ++k) I.coef[k] = pr.coef[k];
+        for (int k = 0; k < 16; ++k) I.coef[k] = pr.coef[k];
         I.D = pr.D;
         for (int a = 0; a < 3; ++a) I.center[a] = pr.center[a];
         I.r2 = pr.radius * pr.radius;
         const double sq = std::sqrt(2.0 * pr.dt);
         I.S = std::sqrt(2.0 * pr.D) * sq;
         I.dSdD = pr.D > 0 ? I.S / (2.0 * pr.D) : 0.0;
+        double re_bmax[3] = {0, 0, 0}, re_smax[3] = {0, 0, 0};
+        if (pr.coef_kind == FK_COEF_RUNAWAY3D) {
+            runaway_bounds(pr, re_bmax, re_smax);
+            I.sdiff = 1;
+            I.S = 0.0;
+            I.dSdD = 0.0;
+        }
+        for (int a = 0; a < 3; ++a)
+            for (int sd = 0; sd < 2; ++sd) I.face[a][sd] = a < pr.d ? pr.face[a][sd] : 0;
         I.node_off = p->n_nodes;
         I.out_off = p->n_nodes;
         I.act_off = p->n_active;
@@ -469,8 +576,8 @@ fk_status build_plan(fk_plan *p)
             for (int a = 0; a < pr.d; ++a)
                 if (pr.ax[a].periodic && idx[a] == pr.ax[a].n - 1) { image = true; idx[a] = 0; }
             for (int a = 0; a < pr.d; ++a) x[a] = pr.ax[a].nodes[idx[a]];
-            const bool ex = skip_i || exit_point(pr, x);
-            c[j] = (unsigned char)((image ? 2 : 0) | (ex ? 1 : 0));
+            const int ev = skip_i ? 1 : exit_value(pr, x);
+            c[j] = (unsigned char)((image ? 2 : 0) | (ev >= 0 ? 1 : 0) | (ev == 0 ? 4 : 0));
         }
         int na = 0;
         int amin[3] = {1 << 30, 1 << 30, 1 << 30}, amax_i[3] = {-1, -1, -1};
@@ -487,7 +594,7 @@ fk_status build_plan(fk_plan *p)
                 }
             }
         // trig tables of the drift arguments, one entry per axis coordinate
-        if (pr.coef_kind != FK_COEF_CONST)
+        if (pr.coef_kind != FK_COEF_CONST && pr.coef_kind != FK_COEF_RUNAWAY3D)
             for (int a = 0; a < pr.d; ++a)
                 build_work(tables, i, pr.ax[a].n, kBlock, 0, 1 + a);
         // slope records are needed only where landing cells of active nodes can
@@ -498,7 +605,9 @@ fk_status build_plan(fk_plan *p)
             double hmin = 1e300;
             for (int k = 1; k < pr.ax[a].n; ++k)
                 hmin = std::min(hmin, pr.ax[a].nodes[k] - pr.ax[a].nodes[k - 1]);
-            const double reach = drift_bound(pr, a) * pr.dt + I.S * amax;
+            const double reach = pr.coef_kind == FK_COEF_RUNAWAY3D
+                ? re_bmax[a] * pr.dt + re_smax[a] * std::sqrt(2.0 * pr.dt) * amax
+                : drift_bound(pr, a) * pr.dt + I.S * amax;
             const double cells = std::ceil(reach / hmin) + 2.0;
             const int dil = cells > 1e9 ? (1 << 30) : (int)cells;
             // a landing cell lies within ceil(reach / h) cells of its node, and
@@ -637,13 +746,13 @@ fk_status build_plan(fk_plan *p)
         bool affine = true;
         for (const fk::DevInst &I : p->inst)
             for (int a = 0; a < p->d; ++a) affine = affine && I.affine[a];
-        if (sk == 2 || !node_ok) p->step_kind = 1;
+        if (sk == 2 || !node_ok || p->faces) p->step_kind = 1;   // faces: the lane-group step
         else if (sk == 3 || (sk == 0 && !large)) p->step_kind = 2;
         else p->step_kind = 0;
         // the separable form by default in 3D only: there a node's Q*^3
         // points gather 8 corners each, against L^3 records of its footprint;
         // in 2D (Q*^2 points x 4 corners vs L^2) the per-point gather is faster
-        p->use_box = node_ok && affine && fk::box_compiled(p->d, p->qs) &&
+        p->use_box = node_ok && affine && !p->faces && fk::box_compiled(p->d, p->qs) &&
                      (sk == 4 || (sk == 0 && large && p->d == 3));
         const int gs = std::max(2, group_of(p->qs));
         std::vector<std::vector<fk::WorkItem>> bw(fk::kBoxClasses);
@@ -836,6 +945,8 @@ fk_status build_plan(fk_plan *p)
                 tf[1] = std::sin(pr.coef[2] * t);
                 tf[2] = std::cos(pr.coef[2] * t);
                 tf[3] = t;
+            } else if (pr.coef_kind == FK_COEF_RUNAWAY3D) {
+                runaway_time_factors(pr, t, tf);
             } else if (pr.coef_kind == FK_COEF_ROLLS2D) {
                 tf[0] = pr.coef[1] * std::cos(pr.coef[2] * t);
                 tf[1] = std::cos(pr.coef[2] * t);
@@ -1085,6 +1196,7 @@ void fill_dev(fk_plan *p)
     D.block = kBlock;
     D.group = p->G;
     D.hermite2 = (p->opt.hermite == FK_HERMITE_R2 && p->d == 2) ? 1 : 0;
+    D.faces = p->faces ? 1 : 0;
     D.all_affine = 1;
     for (const fk::DevInst &I : p->inst)
         for (int a = 0; a < p->d; ++a)
@@ -1358,6 +1470,14 @@ fk_status fk_plan_create(const fk_problem *probs, int n_inst, const fk_options *
             b.t0 != a.t0 || b.coef_kind != a.coef_kind || b.region_kind != a.region_kind)
             return fail(FK_ERR_ARG, "instance %d: d, gh_q, dt, n_steps, t0, coef_kind and "
                         "region_kind must match instance 0", i);
+    }
+    for (int i = 0; i < n_inst; ++i) {
+        bool fc = probs[i].coef_kind == FK_COEF_RUNAWAY3D;
+        for (int a = 0; a < probs[i].d; ++a)
+            fc = fc || probs[i].face[a][0] != FK_FACE_EXIT1 || probs[i].face[a][1] != FK_FACE_EXIT1;
+        if (fc && (o.form != FK_FORM_FUSED || o.ckpt_every > 0))
+            return fail(FK_ERR_UNSUPPORTED, "instance %d: face kinds other than exit-1 and the "
+                        "runaway model run the fused forward calls only", i);
     }
     if (o.ckpt_every > 0)
         for (int i = 0; i < n_inst; ++i)

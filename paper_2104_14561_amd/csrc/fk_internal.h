@@ -29,7 +29,7 @@ struct DevInst {
     long long coord_off[kMaxDim];  // offsets of the axes in the coordinate array
     long long act_off;             // offset in the packed active list
     double lo[kMaxDim], hi[kMaxDim], inv_h[kMaxDim], period[kMaxDim], step[kMaxDim];
-    double coef[7];
+    double coef[16];
     double D;
     double center[kMaxDim];
     double r2;
@@ -46,6 +46,9 @@ struct DevInst {
     // FP64 sub-plan of an FP32 plan, whose inputs and outputs use the
     // parent's layout
     long long out_off;
+    int face[kMaxDim][2];          // FK_FACE_* per axis and side
+    int sdiff;                     // diffusion depends on the node (runaway model)
+    int pad1;
 };
 
 // A contiguous chunk of one instance's nodes (slope pass) or active nodes
@@ -118,6 +121,7 @@ struct PlanDev {
     int step_kind;              // 0: thread per node, 1: lane group, 2: split node
     int all_affine;             // every axis of every instance is affine
     int hermite2;               // R2 interpolant (2D): twist field in the records
+    int faces;                  // face kinds other than exit-1, or node-dependent diffusion
     // forward step work: nodes handled per landing point (fw) and separable
     // nodes handled in box form, by box class
     const int *fw_nodes;

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libfkexit.so")
 FK_OK = 0
 STATUS = {0: "FK_OK", -1: "FK_ERR_ARG", -2: "FK_ERR_UNSUPPORTED", -3: "FK_ERR_WORKSPACE",
           -4: "FK_ERR_HIP", -5: "FK_ERR_NONFINITE", -6: "FK_ERR_STATE"}
-COEF = {"const": 0, "cellular2d": 1, "abc3d": 2, "rolls2d": 3}
+COEF = {"const": 0, "cellular2d": 1, "abc3d": 2, "rolls2d": 3, "runaway3d": 4}
+FACE = {"exit1": 0, "exit0": 1, "reflect": 2}
 REGION = {"box": 0, "ball": 1}
 PREC = {"f64": 0, "f32": 1}
 FORM = {"fused": 0, "ell": 1}
@@ -47,11 +48,11 @@ class _Axis(ctypes.Structure):
 
 class _Problem(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int), ("ax", _Axis * 3), ("coef_kind", ctypes.c_int),
-                ("coef", ctypes.c_double * 7), ("D", ctypes.c_double),
+                ("coef", ctypes.c_double * 16), ("D", ctypes.c_double),
                 ("region_kind", ctypes.c_int), ("center", ctypes.c_double * 3),
                 ("radius", ctypes.c_double), ("gh_q", ctypes.c_int), ("dt", ctypes.c_double),
                 ("n_steps", ctypes.c_int), ("t0", ctypes.c_double),
-                ("force_f64", ctypes.c_int)]
+                ("force_f64", ctypes.c_int), ("face", (ctypes.c_int * 2) * 3)]
 
 
 class _Options(ctypes.Structure):
@@ -167,6 +168,10 @@ def _marshal(problems, force_f64=None) -> tuple:
         s.n_steps = int(pr.n_steps)
         s.t0 = float(pr.t0)
         s.force_f64 = int(bool(force_f64[i])) if force_f64 is not None else 0
+        faces = getattr(pr, "faces", None)
+        for a in range(3):
+            for side in range(2):
+                s.face[a][side] = FACE[faces[a][side]] if faces and a < len(faces) else 0
     return arr, keep
 
 

@@ -1,0 +1,93 @@
+"""Boundary faces (exit with 1, exit with 0, reflecting) and the
+runaway-electron model of Section 4.3 (drift and diagonal diffusion that
+depend on the node, non-uniform radial grid) on the GPU against the oracle:
+fields FP64 within 1e-12 and FP32 within 1e-5, landing cells and exit flags
+bit-exact, on 1D Brownian exits through one face, a 2D problem with mixed
+faces, the runaway model (time-independent and thermal-quench) on a small
+grid and on the paper's grid (49 x 41 x 128, the radial spacing 0.1 on
+[0, 0.7] and 0.0025 on [0.7, 1]) over the first 48 steps."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2104_14561_amd import FkError, Plan  # noqa: E402
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def _run(prob, prec, snaps):
+    plan = Plan(prob, precision=prec, use_graph=True)
+    out = plan.split(plan.forward(snaps))[0].double().cpu().numpy()
+    torch.cuda.synchronize()
+    assert plan.check_flags() == 0
+    plan.close()
+    return out
+
+
+def _cases():
+    bm = lambda faces: W.Problem(axes=[W.uniform_axis(0.0, 1.0, 101)], coef_kind="const",  # noqa: E731
+                                 coef=(0.3,), D=0.1, region_kind="box", gh_q=8, dt=1e-3,
+                                 n_steps=150, faces=(faces,))
+    mixed = W.Problem(axes=[W.uniform_axis(0.0, 1.0, 41), W.uniform_axis(0.0, 2.0, 53)],
+                      coef_kind="const", coef=(-0.8, 0.5), D=0.02, region_kind="box", gh_q=5,
+                      dt=0.01, n_steps=30, faces=(("exit0", "exit1"), ("reflect", "exit0")))
+    re_small = W.runaway3d(n_p=13, n_xi=9, r_axis=W.remark2_axis(0.0, 0.7, 1.0, 0.1, 0.05),
+                           dt=1.0, T=20.0)
+    re_tq = W.runaway3d(n_p=13, n_xi=9, r_axis=W.remark2_axis(0.0, 0.7, 1.0, 0.1, 0.05),
+                        dt=1.0, T=20.0, t_star=10.0, E0=0.05, That0=3.0, Thatf=0.5,
+                        Ttilde=3.0, tau=6000.0)
+    return {"bm_exit0": bm(("exit0", "exit1")), "bm_reflect": bm(("reflect", "exit1")),
+            "mixed2d": mixed, "runaway": re_small, "runaway_quench": re_tq}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("name", ["bm_exit0", "bm_reflect", "mixed2d", "runaway", "runaway_quench"])
+def test_faces_and_runaway_match_oracle(name, prec):
+    prob = _cases()[name]
+    snaps = [prob.n_steps, prob.n_steps // 2, 0]
+    ref = oracle.solve(prob, snaps=snaps)
+    got = _run(prob, prec, snaps)
+    err = float(np.abs(got - ref).max())
+    print(f"{name} {prec}: max|gpu - oracle| {err:.3e} (u0 in [{ref[-1].min():.3g}, {ref[-1].max():.3g}])")
+    assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("name", ["bm_reflect", "mixed2d", "runaway"])
+def test_faces_landing_cells_bit_exact(name):
+    prob = _cases()[name]
+    plan = Plan(prob)
+    chi = oracle.chi(prob)
+    for n in (0, prob.n_steps - 1):
+        cells, exitf = plan.export_cells(0, n)
+        torch.cuda.synchronize()
+        rc, rf = oracle.step_cells(prob, n, chi)
+        assert int((cells.cpu().numpy() != rc).sum()) == 0
+        assert int((exitf.cpu().numpy() != rf).sum()) == 0
+    plan.close()
+
+
+def test_runaway_paper_grid_first_48_steps():
+    prob = W.runaway3d(T=24.0)          # 49 x 41 x 128, dt = 0.5
+    ref = oracle.solve(prob, snaps=[0])[0]
+    for prec in ("f64", "f32"):
+        got = _run(prob, prec, [0])[0]
+        err = float(np.abs(got - ref).max())
+        print(f"runaway 49x41x128 {prec}: {err:.3e}")
+        assert err <= TOL[prec]
+
+
+def test_faces_refused_outside_what_is_built():
+    prob = _cases()["mixed2d"]
+    for kw in ({"form": "ell"}, {"ckpt_every": 4}):
+        with pytest.raises(FkError, match="FK_ERR_UNSUPPORTED"):
+            Plan(prob, **kw)
