@@ -14,7 +14,9 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfkexit.so")
+# FKEXIT_LIB names another build of the same library (the AddressSanitizer
+# build of the host code, for instance)
+LIB_PATH = os.environ.get("FKEXIT_LIB") or os.path.join(_HERE, "libfkexit.so")
 
 FK_OK = 0
 STATUS = {0: "FK_OK", -1: "FK_ERR_ARG", -2: "FK_ERR_UNSUPPORTED", -3: "FK_ERR_WORKSPACE",
