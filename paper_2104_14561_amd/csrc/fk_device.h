@@ -2091,8 +2091,10 @@ __device__ inline void node_theta(const PlanDev &P, const DevInst &I, const doub
 // in-cell position, width, exit flag, ball distance) are evaluated once per
 // node; the Hermite bases are rebuilt from them per point, which keeps the
 // kernel's registers low enough for several waves per SIMD.  The scatter goes
-// to the work item's LDS tile (field planes, padded rows), flushed once.
-template <typename T, int D, int QS, bool AFF>
+// to the work item's LDS tile (field planes, padded rows), flushed once.  IN
+// (2D): the host has shown that no landing point of the work item's nodes can
+// exit (reach bound), so the exit tests and their per-point data are left out.
+template <typename T, int D, int QS, bool AFF, bool IN>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 2))) k_adjoint_node(
     const PlanDev P, int n, int n_work, const DevInst *__restrict__ insts,
     const WorkItem *__restrict__ work, const TileBox *__restrict__ tiles,
@@ -2147,9 +2149,12 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
             if constexpr (D == 2) {
                 const long long s0 = I.stride[0];
                 const int pl = tile.plane, pitch = tile.pitch;
+                // one row of landing points at a time (unrolled rows would hold
+                // every row's gathers in registers)
+#pragma unroll 1
                 for (int q0 = 0; q0 < QS; ++q0) {
                     const AxisEval e0 = eval_axis_t<AFF>(I, coords, 0, c[0], ga[q0]);
-                    if (e0.ex) continue;
+                    if (!IN && e0.ex) continue;
                     const Basis<T> X = hermite<T>(e0.s, e0.h), Xz = hermite_dz<T>(e0.s, e0.h);
                     const T w0 = w1[q0], a0 = (T)ga[q0];
                     const T Lw0 = Lm * w0;
@@ -2161,16 +2166,25 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
                     const long long row = I.node_off + (long long)e0.k * s0;
 #pragma unroll
                     for (int q1 = 0; q1 < QS; ++q1) {
-                        bool ex = exin[q1];
-                        if (ball) ex = ex || ball_exit2(e0.dz2, din[q1], r2);
-                        if (ex) continue;
-                        const T s = sin_[q1], h = hin[q1];
+                        if constexpr (!IN) {
+                            bool ex = exin[q1];
+                            if (ball) ex = ex || ball_exit2(e0.dz2, din[q1], r2);
+                            if (ex) continue;
+                        }
+                        T s = sin_[q1], h = hin[q1];
+                        // the bases below depend on q1 only: keep them from being
+                        // hoisted out of the q0 loop for all q1 at once (that
+                        // would hold 8 x 12 values in registers and spill)
+                        int k1 = kin[q1];
+                        asm volatile("" : "+v"(s), "+v"(h), "+v"(k1));
+                        // interior points have valid cells; the (never taken)
+                        // branch keeps each point's code in its own block
+                        if (IN && k1 < 0) continue;
                         const T om = T(1) - s;
                         const T yv0 = (T(1) + T(2) * s) * om * om, yv1 = s * s * (T(3) - T(2) * s);
                         const T yd0 = h * s * om * om, yd1 = h * s * s * (s - T(1));
                         const T zv0 = (T(6) * s * s - T(6) * s) / h, zv1 = (T(6) * s - T(6) * s * s) / h;
                         const T zd0 = T(1) - T(4) * s + T(3) * s * s, zd1 = T(3) * s * s - T(2) * s;
-                        const int k1 = kin[q1];
                         const long long b = row + k1;
                         const R p00 = rec[b], p01 = rec[b + 1], p10 = rec[b + s0], p11 = rec[b + s0 + 1];
                         // interpolant gradient: d/dz0 (Xz, Y) and d/dz1 (X, Yz)

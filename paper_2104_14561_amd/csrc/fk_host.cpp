@@ -175,6 +175,7 @@ struct fk_plan {
         std::vector<fk::WorkItem> fw_work, box_work;
         std::vector<fk::TileBox> fw_tiles, box_tiles;
         int box_work_off[fk::kBoxClasses] = {0}, n_box_work[fk::kBoxClasses] = {0};
+        int n_in_work = 0;
     } adj;
     // forward step lists
     std::vector<int> fw_nodes, box_nodes;
@@ -918,6 +919,21 @@ fk_status build_plan(fk_plan *p)
                 p->adj.fw_nodes.insert(p->adj.fw_nodes.end(), fw.begin(), fw.end());
                 patch_work(p->adj.fw_work, i, keys, f1, kBlock);
             }
+            // 2D: work items none of whose nodes has a landing point that can
+            // exit go first (their kernel has no exit tests)
+            if (p->d == 2) {
+                std::vector<fk::WorkItem> in, rest;
+                for (fk::WorkItem it : p->adj.fw_work) {
+                    bool all = true;
+                    for (int u = 0; u < it.count && all; ++u)
+                        all = inst_inner[it.inst][p->adj.fw_nodes[it.first + u]] != 0;
+                    it.kind = all ? 1 : 0;
+                    (all ? in : rest).push_back(it);
+                }
+                p->adj.n_in_work = (int)in.size();
+                in.insert(in.end(), rest.begin(), rest.end());
+                p->adj.fw_work.swap(in);
+            }
             for (int c2 = 0; c2 < fk::kBoxClasses; ++c2) {
                 p->adj.box_work_off[c2] = (int)p->adj.box_work.size();
                 p->adj.n_box_work[c2] = (int)abw[c2].size();
@@ -1155,8 +1171,10 @@ void fill_dev(fk_plan *p)
     D.adj.fw_nodes = (const int *)p->at("afw_nodes");
     D.adj.fw_work = (const fk::WorkItem *)p->at("afw_work");
     D.adj.fw_tiles = (const fk::TileBox *)p->at("afw_tiles");
-    D.adj.n_fw_work = (int)p->adj.fw_work.size();
-    D.adj.fw_grid = grid_for(p->adj.fw_work.size());
+    D.adj.n_in_work = p->adj.n_in_work;
+    D.adj.n_fw_work = (int)p->adj.fw_work.size() - p->adj.n_in_work;
+    D.adj.in_grid = grid_for(p->adj.n_in_work);
+    D.adj.fw_grid = grid_for(D.adj.n_fw_work);
     D.adj.box_nodes = (const int *)p->at("abox_nodes");
     D.adj.box_work = (const fk::WorkItem *)p->at("abox_work");
     D.adj.box_tiles = (const fk::TileBox *)p->at("abox_tiles");

@@ -80,6 +80,9 @@ struct AdjLists {
     const TileBox *fw_tiles;
     int n_fw_work;
     int fw_grid;
+    // the first n_in_work items: no landing point of any of their nodes can exit
+    int n_in_work;
+    int in_grid;
     const int *box_nodes;
     const WorkItem *box_work;
     const TileBox *box_tiles;

@@ -220,7 +220,7 @@ hipError_t launch_adjoint_step(const PlanDev &P0, bool f32, int n, const void *p
         PlanDev P = P0;
         if (part == 1)
             for (int c = 0; c < kBoxClasses; ++c) P.adj.n_box_work[c] = 0;
-        if (part == 2) P.adj.n_fw_work = 0;
+        if (part == 2) P.adj.n_fw_work = P.adj.n_in_work = 0;
         bool ok = false;
         switch (P.d) {
         case 1: ok = f32 ? adjoint_node_f32_d1(P, n, packed, lam, mu, grad, s) : adjoint_node_f64_d1(P, n, packed, lam, mu, grad, s); break;

@@ -79,14 +79,27 @@ void adjoint_node_launch(const PlanDev &P, int n, const void *packed, const void
 {
     const size_t lds = (size_t)P.tile_elems * sizeof(double);   // FP64 tiles
     const AdjLists &A = P.adj;
-    if (A.n_fw_work > 0) {
+    // interior items (no exit tests; 2D plans only) first, then the rest
+    if constexpr (D == 2) if (A.n_in_work > 0) {
         if (P.all_affine)
-            k_adjoint_node<T, D, QS, true><<<A.fw_grid, kBlock, lds, s>>>(
-                P, n, A.n_fw_work, P.inst, A.fw_work, A.fw_tiles, A.fw_nodes, P.trig, P.coords,
+            k_adjoint_node<T, D, QS, true, true><<<A.in_grid, kBlock, lds, s>>>(
+                P, n, A.n_in_work, P.inst, A.fw_work, A.fw_tiles, A.fw_nodes, P.trig, P.coords,
                 (const T *)packed, (const T *)lam, (T *)mu, grad);
         else
-            k_adjoint_node<T, D, QS, false><<<A.fw_grid, kBlock, lds, s>>>(
-                P, n, A.n_fw_work, P.inst, A.fw_work, A.fw_tiles, A.fw_nodes, P.trig, P.coords,
+            k_adjoint_node<T, D, QS, false, true><<<A.in_grid, kBlock, lds, s>>>(
+                P, n, A.n_in_work, P.inst, A.fw_work, A.fw_tiles, A.fw_nodes, P.trig, P.coords,
+                (const T *)packed, (const T *)lam, (T *)mu, grad);
+    }
+    if (A.n_fw_work > 0) {
+        const WorkItem *wk = A.fw_work + A.n_in_work;
+        const TileBox *tl = A.fw_tiles + A.n_in_work;
+        if (P.all_affine)
+            k_adjoint_node<T, D, QS, true, false><<<A.fw_grid, kBlock, lds, s>>>(
+                P, n, A.n_fw_work, P.inst, wk, tl, A.fw_nodes, P.trig, P.coords,
+                (const T *)packed, (const T *)lam, (T *)mu, grad);
+        else
+            k_adjoint_node<T, D, QS, false, false><<<A.fw_grid, kBlock, lds, s>>>(
+                P, n, A.n_fw_work, P.inst, wk, tl, A.fw_nodes, P.trig, P.coords,
                 (const T *)packed, (const T *)lam, (T *)mu, grad);
     }
     if constexpr (D == 2) {
