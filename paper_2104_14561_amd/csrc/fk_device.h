@@ -2031,11 +2031,13 @@ struct MuTile {
             const int ll = r % pitch;
             if (ll >= ext[D - 1]) continue;
             r /= pitch;
-            long long o = I.node_off + (long long)(lo[D - 1] + ll) * I.stride[D - 1];
+            // tiles of periodic axes may run past the seam: wrap back onto the grid
+            long long o = I.node_off + (long long)wrap_index(lo[D - 1] + ll, I.n[D - 1],
+                                                             I.periodic[D - 1]) * I.stride[D - 1];
             for (int a = D - 2; a >= 0; --a) {
                 const int la = r % ext[a];
                 r /= ext[a];
-                o += (long long)(lo[a] + la) * I.stride[a];
+                o += (long long)wrap_index(lo[a] + la, I.n[a], I.periodic[a]) * I.stride[a];
             }
             atomicAdd(&mu[o * PS + f], v);
         }
@@ -2528,8 +2530,9 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_box(
         tile.init(tmem, tiles[w]);
         tile.clear();
         __syncthreads();
-        auto scatter = [&](const int *cidx, int f, T v) {
-            const int off = tile.node_offset(cidx);
+        // uidx: unwrapped box indices (the tile's), cidx: the grid's
+        auto scatter = [&](const int *uidx, const int *cidx, int f, T v) {
+            const int off = tile.node_offset(uidx);
             if (off >= 0) {
                 lds_add(&tmem[f * tile.plane + off], v);
                 return;
@@ -2566,9 +2569,9 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_box(
                     const R r = rec[I.node_off + ci];
                     Gz[0] += dV[0][i] * r.x + dS[0][i] * r.y;
                     Hz[0] += aV[0][i] * r.x + aS[0][i] * r.y;
-                    int cidx[1] = {ci};
-                    scatter(cidx, 0, Lm * V[0][i]);
-                    scatter(cidx, 1, Lm * Sv[0][i]);
+                    int cidx[1] = {ci}, uidx[1] = {o[0] + i};
+                    scatter(uidx, cidx, 0, Lm * V[0][i]);
+                    scatter(uidx, cidx, 1, Lm * Sv[0][i]);
                 }
             } else if constexpr (D == 2) {
 #pragma unroll
@@ -2582,10 +2585,10 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_box(
                         Gz[1] += V[0][i] * (dV[1][j] * r.x + dS[1][j] * r.z) + Sv[0][i] * dV[1][j] * r.y;
                         Hz[0] += aV[0][i] * (V[1][j] * r.x + Sv[1][j] * r.z) + aS[0][i] * V[1][j] * r.y;
                         Hz[1] += V[0][i] * (aV[1][j] * r.x + aS[1][j] * r.z) + Sv[0][i] * aV[1][j] * r.y;
-                        int cidx[2] = {ci, cj};
-                        scatter(cidx, 0, Lm * V[0][i] * V[1][j]);
-                        scatter(cidx, 1, Lm * Sv[0][i] * V[1][j]);
-                        scatter(cidx, 2, Lm * V[0][i] * Sv[1][j]);
+                        int cidx[2] = {ci, cj}, uidx[2] = {o[0] + i, o[1] + j};
+                        scatter(uidx, cidx, 0, Lm * V[0][i] * V[1][j]);
+                        scatter(uidx, cidx, 1, Lm * Sv[0][i] * V[1][j]);
+                        scatter(uidx, cidx, 2, Lm * V[0][i] * Sv[1][j]);
                     }
                 }
             } else {
@@ -2617,12 +2620,12 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_box(
                             const T t2s = v01 * r.w;
                             Gz[2] += dV[2][kk] * t2 + dS[2][kk] * t2s;
                             Hz[2] += aV[2][kk] * t2 + aS[2][kk] * t2s;
-                            int cidx[3] = {ci, cj, ck};
+                            int cidx[3] = {ci, cj, ck}, uidx[3] = {o[0] + i, o[1] + j, o[2] + kk};
                             const T lv = Lm * v01 * V[2][kk];
-                            scatter(cidx, 0, lv);
-                            scatter(cidx, 1, Lm * Sv[0][i] * V[1][j] * V[2][kk]);
-                            scatter(cidx, 2, Lm * V[0][i] * Sv[1][j] * V[2][kk]);
-                            scatter(cidx, 3, Lm * v01 * Sv[2][kk]);
+                            scatter(uidx, cidx, 0, lv);
+                            scatter(uidx, cidx, 1, Lm * Sv[0][i] * V[1][j] * V[2][kk]);
+                            scatter(uidx, cidx, 2, Lm * V[0][i] * Sv[1][j] * V[2][kk]);
+                            scatter(uidx, cidx, 3, Lm * v01 * Sv[2][kk]);
                         }
                     }
                 }

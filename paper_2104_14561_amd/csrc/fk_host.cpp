@@ -843,7 +843,9 @@ fk_status build_plan(fk_plan *p)
         const int NF = p->d + 1;
         const size_t elt_b = 8;   // tiles accumulate in FP64 in both precisions
         const size_t budget = 60 * 1024;   // plus static LDS, within 64 KB per workgroup
-        auto tile_of = [&](const fk::WorkItem &it, const std::vector<int> &list) {
+        // wrap: a periodic axis' tile may run past the seam (unwrapped indices,
+        // less than one period long); the kernel then indexes it unwrapped
+        auto tile_of = [&](const fk::WorkItem &it, const std::vector<int> &list, bool wrap) {
             const fk_problem &pr = p->probs[it.inst];
             int mn[3] = {1 << 30, 1 << 30, 1 << 30}, mx[3] = {-1, -1, -1};
             for (int t = 0; t < it.count; ++t) {
@@ -862,9 +864,12 @@ fk_status build_plan(fk_plan *p)
             for (int a = 0; a < pr.d; ++a) {
                 const int dil = inst_dils[it.inst][a];
                 int lo = mn[a] - dil, hi = mx[a] + dil;
-                if (pr.ax[a].periodic && (lo < 0 || hi > pr.ax[a].n - 1)) ok = false;
-                lo = std::max(lo, 0);
-                hi = std::min(hi, pr.ax[a].n - 1);
+                if (pr.ax[a].periodic && (lo < 0 || hi > pr.ax[a].n - 1)) {
+                    if (!wrap || hi - lo + 1 > pr.ax[a].n - 1) ok = false;
+                } else {
+                    lo = std::max(lo, 0);
+                    hi = std::min(hi, pr.ax[a].n - 1);
+                }
                 tb.lo[a] = lo;
                 tb.ext[a] = std::max(hi - lo + 1, 1);
                 if (a < pr.d - 1) elems *= (size_t)tb.ext[a];
@@ -940,9 +945,10 @@ fk_status build_plan(fk_plan *p)
                 p->adj.box_work.insert(p->adj.box_work.end(), abw[c2].begin(), abw[c2].end());
             }
             for (const fk::WorkItem &it : p->adj.fw_work)
-                p->adj.fw_tiles.push_back(tile_of(it, p->adj.fw_nodes));
+                p->adj.fw_tiles.push_back(tile_of(it, p->adj.fw_nodes, false));
             for (const fk::WorkItem &it : p->adj.box_work)
-                p->adj.box_tiles.push_back(tile_of(it, p->adj.box_nodes));
+                // the box kernels index their tiles with unwrapped indices
+                p->adj.box_tiles.push_back(tile_of(it, p->adj.box_nodes, true));
         }
     }
     p->slope_work = tables;
