@@ -2592,42 +2592,91 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_box(
                     }
                 }
             } else {
+                // theta-gradient first, contracting along the innermost axis: per
+                // box row (i, j) twelve sums of the records against the axis-2
+                // vectors, then the axis-0 and axis-1 factors once per row
+                int ck[L];
+#pragma unroll
+                for (int kk = 0; kk < L; ++kk) ck[kk] = wrap_index(o[2] + kk, I.n[2], I.periodic[2]);
 #pragma unroll
                 for (int i = 0; i < L; ++i) {
                     const int ci = wrap_index(o[0] + i, I.n[0], I.periodic[0]);
 #pragma unroll
                     for (int j = 0; j < L; ++j) {
                         const int cj = wrap_index(o[1] + j, I.n[1], I.periodic[1]);
+                        const R *rr = rec + I.node_off + (long long)ci * I.stride[0] +
+                                      (long long)cj * I.stride[1];
+                        T uV = T(0), udV = T(0), uaV = T(0), g0V = T(0), g0dV = T(0), g0aV = T(0);
+                        T g1V = T(0), g1dV = T(0), g1aV = T(0), g2S = T(0), g2dS = T(0), g2aS = T(0);
 #pragma unroll
                         for (int kk = 0; kk < L; ++kk) {
-                            const int ck = wrap_index(o[2] + kk, I.n[2], I.periodic[2]);
-                            const R r = rec[I.node_off + (long long)ci * I.stride[0] +
-                                            (long long)cj * I.stride[1] + ck];
-                            // f(A, B, C) = A V1 V2 u + As V1 V2 g0 + A S1 V2 g1 + A V1 S2 g2
-                            // with per-axis pairs (value, slope) for the three axes
-                            const T v12 = V[1][j] * V[2][kk];
-                            const T t0 = v12 * r.x + Sv[1][j] * V[2][kk] * r.z + V[1][j] * Sv[2][kk] * r.w;
-                            const T t0s = v12 * r.y;
-                            Gz[0] += dV[0][i] * t0 + dS[0][i] * t0s;
-                            Hz[0] += aV[0][i] * t0 + aS[0][i] * t0s;
-                            const T v02 = V[0][i] * V[2][kk];
-                            const T t1 = v02 * r.x + Sv[0][i] * V[2][kk] * r.y + V[0][i] * Sv[2][kk] * r.w;
-                            const T t1s = v02 * r.z;
-                            Gz[1] += dV[1][j] * t1 + dS[1][j] * t1s;
-                            Hz[1] += aV[1][j] * t1 + aS[1][j] * t1s;
-                            const T v01 = V[0][i] * V[1][j];
-                            const T t2 = v01 * r.x + Sv[0][i] * V[1][j] * r.y + V[0][i] * Sv[1][j] * r.z;
-                            const T t2s = v01 * r.w;
-                            Gz[2] += dV[2][kk] * t2 + dS[2][kk] * t2s;
-                            Hz[2] += aV[2][kk] * t2 + aS[2][kk] * t2s;
-                            int cidx[3] = {ci, cj, ck}, uidx[3] = {o[0] + i, o[1] + j, o[2] + kk};
-                            const T lv = Lm * v01 * V[2][kk];
-                            scatter(uidx, cidx, 0, lv);
-                            scatter(uidx, cidx, 1, Lm * Sv[0][i] * V[1][j] * V[2][kk]);
-                            scatter(uidx, cidx, 2, Lm * V[0][i] * Sv[1][j] * V[2][kk]);
-                            scatter(uidx, cidx, 3, Lm * v01 * Sv[2][kk]);
+                            const R r = rr[ck[kk]];
+                            uV += V[2][kk] * r.x;
+                            udV += dV[2][kk] * r.x;
+                            uaV += aV[2][kk] * r.x;
+                            g0V += V[2][kk] * r.y;
+                            g0dV += dV[2][kk] * r.y;
+                            g0aV += aV[2][kk] * r.y;
+                            g1V += V[2][kk] * r.z;
+                            g1dV += dV[2][kk] * r.z;
+                            g1aV += aV[2][kk] * r.z;
+                            g2S += Sv[2][kk] * r.w;
+                            g2dS += dS[2][kk] * r.w;
+                            g2aS += aS[2][kk] * r.w;
                         }
+                        // d/dz_a of (V0 V1 V2 u + S0 V1 V2 g0 + V0 S1 V2 g1 + V0 V1 S2 g2)
+                        const T in0 = V[1][j] * (uV + g2S) + Sv[1][j] * g1V, s0 = V[1][j] * g0V;
+                        Gz[0] += dV[0][i] * in0 + dS[0][i] * s0;
+                        Hz[0] += aV[0][i] * in0 + aS[0][i] * s0;
+                        const T in1 = V[0][i] * (uV + g2S) + Sv[0][i] * g0V, s1 = V[0][i] * g1V;
+                        Gz[1] += dV[1][j] * in1 + dS[1][j] * s1;
+                        Hz[1] += aV[1][j] * in1 + aS[1][j] * s1;
+                        const T v01 = V[0][i] * V[1][j], s0v1 = Sv[0][i] * V[1][j], v0s1 = V[0][i] * Sv[1][j];
+                        Gz[2] += v01 * (udV + g2dS) + s0v1 * g0dV + v0s1 * g1dV;
+                        Hz[2] += v01 * (uaV + g2aS) + s0v1 * g0aV + v0s1 * g1aV;
                     }
+                }
+                // transposed weights of box node (i, j, k): row factors
+                // Lm (V0 V1, S0 V1, V0 S1) times V2, and Lm V0 V1 times S2
+                const int b0 = o[0] - tile.lo[0], b1 = o[1] - tile.lo[1], b2 = o[2] - tile.lo[2];
+                if (tile.use && b0 >= 0 && b0 + L <= tile.ext[0] && b1 >= 0 && b1 + L <= tile.ext[1] &&
+                    b2 >= 0 && b2 + L <= tile.pitch) {
+#pragma unroll
+                    for (int i = 0; i < L; ++i)
+#pragma unroll
+                        for (int j = 0; j < L; ++j) {
+                            const T fa = Lm * V[0][i] * V[1][j], fb = Lm * Sv[0][i] * V[1][j];
+                            const T fc = Lm * V[0][i] * Sv[1][j];
+                            double *t = tmem + ((b0 + i) * tile.ext[1] + (b1 + j)) * tile.pitch + b2;
+#pragma unroll
+                            for (int kk = 0; kk < L; ++kk) {
+                                lds_add(t + kk, fa * V[2][kk]);
+                                lds_add(t + tile.plane + kk, fb * V[2][kk]);
+                                lds_add(t + 2 * tile.plane + kk, fc * V[2][kk]);
+                                lds_add(t + 3 * tile.plane + kk, fa * Sv[2][kk]);
+                            }
+                        }
+                } else {
+                    for (int i = 0; i < L; ++i)
+                        for (int j = 0; j < L; ++j)
+                            for (int kk = 0; kk < L; ++kk) {
+                                T v0 = T(0), s0 = T(0), v1 = T(0), s1 = T(0), v2 = T(0), s2 = T(0);
+#pragma unroll
+                                for (int t = 0; t < L; ++t) {
+                                    if (t == i) { v0 = V[0][t]; s0 = Sv[0][t]; }
+                                    if (t == j) { v1 = V[1][t]; s1 = Sv[1][t]; }
+                                    if (t == kk) { v2 = V[2][t]; s2 = Sv[2][t]; }
+                                }
+                                const int cidx[3] = {wrap_index(o[0] + i, I.n[0], I.periodic[0]),
+                                                     wrap_index(o[1] + j, I.n[1], I.periodic[1]),
+                                                     wrap_index(o[2] + kk, I.n[2], I.periodic[2])};
+                                const int uidx[3] = {o[0] + i, o[1] + j, o[2] + kk};
+                                const T fa = Lm * v0 * v1;
+                                scatter(uidx, cidx, 0, fa * v2);
+                                scatter(uidx, cidx, 1, Lm * s0 * v1 * v2);
+                                scatter(uidx, cidx, 2, Lm * v0 * s1 * v2);
+                                scatter(uidx, cidx, 3, fa * s2);
+                            }
                 }
             }
             node_theta<D, T>(P, I, tf, trig, idx, Lm, Gz, Hz, gth);
