@@ -1964,7 +1964,21 @@ struct MuTile {
     double *lds;
     int lo[3], ext[3];
     int pitch, plane, total;
+    // reciprocals for the flush's index decoding: floor(n / d) = (n m) >> 32
+    // with m = floor(2^32 / d) + 1, exact while n d < 2^32 (tiles hold fewer
+    // than 2^13 entries)
+    unsigned long long rplane, rpitch, rext1, rlast;
+    int soff, cells;
     bool use;
+
+    __device__ static unsigned long long recip(int d)
+    {
+        return (1ull << 32) / (unsigned long long)d + 1ull;
+    }
+    __device__ static int qdiv(int n, unsigned long long m)
+    {
+        return (int)(((unsigned long long)(unsigned)n * m) >> 32);
+    }
 
     __device__ void init(double *mem, const TileBox &tb)
     {
@@ -1979,6 +1993,12 @@ struct MuTile {
         for (int a = 0; a < D - 1; ++a) plane *= ext[a];
         plane *= pitch;
         total = NF * plane;
+        rplane = recip(plane);
+        rpitch = recip(pitch);
+        rext1 = recip(ext[1] > 0 ? ext[1] : 1);
+        rlast = recip(ext[D - 1]);
+        soff = tb.soff;
+        cells = plane / pitch * ext[D - 1];
     }
 
     __device__ void clear() const
@@ -2018,26 +2038,41 @@ struct MuTile {
         return in ? off : -1;
     }
 
-    // add the tile to mu (node records of stride PS) with global atomics
+    // add the tile to mu (node records of stride PS): with plain stores into
+    // the tile's staging slot (every entry, fields interleaved; k_gather_tiles
+    // sums the slots per node), else with global atomics
     template <int PS>
-    __device__ void flush(const DevInst &I, T *mu) const
+    __device__ void flush(const DevInst &I, T *mu, T *stage) const
     {
         if (!use) return;
+        if (stage != nullptr && soff >= 0) {
+            // slot order (cell, field): consecutive lanes store consecutive words
+            T *slot = stage + soff;
+            for (int k = threadIdx.x; k < cells * NF; k += blockDim.x) {
+                const int c = k / NF, f = k - c * NF;
+                const int row = qdiv(c, rlast), ll = c - row * ext[D - 1];
+                slot[k] = (T)lds[f * plane + row * pitch + ll];
+            }
+            return;
+        }
         for (int e = threadIdx.x; e < total; e += blockDim.x) {
             const T v = (T)lds[e];
             if (v == T(0)) continue;
-            const int f = e / plane;
-            int r = e - f * plane;
-            const int ll = r % pitch;
+            // e = ((f ext0 + l0) ext1 + l1) pitch + ll in 3D, (f ext0 + l0) pitch + ll in 2D
+            const int f = qdiv(e, rplane);
+            const int r = e - f * plane;
+            const int row = qdiv(r, rpitch);
+            const int ll = r - row * pitch;
             if (ll >= ext[D - 1]) continue;
-            r /= pitch;
             // tiles of periodic axes may run past the seam: wrap back onto the grid
             long long o = I.node_off + (long long)wrap_index(lo[D - 1] + ll, I.n[D - 1],
                                                              I.periodic[D - 1]) * I.stride[D - 1];
-            for (int a = D - 2; a >= 0; --a) {
-                const int la = r % ext[a];
-                r /= ext[a];
-                o += (long long)wrap_index(lo[a] + la, I.n[a], I.periodic[a]) * I.stride[a];
+            if constexpr (D == 2) {
+                o += (long long)wrap_index(lo[0] + row, I.n[0], I.periodic[0]) * I.stride[0];
+            } else if constexpr (D == 3) {
+                const int l0 = qdiv(row, rext1), l1 = row - l0 * ext[1];
+                o += (long long)wrap_index(lo[1] + l1, I.n[1], I.periodic[1]) * I.stride[1];
+                o += (long long)wrap_index(lo[0] + l0, I.n[0], I.periodic[0]) * I.stride[0];
             }
             atomicAdd(&mu[o * PS + f], v);
         }
@@ -2060,6 +2095,34 @@ __device__ inline void reduce_theta(double (*red)[kThetaSlots], const double *gt
         double v = 0.0;
         for (int wv = 0; wv < kBlock / 64; ++wv) v += red[wv][threadIdx.x];
         if (v != 0.0) atomicAdd(&grad[inst * kThetaSlots + threadIdx.x], v);
+    }
+}
+
+// mu += the staged tile entries that cover each node (fixed order: the tiles'
+// order in the work lists), after the transposed-step kernels.
+template <typename T, int D>
+__global__ void __launch_bounds__(kBlock) k_gather_tiles(int n_cov, const int *__restrict__ cov_node,
+                                                         const int *__restrict__ cov_ptr,
+                                                         const int *__restrict__ cov_base,
+                                                         const T *__restrict__ stage,
+                                                         T *__restrict__ mu)
+{
+    constexpr int NF = D + 1, PS = RecStride<D>::value;
+    const int stride = gridDim.x * blockDim.x;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n_cov; t += stride) {
+        const long long j = cov_node[t];
+        const int b = cov_ptr[t], e = cov_ptr[t + 1];
+        T acc[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) acc[f] = T(0);
+        for (int k = b; k < e; ++k) {
+            const T *sp = stage + cov_base[k];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) acc[f] += sp[f];
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+            if (acc[f] != T(0)) mu[j * PS + f] += acc[f];
     }
 }
 
@@ -2349,7 +2412,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
             node_theta<D, T>(P, I, tf, trig, idx, Lm, Gz, Hz, gth);
         }
         __syncthreads();
-        tile.template flush<PS>(I, mu);
+        tile.template flush<PS>(I, mu, (T *)P.adj.stage);
         reduce_theta(red, gth, grad, it.inst);
         __syncthreads();
     }
@@ -2496,7 +2559,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
             node_theta<D, T>(P, I, tf, trig, idx, Lm, Gz, Hz, gth);
         }
         __syncthreads();
-        tile.template flush<PS>(I, mu);
+        tile.template flush<PS>(I, mu, (T *)P.adj.stage);
         reduce_theta(red, gth, grad, it.inst);
         __syncthreads();
     }
@@ -2682,7 +2745,7 @@ __global__ void __launch_bounds__(kBlock) k_adjoint_box(
             node_theta<D, T>(P, I, tf, trig, idx, Lm, Gz, Hz, gth);
         }
         __syncthreads();
-        tile.template flush<PS>(I, mu);
+        tile.template flush<PS>(I, mu, (T *)P.adj.stage);
         reduce_theta(red, gth, grad, it.inst);
         __syncthreads();
     }

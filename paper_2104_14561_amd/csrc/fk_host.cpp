@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <array>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -176,6 +177,9 @@ struct fk_plan {
         std::vector<fk::TileBox> fw_tiles, box_tiles;
         int box_work_off[fk::kBoxClasses] = {0}, n_box_work[fk::kBoxClasses] = {0};
         int n_in_work = 0;
+        // tile staging (see stage_tiles)
+        long long stage_entries = 0;
+        std::vector<int> cov_node, cov_ptr, cov_base;
     } adj;
     // forward step lists
     std::vector<int> fw_nodes, box_nodes;
@@ -431,6 +435,88 @@ void add_region(fk_plan *p, const char *name, size_t bytes)
     r.bytes = bytes;
     p->reg[name] = r;
     p->ws_bytes = align_up(p->ws_bytes + std::max<size_t>(bytes, 1));
+}
+
+// Staging of the adjoint's LDS tiles.  Tiles of neighbouring work items
+// overlap (each is its node box widened by the reach), so adding them to mu
+// directly takes device-wide atomics.  Instead every tile that fits LDS gets
+// a slot of its own (entries in row-major tile order, the d + 1 fields of an
+// entry adjacent), written with plain stores, and each node gets the list of
+// slot entries that hold it; k_gather_tiles sums those lists into mu.  Plans
+// whose slots would pass 2^31 entries keep the atomic flush.
+void stage_tiles(fk_plan *p)
+{
+    const int d = p->d, NF = d + 1;
+    auto &A = p->adj;
+    A.stage_entries = 0;
+    A.cov_node.clear();
+    A.cov_ptr.clear();
+    A.cov_base.clear();
+    long long off = 0;
+    auto assign = [&](std::vector<fk::TileBox> &tiles) {
+        for (fk::TileBox &tb : tiles) {
+            tb.soff = -1;
+            if (!tb.use_lds) continue;
+            long long cells = 1;
+            for (int a = 0; a < d; ++a) cells *= tb.ext[a];
+            tb.soff = (int)std::min<long long>(off, INT_MAX);
+            off += cells * NF;
+        }
+    };
+    assign(A.fw_tiles);
+    assign(A.box_tiles);
+    if (off == 0 || off > (long long)INT_MAX || p->n_nodes > (long long)INT_MAX) {
+        for (fk::TileBox &tb : A.fw_tiles) tb.soff = -1;
+        for (fk::TileBox &tb : A.box_tiles) tb.soff = -1;
+        return;
+    }
+    A.stage_entries = off;
+    // each tile entry's packed node (periodic tiles may run past the seam)
+    auto visit = [&](const std::vector<fk::TileBox> &tiles, const std::vector<fk::WorkItem> &work,
+                     auto &&fn) {
+        for (size_t t = 0; t < tiles.size(); ++t) {
+            const fk::TileBox &tb = tiles[t];
+            if (tb.soff < 0) continue;
+            const fk_problem &pr = p->probs[work[t].inst];
+            long long stride[3] = {1, 1, 1};
+            for (int a = d - 2; a >= 0; --a) stride[a] = stride[a + 1] * pr.ax[a + 1].n;
+            const int e0 = tb.ext[0], e1 = d > 1 ? tb.ext[1] : 1, e2 = d > 2 ? tb.ext[2] : 1;
+            int c = 0;
+            for (int l0 = 0; l0 < e0; ++l0)
+                for (int l1 = 0; l1 < e1; ++l1)
+                    for (int l2 = 0; l2 < e2; ++l2, ++c) {
+                        const int l[3] = {l0, l1, l2};
+                        long long node = p->node_off[work[t].inst];
+                        for (int a = 0; a < d; ++a) {
+                            const int n = pr.ax[a].n;
+                            int i = tb.lo[a] + l[a];
+                            if (pr.ax[a].periodic) {
+                                if (i < 0) i += n - 1;
+                                else if (i > n - 1) i -= n - 1;
+                            }
+                            node += (long long)i * stride[a];
+                        }
+                        fn(node, tb.soff + c * NF);
+                    }
+        }
+    };
+    // counting sort by node, then the covered nodes only
+    std::vector<int> cnt((size_t)p->n_nodes + 1, 0);
+    auto count = [&](long long node, int) { ++cnt[(size_t)node + 1]; };
+    visit(A.fw_tiles, A.fw_work, count);
+    visit(A.box_tiles, A.box_work, count);
+    for (size_t j = 0; j < (size_t)p->n_nodes; ++j) cnt[j + 1] += cnt[j];
+    A.cov_base.assign((size_t)cnt[(size_t)p->n_nodes], 0);
+    std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+    auto put = [&](long long node, int base) { A.cov_base[(size_t)fill[(size_t)node]++] = base; };
+    visit(A.fw_tiles, A.fw_work, put);
+    visit(A.box_tiles, A.box_work, put);
+    for (size_t j = 0; j < (size_t)p->n_nodes; ++j)
+        if (cnt[j + 1] > cnt[j]) {
+            A.cov_node.push_back((int)j);
+            A.cov_ptr.push_back(cnt[j]);
+        }
+    A.cov_ptr.push_back(cnt[(size_t)p->n_nodes]);
 }
 
 void build_work(std::vector<fk::WorkItem> &out, int inst, int count, int chunk, int first = 0,
@@ -949,6 +1035,7 @@ fk_status build_plan(fk_plan *p)
             for (const fk::WorkItem &it : p->adj.box_work)
                 // the box kernels index their tiles with unwrapped indices
                 p->adj.box_tiles.push_back(tile_of(it, p->adj.box_nodes, true));
+            stage_tiles(p);
         }
     }
     p->slope_work = tables;
@@ -1131,6 +1218,10 @@ fk_status build_plan(fk_plan *p)
         add_region(p, "lamA", fb);
         add_region(p, "lamB", fb);
         add_region(p, "mu", fb * rec_stride(p->d));
+        add_region(p, "stage", elt(p) * (size_t)std::max<long long>(p->adj.stage_entries, 1));
+        add_region(p, "cov_node", sizeof(int) * std::max<size_t>(p->adj.cov_node.size(), 1));
+        add_region(p, "cov_ptr", sizeof(int) * std::max<size_t>(p->adj.cov_ptr.size(), 1));
+        add_region(p, "cov_base", sizeof(int) * std::max<size_t>(p->adj.cov_base.size(), 1));
         add_region(p, "grad", sizeof(double) * fk::kThetaSlots * p->n_inst);
         add_region(p, "ckpt", fb * p->n_ckpt);
         add_region(p, "seg", fb * std::max(1, std::min(K, p->N) - 1));   // recomputed fields
@@ -1184,6 +1275,12 @@ void fill_dev(fk_plan *p)
     D.adj.box_nodes = (const int *)p->at("abox_nodes");
     D.adj.box_work = (const fk::WorkItem *)p->at("abox_work");
     D.adj.box_tiles = (const fk::TileBox *)p->at("abox_tiles");
+    const bool staged = p->opt.ckpt_every > 0 && p->adj.stage_entries > 0;
+    D.adj.stage = staged ? p->at("stage") : nullptr;
+    D.adj.n_cov = staged ? (int)p->adj.cov_node.size() : 0;
+    D.adj.cov_node = staged ? (const int *)p->at("cov_node") : nullptr;
+    D.adj.cov_ptr = staged ? (const int *)p->at("cov_ptr") : nullptr;
+    D.adj.cov_base = staged ? (const int *)p->at("cov_base") : nullptr;
     for (int c2 = 0; c2 < fk::kBoxClasses; ++c2) {
         D.adj.box_work_off[c2] = p->adj.box_work_off[c2];
         D.adj.n_box_work[c2] = p->adj.n_box_work[c2];
@@ -1694,6 +1791,11 @@ fk_status upload_tables(fk_plan *p, hipStream_t s)
     FK_TRY(up("abox_nodes", p->adj.box_nodes.data(), sizeof(int) * p->adj.box_nodes.size()));
     FK_TRY(up("abox_work", p->adj.box_work.data(), sizeof(fk::WorkItem) * p->adj.box_work.size()));
     FK_TRY(up("abox_tiles", p->adj.box_tiles.data(), sizeof(fk::TileBox) * p->adj.box_tiles.size()));
+    if (p->opt.ckpt_every > 0 && p->adj.stage_entries > 0) {
+        FK_TRY(up("cov_node", p->adj.cov_node.data(), sizeof(int) * p->adj.cov_node.size()));
+        FK_TRY(up("cov_ptr", p->adj.cov_ptr.data(), sizeof(int) * p->adj.cov_ptr.size()));
+        FK_TRY(up("cov_base", p->adj.cov_base.data(), sizeof(int) * p->adj.cov_base.size()));
+    }
     FK_TRY(up("fw_nodes", p->fw_nodes.data(), sizeof(int) * p->fw_nodes.size()));
     FK_TRY(up("fw_work", p->fw_work.data(), sizeof(fk::WorkItem) * p->fw_work.size()));
     FK_TRY(up("fw_split_work", p->fw_split_work.data(), sizeof(fk::WorkItem) * p->fw_split_work.size()));

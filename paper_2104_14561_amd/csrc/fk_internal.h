@@ -69,6 +69,7 @@ struct TileBox {
     int ext[kMaxDim];
     int use_lds;
     int pad;
+    int soff;   // first entry of the tile's staging slot, or -1 (flush with atomics)
 };
 
 // The adjoint's work lists: active nodes handled per landing point (fw) and
@@ -83,6 +84,13 @@ struct AdjLists {
     // the first n_in_work items: no landing point of any of their nodes can exit
     int n_in_work;
     int in_grid;
+    // tile staging: each tile's entries (fields interleaved) at its soff; per
+    // node the staging entries (field 0) of the tiles that cover it
+    void *stage;                // T, or null when the tiles flush with atomics
+    int n_cov;                  // nodes covered by a staged tile
+    const int *cov_node;        // [n_cov] packed node index
+    const int *cov_ptr;         // [n_cov + 1] into cov_base
+    const int *cov_base;        // staging index of field 0, per (node, covering tile)
     const int *box_nodes;
     const WorkItem *box_work;
     const TileBox *box_tiles;

@@ -228,7 +228,15 @@ hipError_t launch_adjoint_step(const PlanDev &P0, bool f32, int n, const void *p
         case 3: ok = f32 ? adjoint_node_f32_d3(P, n, packed, lam, mu, grad, s) : adjoint_node_f64_d3(P, n, packed, lam, mu, grad, s); break;
         default: return hipErrorInvalidValue;
         }
-        if (ok) return hipGetLastError();
+        if (ok) {
+            // the staged tiles into mu, once both lists have run
+            if (part != 1 && P.adj.stage) {
+                FK_DISPATCH_D(P.d,
+                    if (f32) k_gather_tiles<float, D><<<flat_grid(P.adj.n_cov), kBlock, 0, s>>>(P.adj.n_cov, P.adj.cov_node, P.adj.cov_ptr, P.adj.cov_base, (const float *)P.adj.stage, (float *)mu);
+                    else k_gather_tiles<double, D><<<flat_grid(P.adj.n_cov), kBlock, 0, s>>>(P.adj.n_cov, P.adj.cov_node, P.adj.cov_ptr, P.adj.cov_base, (const double *)P.adj.stage, (double *)mu));
+            }
+            return hipGetLastError();
+        }
     }
     if (part == 2) return hipSuccess;   // the lane-group form has no separate box part
     const PlanDev &P = P0;
