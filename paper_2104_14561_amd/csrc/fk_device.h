@@ -1401,6 +1401,18 @@ struct alignas(16) EllBlock {
     T v[K];
 };
 
+// Store a block past the caches' allocation (the values are read back by the
+// product only after the whole operator, gigabytes, has been written).
+template <typename T>
+__device__ inline void store_block_nt(EllBlock<T> *dst, const EllBlock<T> &b)
+{
+    using V = T __attribute__((ext_vector_type(EllBlock<T>::K)));
+    V x;
+#pragma unroll
+    for (int j = 0; j < EllBlock<T>::K; ++j) x[j] = b.v[j];
+    __builtin_nontemporal_store(x, reinterpret_cast<V *>(dst));
+}
+
 template <typename T, int D, int G>
 __global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n,
                                                          const WorkItem *__restrict__ work,
@@ -1523,50 +1535,65 @@ __global__ void __launch_bounds__(kBlock) k_assemble_ell(PlanDev P, int n,
     }
 }
 
+// floor(n / d) for 0 <= n, d < 2^16 as a multiply-high: m = floor(2^32 / d) + 1
+// makes (n m) >> 32 exact while n d < 2^32.
+__device__ inline unsigned long long fast_recip(int d)
+{
+    return (1ull << 32) / (unsigned long long)d + 1ull;
+}
+__device__ inline int fast_div(int n, unsigned long long m)
+{
+    return (int)(((unsigned long long)(unsigned)n * m) >> 32);
+}
+
 // Assembly of separable rows (no landing point can reach a curved exit
 // boundary; exits through the faces of a box region decide per axis): the
 // row is the outer product of per-axis vectors, the value and slope bases of
 // that axis summed with its 1D weights over the GH nodes that stay inside, so
-// it is written directly, with no LDS atomics.  One thread per row builds its
-// vectors in LDS (thread-minor, conflict-free), then writes its 16-byte
-// blocks: a wave's stores of one block index are 1 KB in one piece.  The exit
-// mass is accumulated axis by axis, exactly 0 when nothing leaves.
+// it is written directly, with no LDS atomics.  A workgroup takes up to 64
+// rows (a lane per row); wave a builds the rows' axis-a vectors in LDS
+// (thread-minor, conflict-free), then the four waves share the rows' 16-byte
+// blocks (wave w: block indices w, w + 4, ..), so that a wave's stores of one
+// block index are 1 KB in one piece and four waves keep stores in flight per
+// set of vectors.  The exit mass is accumulated axis by axis, exactly 0 when
+// nothing leaves.
 template <typename T, int D>
-__global__ void __launch_bounds__(64) k_assemble_ell_sep(PlanDev P, int n,
-                                                         const WorkItem *__restrict__ work,
-                                                         int n_work, int lmax,
-                                                         int *__restrict__ org,
-                                                         T *__restrict__ vals,
-                                                         T *__restrict__ exit_mass)
+__global__ void __launch_bounds__(256) k_assemble_ell_sep(PlanDev P, int n,
+                                                          const WorkItem *__restrict__ work,
+                                                          int n_work, int lmax,
+                                                          int *__restrict__ org,
+                                                          T *__restrict__ vals,
+                                                          T *__restrict__ exit_mass)
 {
     constexpr int K = EllBlock<T>::K;
     using B = EllBlock<T>;
     extern __shared__ unsigned char smem_raw[];
     T *vec = reinterpret_cast<T *>(smem_raw);   // [D][value, slope][lmax][64]
+    __shared__ T mass[2][3][64];                // per axis: inside, outside weight
+    __shared__ int orgs[3][64];
     const T *w1 = weights1<T>(P);
-    const int t = threadIdx.x;
+    const int t = threadIdx.x % 64, wv = threadIdx.x / 64;
     auto V = [&](int a, int v, int l) -> T & { return vec[((a * 2 + v) * lmax + l) * 64 + t]; };
     const WorkRange wr = work_range(0, n_work);
     for (int w = wr.begin; w < wr.end; w += wr.step) {
         const WorkItem it = work[w];
-        if (t >= it.count) continue;   // rows are independent: no barrier below
         const DevInst &I = P.inst[it.inst];
+        const bool valid = t < it.count;
         const long long r = it.first + t;   // row within the instance
         const long long row = I.act_off + r;
-        const int node = P.active[row];
-        int idx[3];
-        split_node<D>(I, node, idx);
-        double c[3];
-        node_centre<D>(I, P.coords, time_factors(P, n, it.inst), P.trig, idx, P.dt, c);
-        int origin[3] = {0, 0, 0};
-        T em = T(0), in_all = T(1);
-        for (int a = 0; a < D; ++a) {
+        if (wv < D && valid) {
+            const int a = wv;
+            const int node = P.active[row];
+            int idx[3];
+            split_node<D>(I, node, idx);
+            double c[3];
+            node_centre<D>(I, P.coords, time_factors(P, n, it.inst), P.trig, idx, P.dt, c);
             const int L = I.ell_box[a];
             for (int l = 0; l < L; ++l) {
                 V(a, 0, l) = T(0);
                 V(a, 1, l) = T(0);
             }
-            origin[a] = eval_axis(I, P.coords, a, c[a], P.gh_a[0]).k;
+            const int origin = eval_axis(I, P.coords, a, c[a], P.gh_a[0]).k;
             T in_a = T(0), out_a = T(0);
             for (int q = 0; q < P.qs; ++q) {
                 const AxisEval e = eval_axis(I, P.coords, a, c[a], P.gh_a[q]);
@@ -1575,7 +1602,7 @@ __global__ void __launch_bounds__(64) k_assemble_ell_sep(PlanDev P, int n,
                     out_a += wq;
                     continue;
                 }
-                const int l = e.k - origin[a];
+                const int l = e.k - origin;
                 if (l < 0 || l + 1 >= L) {
                     atomicOr(P.flags, 2);
                     continue;
@@ -1587,22 +1614,43 @@ __global__ void __launch_bounds__(64) k_assemble_ell_sep(PlanDev P, int n,
                 V(a, 1, l + 1) += wq * Bq.d1;
                 in_a += wq;
             }
-            // mass of the tensor points with some axis outside, over axes 0..a
-            em = em * (in_a + out_a) + in_all * out_a;
-            in_all *= in_a;
+            mass[0][a][t] = in_a;
+            mass[1][a][t] = out_a;
+            orgs[a][t] = origin;
         }
-        for (int a = 0; a < 3; ++a) org[row * 3 + a] = a < D ? origin[a] : 0;
-        exit_mass[row] = em;
-        // blocks: field f (0 value, 1 + a slope along a), K box nodes each,
-        // box nodes in order with the last axis fastest; padding nodes hold 0
-        const int nbox = I.ell_w / (D + 1);
-        const int bpf = I.ell_nbp / K;
-        const long long rows = I.n_act;
-        B *dst = reinterpret_cast<B *>(vals + I.ell_off) + r;
-        for (int f = 0; f <= D; ++f) {
-            int li[3] = {0, 0, 0};
-            int l = 0;
-            for (int lb = 0; lb < bpf; ++lb) {
+        __syncthreads();
+        if (valid) {
+            if (wv == 0) {
+                // mass of the tensor points with some axis outside, over axes 0..a
+                T em = T(0), in_all = T(1);
+                for (int a = 0; a < D; ++a) {
+                    em = em * (mass[0][a][t] + mass[1][a][t]) + in_all * mass[1][a][t];
+                    in_all *= mass[0][a][t];
+                }
+                for (int a = 0; a < 3; ++a) org[row * 3 + a] = a < D ? orgs[a][t] : 0;
+                exit_mass[row] = em;
+            }
+            // blocks: field f (0 value, 1 + a slope along a), K box nodes each,
+            // box nodes in order with the last axis fastest; padding nodes hold 0
+            const int nbox = I.ell_w / (D + 1);
+            const int bpf = I.ell_nbp / K;
+            const long long rows = I.n_act;
+            unsigned long long rb[3];
+            for (int a = 0; a < D; ++a) rb[a] = fast_recip(I.ell_box[a]);
+            B *dst = reinterpret_cast<B *>(vals + I.ell_off) + r;
+            const int nblk = (D + 1) * bpf;
+            for (int g = wv; g < nblk; g += 4) {
+                const int f = g / bpf, lb = g - f * bpf;
+                int l = lb * K;
+                int li[3] = {0, 0, 0};
+                {
+                    int rem = l;
+                    for (int a = D - 1; a >= 0; --a) {
+                        const int q = fast_div(rem, rb[a]);
+                        li[a] = rem - q * I.ell_box[a];
+                        rem = q;
+                    }
+                }
                 B blk;
 #pragma unroll
                 for (int j = 0; j < K; ++j, ++l) {
@@ -1617,9 +1665,10 @@ __global__ void __launch_bounds__(64) k_assemble_ell_sep(PlanDev P, int n,
                     }
                     blk.v[j] = v;
                 }
-                dst[((long long)f * bpf + lb) * rows] = blk;
+                store_block_nt(dst + (long long)g * rows, blk);
             }
         }
+        __syncthreads();   // the vectors are rebuilt for the next work item
     }
 }
 

@@ -1254,7 +1254,7 @@ void fill_dev(fk_plan *p)
         D.ell_sep_off[c] = p->ell_sep_off[c];
         D.ell_sep_n[c] = p->ell_sep_n[c];
         D.ell_sep_l[c] = p->ell_sep_l[c];
-        D.ell_sep_grid[c] = grid_for(p->ell_sep_n[c], 32);   // 64-thread workgroups
+        D.ell_sep_grid[c] = grid_for(p->ell_sep_n[c]);   // 256 threads share 64 rows
     }
     D.n_ell_cls = p->n_ell_cls;
     for (int c = 0; c < fk::kEllClasses; ++c) {

@@ -142,8 +142,8 @@ hipError_t launch_assemble_ell(const PlanDev &P, bool f32, int n, int *org, void
         const int nw = P.ell_sep_n[c], lm = P.ell_sep_l[c], grid = P.ell_sep_grid[c];
         const size_t lds = (size_t)P.d * 2 * lm * 64 * (f32 ? sizeof(float) : sizeof(double));
         FK_DISPATCH_D(P.d,
-            if (f32) k_assemble_ell_sep<float, D><<<grid, 64, lds, s>>>(P, n, work, nw, lm, org, (float *)vals, (float *)exit_mass);
-            else k_assemble_ell_sep<double, D><<<grid, 64, lds, s>>>(P, n, work, nw, lm, org, (double *)vals, (double *)exit_mass));
+            if (f32) k_assemble_ell_sep<float, D><<<grid, 256, lds, s>>>(P, n, work, nw, lm, org, (float *)vals, (float *)exit_mass);
+            else k_assemble_ell_sep<double, D><<<grid, 256, lds, s>>>(P, n, work, nw, lm, org, (double *)vals, (double *)exit_mass));
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
