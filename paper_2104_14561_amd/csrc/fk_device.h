@@ -2553,7 +2553,11 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(siz
                     const bool lo = l0[q] == i, hi = l0[q] + 1 == i;
                     if (!in0[q] || !(lo || hi)) continue;
                     hit = true;
-                    const Basis<T> B = hermite<T>(s0[q], h0), Bz = hermite_dz<T>(s0[q], h0);
+                    // the bases depend on q only: rebuilt per row rather than hoisted
+                    // out of the row loop for every q at once (registers)
+                    T sq = s0[q];
+                    asm volatile("" : "+v"(sq));
+                    const Basis<T> B = hermite<T>(sq, h0), Bz = hermite_dz<T>(sq, h0);
                     const T wq = w1[q], wa = wq * (T)ga[q];
                     v0 += wq * (lo ? B.v0 : B.v1);
                     sv0 += wq * (lo ? B.d0 : B.d1);
