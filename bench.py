@@ -130,11 +130,15 @@ def traffic_table():
     return t["kernels"]
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernels):
+    """Calibrated HBM bytes of one launch of each named kernel, summed (the
+    kernels one timed group launches once each), or None."""
     t = traffic_table()
-    if not t or kernel not in t:
+    if isinstance(kernels, str):
+        kernels = [kernels]
+    if not t or any(k not in t for k in kernels):
         return None
-    return t[kernel]["fetch_bytes_per_launch"] + t[kernel]["write_bytes_per_launch"]
+    return sum(t[k]["fetch_bytes_per_launch"] + t[k]["write_bytes_per_launch"] for k in kernels)
 
 
 def disc_mean_weights(probs, dtype, device):
@@ -463,12 +467,14 @@ def main():
             "frac": round(rate / peak, 4),
             "note": "lane-level ds_add_f64; peak from fk_probe_lds_atomics (2048 x 256 lanes, "
                     "conflict-free) on this device, this run"}
-        kname = "void k_adjoint_node<float, 2, 8, true>"
+        # interior work items (no exit tests) and the rest: one launch each
+        kname = ["void k_adjoint_node<float, 2, 8, true, true>",
+                 "void k_adjoint_node<float, 2, 8, true, false>"]
         share = t_adj_kernel / ms_step
     else:
         ms_k = prof_f["step_fused"][0]
         roof = scope_roofline(d, Q, Ja, ms_k, 1, plan.precision, "k_step_node (fused step)")
-        kname = "void k_step_node<float, 2, 8, 1, true>"
+        kname = "void k_step_node<float, 2, 8, 1, true, false>"
         share = t_step_kernel / ms_step
     roof["traffic"] = measured_traffic(kname)
     roof["share_of_step"] = round(share, 4)
