@@ -110,9 +110,13 @@ enum { FK_PREC_F64 = 0, FK_PREC_F32 = 1 };
  * FK_HERMITE_R2: also the mixed derivatives, the twist field of an axis set
  * composed from the one-dimensional rule in increasing axis order
  * (u_xy = D_y(D_x u)); exact on tensor products of cubics given exact fields.
- * R2 is built for d <= 2 (1D: the same as R1), the fused form and the
- * forward pass (fk_forward, fk_forward_from, fk_step, fk_forward_horizons);
- * other combinations are FK_ERR_UNSUPPORTED. */
+ * In 3D the four twist fields (axis sets {0,1}, {0,2}, {1,2}, {0,1,2}) sit in
+ * a second record per node in the workspace.  R2 is built for d = 1 (the
+ * same as R1), 2 and 3, the fused form and the forward pass (fk_forward,
+ * fk_forward_from, fk_step, fk_forward_horizons); in 3D with the
+ * thread-per-node step only (fk_options.step_kernel 0, 1 or 3; a gh_q with
+ * such a kernel compiled) and exit-1 faces.  Other combinations are
+ * FK_ERR_UNSUPPORTED. */
 enum { FK_HERMITE_R1 = 0, FK_HERMITE_R2 = 1 };
 
 /* FK_FORM_FUSED: matrix-free step (landing, weights and contraction in one

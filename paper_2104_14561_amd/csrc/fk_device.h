@@ -567,6 +567,36 @@ __device__ inline T hermite_value(const R *p, const Basis<T> *B, T uref)
     }
 }
 
+// The R2 interpolant in 3D: corner records p (u, g0, g1, g2) and q (t01, t02,
+// t12, t012), corners [(a*2 + b)*2 + c]; the field of axis set S weighted by
+// the slope bases of S and the value bases of the other axes.
+template <typename T, typename R>
+__device__ inline T hermite_value3_tw(const R *p, const R *q, const Basis<T> *B, T uref)
+{
+    const Basis<T> &X = B[0], &Y = B[1], &Z = B[2];
+    T acc = T(0);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const T Zv = c ? Z.v1 : Z.v0, Zd = c ? Z.d1 : Z.d0;
+        T sv = T(0), sd = T(0);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const T Yv = b ? Y.v1 : Y.v0, Yd = b ? Y.d1 : Y.d0;
+            const int k0 = (0 * 2 + b) * 2 + c, k1 = (1 * 2 + b) * 2 + c;
+            const R &p0 = p[k0], &p1 = p[k1], &q0 = q[k0], &q1 = q[k1];
+            // fields with S restricted to axis 0 given the (axis 1, axis 2) part
+            const T x00 = (p0.x - uref) * X.v0 + (p1.x - uref) * X.v1 + p0.y * X.d0 + p1.y * X.d1;
+            const T x10 = p0.z * X.v0 + p1.z * X.v1 + q0.x * X.d0 + q1.x * X.d1;   // g1, t01
+            const T x01 = p0.w * X.v0 + p1.w * X.v1 + q0.y * X.d0 + q1.y * X.d1;   // g2, t02
+            const T x11 = q0.z * X.v0 + q1.z * X.v1 + q0.w * X.d0 + q1.w * X.d1;   // t12, t012
+            sv += Yv * x00 + Yd * x10;
+            sd += Yv * x01 + Yd * x11;
+        }
+        acc += Zv * sv + Zd * sd;
+    }
+    return acc;
+}
+
 // Gradient of the Hermite value with respect to z (adjoint); Bz = hermite_dz.
 template <typename T, int D, typename R>
 __device__ inline void hermite_grad(const R *p, const Basis<T> *B, const Basis<T> *Bz, T *g)
@@ -727,6 +757,41 @@ __device__ inline T twist_2d(const DevInst &I, const double *coords, const T *ui
     return pchip_slope<T>((gc - gl) / (T)hl1, (gr - gc) / (T)hr1);
 }
 
+// R2 twist fields in 3D at node idx: t01 = D_1(D_0 u), t02 = D_2(D_0 u),
+// t12 = D_2(D_1 u), t012 = D_2(t01) -- each the PCHIP slope along the largest
+// axis of its set of the field of the set without that axis, the lower fields
+// recomputed at the stencil nodes with the same rule.
+template <typename T>
+__device__ inline void twist_3d(const DevInst &I, const double *coords, const T *ui, const int *idx,
+                                T *tw)
+{
+    int l[3][3];
+    double hl[3], hr[3];
+    for (int a = 0; a < 3; ++a) slope_stencil(I, coords, a, idx[a], l[a][0], l[a][1], l[a][2], hl[a], hr[a]);
+    const long long s0 = I.stride[0], s1 = I.stride[1];
+    auto at = [&](int i0, int i1, int i2) -> T { return ui[i0 * s0 + i1 * s1 + i2]; };
+    // slope along axis 0 at (i0 = idx0's stencil, i1, i2)
+    auto g0 = [&](int i1, int i2) -> T {
+        const T ul = at(l[0][0], i1, i2), uc = at(l[0][1], i1, i2), ur = at(l[0][2], i1, i2);
+        return pchip_slope<T>((uc - ul) / (T)hl[0], (ur - uc) / (T)hr[0]);
+    };
+    auto g1 = [&](int i2) -> T {
+        const T ul = at(idx[0], l[1][0], i2), uc = at(idx[0], l[1][1], i2), ur = at(idx[0], l[1][2], i2);
+        return pchip_slope<T>((uc - ul) / (T)hl[1], (ur - uc) / (T)hr[1]);
+    };
+    auto t01 = [&](int i2) -> T {
+        const T gl = g0(l[1][0], i2), gc = g0(l[1][1], i2), gr = g0(l[1][2], i2);
+        return pchip_slope<T>((gc - gl) / (T)hl[1], (gr - gc) / (T)hr[1]);
+    };
+    auto along2 = [&](T fl, T fc, T fr) -> T {
+        return pchip_slope<T>((fc - fl) / (T)hl[2], (fr - fc) / (T)hr[2]);
+    };
+    tw[0] = t01(idx[2]);
+    tw[1] = along2(g0(idx[1], l[2][0]), g0(idx[1], l[2][1]), g0(idx[1], l[2][2]));
+    tw[2] = along2(g1(l[2][0]), g1(l[2][1]), g1(l[2][2]));
+    tw[3] = along2(t01(l[2][0]), t01(l[2][1]), t01(l[2][2]));
+}
+
 // Slope pass for step n over work items [first, first + count): table items
 // (kind 1 + a) fill the (sin, cos) table of axis a; node items (kind 0) write
 // record[node] = (u, g_0, .., g_{d-1}).
@@ -792,6 +857,15 @@ __global__ void __launch_bounds__(kBlock) k_slopes(PlanDev P, int n, int first, 
             // R2 twist: the PCHIP slope along axis 1 of the axis-0 slope field
             // (the one-dimensional rule composed in increasing axis order)
             if (P.hermite2) out[3] = twist_2d<T>(I, P.coords, ui, idx);
+        } else if constexpr (D == 3) {
+            // R2: the four twist fields in the node's second record
+            if (P.hermite2) {
+                T tw[4];
+                twist_3d<T>(I, P.coords, ui, idx, tw);
+                R q;
+                q.x = tw[0]; q.y = tw[1]; q.z = tw[2]; q.w = tw[3];
+                reinterpret_cast<R *>(P.packed2)[I.node_off + node] = q;
+            }
         }
         R r;
         if constexpr (PS == 2) {
@@ -1109,7 +1183,21 @@ __global__ void __launch_bounds__(kBlock) k_step_node(
                             }
                         const Basis<T> Z = {bin[q2][0], bin[q2][1], bin[q2][2], bin[q2][3]};
                         const Basis<T> B[3] = {X, Y, Z};
-                        part += w1[q2] * hermite_value<T, 3, R>(p, B, uref);
+                        if constexpr (TW) {
+                            // R2: the corners' twist records
+                            const R *rec2 = reinterpret_cast<const R *>(P.packed2);
+                            R qq[8];
+#pragma unroll
+                            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                                for (int bb = 0; bb < 2; ++bb) {
+                                    qq[(a * 2 + bb) * 2 + 0] = rec2[b + a * s0 + bb * s1];
+                                    qq[(a * 2 + bb) * 2 + 1] = rec2[b + a * s0 + bb * s1 + 1];
+                                }
+                            part += w1[q2] * hermite_value3_tw<T, R>(p, qq, B, uref);
+                        } else {
+                            part += w1[q2] * hermite_value<T, 3, R>(p, B, uref);
+                        }
                     }
                     acc += w01 * part;
                     emass += w01 * pex;

@@ -839,7 +839,10 @@ fk_status build_plan(fk_plan *p)
         // the separable form by default in 3D only: there a node's Q*^3
         // points gather 8 corners each, against L^3 records of its footprint;
         // in 2D (Q*^2 points x 4 corners vs L^2) the per-point gather is faster
-        p->use_box = node_ok && affine && !p->faces && fk::box_compiled(p->d, p->qs) &&
+        // the R2 interpolant in 3D: thread-per-node kernels only (the 2D box
+        // and lane-group forms carry the 2D twist)
+        const bool r2 = p->opt.hermite == FK_HERMITE_R2 && p->d == 3;
+        p->use_box = node_ok && affine && !p->faces && !r2 && fk::box_compiled(p->d, p->qs) &&
                      (sk == 4 || (sk == 0 && large && p->d == 3));
         const int gs = std::max(2, group_of(p->qs));
         std::vector<std::vector<fk::WorkItem>> bw(fk::kBoxClasses);
@@ -1204,6 +1207,7 @@ fk_status build_plan(fk_plan *p)
     add_region(p, "uA", fb);
     add_region(p, "uB", fb);
     add_region(p, "packed", fb * rec_stride(p->d));
+    if (p->opt.hermite == FK_HERMITE_R2 && p->d == 3) add_region(p, "packed2", fb * 4);
     if (p->opt.form == FK_FORM_ELL) {
         const int nc = std::max(1, std::min(4, p->opt.columns));
         add_region(p, "packed_mc", fb * rec_stride(p->d) * nc);
@@ -1316,7 +1320,8 @@ void fill_dev(fk_plan *p)
     D.n_steps = p->N;
     D.block = kBlock;
     D.group = p->G;
-    D.hermite2 = (p->opt.hermite == FK_HERMITE_R2 && p->d == 2) ? 1 : 0;
+    D.hermite2 = (p->opt.hermite == FK_HERMITE_R2 && p->d >= 2) ? 1 : 0;
+    D.packed2 = (p->opt.hermite == FK_HERMITE_R2 && p->d == 3) ? p->at("packed2") : nullptr;
     D.faces = p->faces ? 1 : 0;
     D.all_affine = 1;
     for (const fk::DevInst &I : p->inst)
@@ -1575,8 +1580,22 @@ fk_status fk_plan_create(const fk_problem *probs, int n_inst, const fk_options *
     if (o.hermite != FK_HERMITE_R1 && o.hermite != FK_HERMITE_R2)
         return fail(FK_ERR_ARG, "hermite must be FK_HERMITE_R1 or FK_HERMITE_R2");
     if (o.hermite == FK_HERMITE_R2) {
-        if (probs[0].d > 2) return fail(FK_ERR_UNSUPPORTED, "the R2 interpolant is built for d <= 2");
         if (o.form != FK_FORM_FUSED) return fail(FK_ERR_UNSUPPORTED, "the R2 interpolant needs the fused form");
+        if (probs[0].d == 3) {
+            // 3D: the twist records are read by the thread-per-node step only
+            if (!fk::step_node_compiled(3, probs[0].gh_q))
+                return fail(FK_ERR_UNSUPPORTED, "the 3D R2 interpolant needs a thread-per-node "
+                            "kernel for gh_q=%d", probs[0].gh_q);
+            if (o.step_kernel == 2 || o.step_kernel == 4)
+                return fail(FK_ERR_UNSUPPORTED, "the 3D R2 interpolant runs in the "
+                            "thread-per-node step");
+            for (int i = 0; i < n_inst; ++i)
+                for (int a = 0; a < 3; ++a)
+                    if (probs[i].face[a][0] != FK_FACE_EXIT1 || probs[i].face[a][1] != FK_FACE_EXIT1 ||
+                        probs[i].coef_kind == FK_COEF_RUNAWAY3D)
+                        return fail(FK_ERR_UNSUPPORTED, "instance %d: the 3D R2 interpolant takes "
+                                    "exit-1 faces only", i);
+        }
         if (o.ckpt_every > 0) return fail(FK_ERR_UNSUPPORTED, "no adjoint of the R2 interpolant");
     }
     if ((o.step_kernel == 1 || o.step_kernel == 3 || o.step_kernel == 4) &&

@@ -131,7 +131,9 @@ struct PlanDev {
     int group;                  // lanes per active node in the step passes
     int step_kind;              // 0: thread per node, 1: lane group, 2: split node
     int all_affine;             // every axis of every instance is affine
-    int hermite2;               // R2 interpolant (2D): twist field in the records
+    int hermite2;               // R2 interpolant: 2D twist field in the records' fourth entry,
+                                // 3D twist fields in a second record per node (packed2)
+    void *packed2;              // 3D R2: (t01, t02, t12, t012) per node, or null
     int faces;                  // face kinds other than exit-1, or node-dependent diffusion
     // forward step work: nodes handled per landing point (fw) and separable
     // nodes handled in box form, by box class

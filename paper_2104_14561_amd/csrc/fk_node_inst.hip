@@ -43,7 +43,7 @@ void step_node_launch(const PlanDev &P, int n, const void *packed, void *u_out, 
         P, n, nw_, P.inst, wl_, P.fw_nodes, P.trig, P.coords, (const T *)packed, (T *)u_out)
 #define FK_NODE(G_, AFF_, grid_, nw_, wl_)                                                     \
     do {                                                                                       \
-        if constexpr (D == 2) {                                                                \
+        if constexpr (D >= 2) {                                                                \
             if (P.hermite2) { FK_NODE_TW(G_, AFF_, true, grid_, nw_, wl_); break; }            \
         }                                                                                      \
         FK_NODE_TW(G_, AFF_, false, grid_, nw_, wl_);                                          \

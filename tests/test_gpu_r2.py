@@ -1,9 +1,11 @@
 """The R2 interpolant (full tensor cubic Hermite with the PCHIP-composed
-twist field, Section 3.1.2) on the GPU against the oracle's R2: fields of
+twist fields, Section 3.1.2) on the GPU against the oracle's R2: fields of
 the time-dependent cellular flow (disc exit) and of the paper's periodic
 roll flow, FP64 within 1e-12 and FP32 within 1e-5, every 2D step layout;
-R2 and R1 differ by far more than that (the twist enters); Algorithm 1 with
-R2; the combinations outside what is built are refused."""
+in 3D the ABC flow (periodic x, y) with its four twist fields, both
+thread-per-node layouts; R2 and R1 differ by far more than the bars (the
+twists enter); Algorithm 1 with R2; the combinations outside what is built
+are refused."""
 from __future__ import annotations
 
 import numpy as np
@@ -48,6 +50,48 @@ def test_r2_fields_match_oracle(name, prec, kernel):
     assert gap > 10 * TOL[prec]
 
 
+def _abc_r2():
+    # a coarse grid and a step long enough that landing points sit well
+    # inside their cells, where the twist terms matter
+    return W.abc3d(n=17, D=1e-2, dt=0.05, n_steps=8).replace(hermite="r2")
+
+
+@pytest.mark.parametrize("kernel", ["node", "split"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_r2_3d_fields_match_oracle(prec, kernel):
+    prob = _abc_r2()
+    snaps = [prob.n_steps, 3, 0]
+    ref = oracle.solve(prob, snaps=snaps)
+    plan = Plan(prob, precision=prec, step_kernel=kernel, hermite="r2", use_graph=True)
+    got = plan.split(plan.forward(snaps))[0].double().cpu().numpy()
+    torch.cuda.synchronize()
+    assert plan.check_flags() == 0
+    plan.close()
+    err = float(np.abs(got - ref).max())
+    r1 = oracle.solve(prob.replace(hermite="r1"), snaps=[0])[0]
+    gap = float(np.abs(ref[-1] - r1).max())
+    print(f"R2 abc3d {prec} {kernel}: max|gpu - oracle| {err:.3e} (R2 - R1: {gap:.2e})")
+    assert err <= TOL[prec]
+    assert gap > 10 * TOL[prec]
+
+
+def test_r2_3d_batched_uneven_and_single_step():
+    a = _abc_r2()
+    b = W.abc3d(n=13, D=2e-2, dt=0.05, n_steps=8).replace(hermite="r2")
+    plan = Plan([a, b], precision="f64", hermite="r2")
+    got = plan.split(plan.forward([0]))
+    torch.cuda.synchronize()
+    for g, p in zip(got, (a, b)):
+        assert np.abs(g[0].cpu().numpy() - oracle.solve(p, snaps=[0])[0]).max() <= 1e-12
+    plan.close()
+    u = W.random_field(a.shape, seed=5)
+    plan = Plan(a, precision="f64", hermite="r2")
+    got = plan.step(2, torch.from_numpy(u.reshape(-1))).cpu().numpy().reshape(a.shape)
+    torch.cuda.synchronize()
+    plan.close()
+    assert np.abs(got - oracle.step(a, 2, u)).max() <= 1e-12
+
+
 def test_r2_horizons_match_oracle():
     prob = _cases()["cell2d"]
     hz = [40, 9, 25]
@@ -73,5 +117,7 @@ def test_r2_refused_outside_what_is_built():
     for kw in ({"form": "ell"}, {"ckpt_every": 4}):
         with pytest.raises(FkError, match="FK_ERR_UNSUPPORTED"):
             Plan(c, hermite="r2", **kw)
-    with pytest.raises(FkError, match="FK_ERR_UNSUPPORTED"):
-        Plan(W.abc3d(n=9, n_steps=2), hermite="r2")
+    # 3D: the twist records are read by the thread-per-node step only
+    for kernel in ("group", "box"):
+        with pytest.raises(FkError, match="FK_ERR_UNSUPPORTED"):
+            Plan(W.abc3d(n=9, n_steps=2).replace(hermite="r2"), hermite="r2", step_kernel=kernel)
