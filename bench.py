@@ -337,6 +337,44 @@ def algorithm1_leg(stream, log):
     return out
 
 
+def extra_rows_leg(stream, log):
+    """The forward pass of the extensions, each on its own workload: the
+    paper's 2D roll-flow example (Section 4.2), the R2 interpolant against R1
+    (2D cellular flow 513x257, 3D ABC flow 65^3), and the runaway-electron
+    model (Section 4.3: exit-0 / exit-1 / reflecting faces, drift and
+    diffusion per node, the non-uniform radial grid).  Whole-pass time and
+    grid-point-steps/s, and the fused step's mean launch time."""
+    import torch
+    from paper_2104_14561_amd import Plan
+    cases = [
+        ("paper2d_rolls", W.paper2d(), {}, ("f64", "f32")),
+        ("cell2d_513x257_r1", W.cell2d(), {}, ("f32",)),
+        ("cell2d_513x257_r2", W.cell2d().replace(hermite="r2"), {"hermite": "r2"}, ("f32",)),
+        ("abc3d_65_r1", W.abc3d(n=65, n_steps=100), {}, ("f32",)),
+        ("abc3d_65_r2", W.abc3d(n=65, n_steps=100).replace(hermite="r2"),
+         {"hermite": "r2", "step_kernel": "node"}, ("f32",)),
+        ("runaway3d", W.runaway3d(), {}, ("f64", "f32")),
+    ]
+    out = {}
+    for name, prob, kw, precs in cases:
+        for prec in precs:
+            pl = Plan(prob, precision=prec, use_graph=True, **kw)
+            Ja = sum(pl.active_count)
+            pl.forward([0])
+            torch.cuda.synchronize()
+            ms, _ = event_time(lambda: pl.forward([0]), 3, stream)
+            prof = pl.profile_pass()
+            pl.close()
+            key = f"{name}_{prec}"
+            out[key] = {"shape": list(prob.shape), "n_steps": prob.n_steps, "gh_q": prob.gh_q,
+                        "active_nodes": Ja, "ms_per_pass": round(ms, 3),
+                        "gp_steps_per_s": Ja * prob.n_steps / (ms * 1e-3),
+                        "step_kernel_ms": round(prof["step_fused"][0], 5),
+                        "slopes_ms": round(prof["slopes"][0], 5)}
+            log(f"{key}: {ms:.2f} ms per pass, {out[key]['gp_steps_per_s']:.3e} gp-steps/s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -620,6 +658,7 @@ def main():
             "roofline_ell_apply": ell_roofline(pe, pp["ell_apply"][0])}
         pe.close()
         result["algorithm1"] = algorithm1_leg(stream, log)
+        result["extensions_forward"] = extra_rows_leg(stream, log)
 
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(probs, args.cpu_steps)
