@@ -30,3 +30,24 @@ def lamN_sensitivity(prob, lam0, rel=2.0 ** -44, trials=3, seed=7):
         _, l = oracle.adjoint_states(prob, Up, lam0)
         worst = max(worst, float(np.abs(l - l0).max() / np.abs(l0).max()) / rel)
     return worst
+
+
+def lamN_fp32_emulation(prob, lam0):
+    """The oracle's dJ/du^N over its own states as an FP32 implementation
+    holds them: every state rounded to FP32, and values whose divided
+    differences' product underflows FP32's normal range in the PCHIP slope
+    (|u| below sqrt(FLT_MIN) times the smallest spacing) set to zero -- the two
+    ways FP32 flips the PCHIP Jacobian to its flat branch at the edge of the
+    spreading solution.  Returns (relative l1 norm of the difference from the
+    exact FP64 dJ/du^N, relative difference of the two l1 norms)."""
+    U = oracle.solve_all(prob)
+    _, l_ref = oracle.adjoint_states(prob, U, lam0)
+    h = min(float(np.diff(ax.nodes).min()) for ax in prob.axes)
+    tau = float(np.sqrt(np.finfo(np.float32).tiny)) * h
+    U32 = U.astype(np.float32).astype(np.float64)
+    U32[np.abs(U32) < tau] = 0.0
+    del U
+    _, l32 = oracle.adjoint_states(prob, U32, lam0)
+    n_ref = float(np.abs(l_ref).sum())
+    return (float(np.abs(l32 - l_ref).sum()) / n_ref,
+            abs(float(np.abs(l32).sum()) - n_ref) / n_ref)

@@ -4,8 +4,15 @@ nodes), for J = mean of u^0 over the disc, and central differences of J with
 relative step h = 1e-6 in each parameter (A, eps, omega, D), once with the
 exit classification frozen at the base parameters and once recomputed.
 
-Calls only the oracle (and the workload definitions).  About 20 minutes on
-8 cores:  python tests/golden/make_cell2d_adj.py
+Also lamN_fp32_emulation: the relative difference of the l1 norms of the
+oracle's dJ/du^N over its exact states and over the same states as an FP32
+implementation holds them (rounded to FP32, values below the FP32 underflow
+threshold of the PCHIP slope's products zeroed; tests/bars.py), the scale of
+the FP32 dJ/du^N deviation.
+
+Calls only the oracle (and the workload definitions).  About 30 minutes on
+8 cores:  python tests/golden/make_cell2d_adj.py   (--augment adds the
+emulation to an existing file)
 """
 from __future__ import annotations
 
@@ -21,6 +28,9 @@ sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
 import workloads as W  # noqa: E402
+
+sys.path.insert(0, os.path.join(ROOT, "tests"))
+from bars import lamN_fp32_emulation  # noqa: E402
 
 H = 1e-6
 N_SAMPLES = 256
@@ -72,11 +82,26 @@ def main(path: str = os.path.join(os.path.dirname(os.path.abspath(__file__)),
         "lamN_max_abs": float(np.abs(flat).max()),
         "lamN_index": idx.tolist(),
         "lamN_value": [float(flat[i]) for i in idx],
+        "lamN_fp32_emulation": lamN_fp32_emulation(prob, lam0)[1],
     }
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", path, flush=True)
 
 
+def augment(path: str = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                     "cell2d_adj_oracle.json")):
+    with open(path) as f:
+        out = json.load(f)
+    prob = W.cell2d_adj()
+    out["lamN_fp32_emulation"] = lamN_fp32_emulation(prob, W.region_mean_weights(prob))[1]
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print("lamN_fp32_emulation", out["lamN_fp32_emulation"], "wrote", path, flush=True)
+
+
 if __name__ == "__main__":
-    main()
+    if "--augment" in sys.argv[1:]:
+        augment()
+    else:
+        main()

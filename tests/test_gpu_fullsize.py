@@ -16,6 +16,7 @@ import pytest
 
 import oracle
 import workloads as W
+from bars import lamN_fp32_emulation
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -95,10 +96,23 @@ def _rel(a, b):
 # solution (down to 1e-300), FP32 holds zeros -- or products of such values
 # underflow in the slope formulas -- and takes the flat branch, so lambda^N
 # differs by O(lambda) at those nodes; the gradient w.r.t. theta, whose terms
-# carry a factor u, does not see it.  An FP64 oracle that zeroes states below
-# 1e-24..1e-30 reproduces the FP32 differences (count and size), so the FP32
-# bar on lambda^N is on its relative l1 norm.
-F32_LAMN_L1 = 0.1
+# carry a factor u, does not see it.  The bar is derived from that mechanism
+# on the oracle (bars.lamN_fp32_emulation): its dJ/du^N over its own states
+# rounded to FP32, with the values whose slope products underflow FP32 zeroed,
+# moves by a relative l1 of about 5e-2 over 300 steps (the GPU's FP32: 4.4e-2).
+# Over longer sweeps the FP32 rounding of the sweep itself adds up instead: a
+# step's dJ/du^n entry is a sum about 82 operations deep, so its relative
+# rounding error is at most gamma_82 in FP32, and N steps of a norm-preserving
+# transposed operator move the l1 norm by at most N gamma_82 (2000 steps:
+# 9.8e-3; the GPU's FP32 |dJ/du^N|_1 moves by 1.1e-4 there, the emulation by
+# 8e-9).  The FP32 bar is the larger of twice the emulated deviation and
+# N gamma_82.
+F32_EMULATION_FACTOR = 2.0
+
+
+def _f32_rounding_bound(n_steps, depth=82):
+    u = 2.0 ** -24
+    return n_steps * depth * u / (1.0 - depth * u)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -124,7 +138,10 @@ def test_cell2d_adj_full_grid_vs_oracle(prec):
         # lambda entries are ~1e-4 here (1/m over the disc): the FP64 bar in max abs
         assert rg <= 1e-9 and la <= 1e-12
     else:
-        assert rg <= 1e-4 and l1 <= F32_LAMN_L1
+        emul_l1, _ = lamN_fp32_emulation(prob, lam0)
+        print(f"FP32 emulation on the oracle: relative l1 {emul_l1:.3e}")
+        assert rg <= 1e-4 and l1 <= max(F32_EMULATION_FACTOR * emul_l1,
+                                        _f32_rounding_bound(prob.n_steps))
 
 
 def _fixture():
@@ -158,7 +175,9 @@ def test_cell2d_adj_full_size_vs_oracle_fixture(prec):
     if prec == "f64":
         assert rg <= 1e-9 and samp <= 1e-12 and l1 <= 1e-9
     else:
-        assert rg <= 1e-4 and l1 <= F32_LAMN_L1
+        # the oracle's own |dJ/du^N|_1 change under the FP32 emulation, stored
+        assert rg <= 1e-4 and l1 <= max(F32_EMULATION_FACTOR * ref["lamN_fp32_emulation"],
+                                        _f32_rounding_bound(prob.n_steps))
 
 
 def test_abc8_full_size_adjoint_wrt_D_vs_central_differences():
