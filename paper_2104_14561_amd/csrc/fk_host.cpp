@@ -894,7 +894,11 @@ fk_status build_plan(fk_plan *p)
         for (int i = 0; i < p->n_inst; ++i) {
             const fk_problem &pr = p->probs[i];
             std::vector<int> fw = inst_rest[i];
-            if (!p->use_box || inst_cls[i] < 0) {
+            // the box form up to 5-node footprints: from L = 6 on the box step's
+            // vectors no longer fit the registers (measured on 65^3 ABC flows:
+            // L = 3 and 5 six and four times faster than a thread per node, L = 6
+            // five times slower)
+            if (!p->use_box || inst_cls[i] < 0 || inst_cls[i] > 2) {
                 fw.insert(fw.end(), inst_sep[i].begin(), inst_sep[i].end());
             } else {
                 std::vector<int> sep = inst_sep[i];
