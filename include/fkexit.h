@@ -86,12 +86,14 @@ enum { FK_COEF_CONST = 0, FK_COEF_CELLULAR2D = 1, FK_COEF_ABC3D = 2, FK_COEF_ROL
  * FK_FACE_REFLECT: it is mirrored back into the domain, z -> lo + (lo - z).
  * Exit nodes hold their face's value for every n; at a corner the lowest axis
  * decides (low face before high face), then the ball.  Plans with a face other
- * than FK_FACE_EXIT1 (and FK_COEF_RUNAWAY3D plans) run the lane-group step,
- * the fused form and the forward calls only. */
+ * than FK_FACE_EXIT1 (and FK_COEF_RUNAWAY3D plans) run the fused form and the
+ * forward calls only, in the thread-per-node step layouts (fk_options
+ * .step_kernel 0, 1 or 3; 4 falls back to 1) or the lane-group one (2, and
+ * with FK_HERMITE_R2). */
 enum { FK_FACE_EXIT1 = 0, FK_FACE_EXIT0 = 1, FK_FACE_REFLECT = 2 };
 
-/* Exit region (paper Section 2: D is an open box; the benchmark spec's targets add
- * a ball).  FK_REGION_BOX: a point exits when a coordinate on a non-periodic
+/* Exit region (paper Section 2: D is an open box; a disc or ball target, such
+ * as the cellular-flow workload's disc, adds a ball).  FK_REGION_BOX: a point exits when a coordinate on a non-periodic
  * axis is <= the first or >= the last node.  FK_REGION_BALL: it also exits
  * when |z - center|^2 >= radius^2 (evaluated as sum over axes of
  * (z_i - c_i)*(z_i - c_i), axis 0 first, no fused multiply-add).  Nodes that

@@ -1022,7 +1022,12 @@ __global__ void __launch_bounds__(kBlock) k_step_fused(
 //
 // G > 1 (small plans): G lanes share a node, lane l taking the outermost
 // axis' indices l, l + G, ...; the lane sums are combined by a shuffle tree.
-template <typename T, int D, int QS, int G, bool AFF, bool TW = false>
+//
+// FC: face kinds other than exit-1 and node-dependent diffusion (the
+// runaway model): the node's own per-axis scales, reflecting faces mirrored
+// by the axis evaluation, and a second exit mass for exits with value 0 (the
+// lowest exiting axis decides a point's value, as in the loops' order).
+template <typename T, int D, int QS, int G, bool AFF, bool TW = false, bool FC = false>
 __global__ void __launch_bounds__(kBlock) k_step_node(
     const PlanDev P, int n, int n_work, const DevInst *__restrict__ insts,
     const WorkItem *__restrict__ work, const int *__restrict__ nodes,
@@ -1044,39 +1049,48 @@ __global__ void __launch_bounds__(kBlock) k_step_node(
         const WorkItem it = work[w];
         if (G == 1 && slot >= it.count) continue;
         const bool valid = slot < it.count;
-        const bool interior = it.kind == 1;   // host: no landing point can exit
+        const bool interior = !FC && it.kind == 1;   // host: no landing point can exit
         const DevInst &I = insts[it.inst];
         const int node = valid ? nodes[it.first + slot] : nodes[it.first];
         int idx[3];
         split_node<D>(I, node, idx);
         const T uref = rec[I.node_off + node].x;
-        double c[3];
-        node_centre<D>(I, coords, time_factors(P, n, it.inst), trig, idx, P.dt, c);
+        double c[3], S[3] = {0.0, 0.0, 0.0};
+        if constexpr (FC) node_centre_s<D>(I, coords, time_factors(P, n, it.inst), trig, idx, P.dt, c, S);
+        else node_centre<D>(I, coords, time_factors(P, n, it.inst), trig, idx, P.dt, c);
+        // one landing coordinate on axis a
+        auto axis = [&](int a, double g) -> AxisEval {
+            if constexpr (FC) return eval_axis_faces(I, coords, a, c[a], g, S[a]);
+            else return eval_axis_t<AFF>(I, coords, a, c[a], g);
+        };
         const bool ball = I.region_kind == 1;
         const double r2 = I.r2;
         // innermost axis, hoisted
         constexpr int AI = D - 1;
         int kin[QS];
         T bin[QS][4];
-        bool exin[QS];
+        bool exin[QS], ex0in[QS];
         double din[QS];
 #pragma unroll
         for (int q = 0; q < QS; ++q) {
-            const AxisEval e = eval_axis_t<AFF>(I, coords, AI, c[AI], ga[q]);
+            const AxisEval e = axis(AI, ga[q]);
             const Basis<T> B = hermite<T>(e.s, e.h);
             kin[q] = e.k;
             bin[q][0] = B.v0; bin[q][1] = B.v1; bin[q][2] = B.d0; bin[q][3] = B.d1;
             exin[q] = e.ex;
+            ex0in[q] = FC && e.ex && e.exv == 0.0;
             din[q] = e.dz2;
         }
-        T acc = T(0), emass = T(0);
+        // exit masses: value 1 (emass) and, with FC, value 0 (em0)
+        T acc = T(0), emass = T(0), em0 = T(0);
         if constexpr (D == 1) {
 #pragma unroll
             for (int q = 0; q < QS; ++q) {
                 if (G > 1 && (q % G) != lane) continue;
                 const bool ex = exin[q] || (ball && din[q] >= r2);
                 if (ex) {
-                    emass += w1[q];
+                    if (ex0in[q]) em0 += w1[q];
+                    else emass += w1[q];
                     continue;
                 }
                 const long long base = I.node_off + kin[q];
@@ -1117,50 +1131,55 @@ __global__ void __launch_bounds__(kBlock) k_step_node(
                 }
             } else {
                 for (int q0 = lane; q0 < QS; q0 += G) {
-                    const AxisEval e0 = eval_axis_t<AFF>(I, coords, 0, c[0], ga[q0]);
+                    const AxisEval e0 = axis(0, ga[q0]);
                     const T w0 = w1[q0];
                     if (e0.ex) {
-                        emass += w0 * wsum;
+                        if (FC && e0.exv == 0.0) em0 += w0 * wsum;
+                        else emass += w0 * wsum;
                         continue;
                     }
                     const Basis<T> X = hermite<T>(e0.s, e0.h);
                     const int row = e0.k * s0;
-                    T part = T(0), pex = T(0);
+                    T part = T(0), pex = T(0), pex0 = T(0);
 #pragma unroll
                     for (int q1 = 0; q1 < QS; ++q1) {
                         bool ex = exin[q1];
                         if (ball) ex = ex || ball_exit2(e0.dz2, din[q1], r2);
                         if (ex) {
-                            pex += w1[q1];
+                            if (ex0in[q1]) pex0 += w1[q1];
+                            else pex += w1[q1];
                             continue;
                         }
                         part += point(row, X, q1);
                     }
                     acc += w0 * part;
                     emass += w0 * pex;
+                    if constexpr (FC) em0 += w0 * pex0;
                 }
             }
         } else {
             for (int q0 = lane; q0 < QS; q0 += G) {
-                const AxisEval e0 = eval_axis_t<AFF>(I, coords, 0, c[0], ga[q0]);
+                const AxisEval e0 = axis(0, ga[q0]);
                 const T w0 = w1[q0];
                 if (e0.ex) {
-                    emass += w0 * wsum * wsum;
+                    if (FC && e0.exv == 0.0) em0 += w0 * wsum * wsum;
+                    else emass += w0 * wsum * wsum;
                     continue;
                 }
                 const Basis<T> X = hermite<T>(e0.s, e0.h);
                 for (int q1 = 0; q1 < QS; ++q1) {
-                    const AxisEval e1 = eval_axis_t<AFF>(I, coords, 1, c[1], ga[q1]);
+                    const AxisEval e1 = axis(1, ga[q1]);
                     const T w01 = w0 * w1[q1];
                     if (e1.ex) {
-                        emass += w01 * wsum;
+                        if (FC && e1.exv == 0.0) em0 += w01 * wsum;
+                        else emass += w01 * wsum;
                         continue;
                     }
                     const Basis<T> Y = hermite<T>(e1.s, e1.h);
                     const long long base = I.node_off + (long long)e0.k * I.stride[0] +
                                            (long long)e1.k * I.stride[1];
                     const long long s0 = I.stride[0], s1 = I.stride[1];
-                    T part = T(0), pex = T(0);
+                    T part = T(0), pex = T(0), pex0 = T(0);
 #pragma unroll
                     for (int q2 = 0; q2 < QS; ++q2) {
                         bool ex = exin[q2];
@@ -1169,7 +1188,8 @@ __global__ void __launch_bounds__(kBlock) k_step_node(
                             ex = ex || ball_exit(dz, 3, r2);
                         }
                         if (ex) {
-                            pex += w1[q2];
+                            if (ex0in[q2]) pex0 += w1[q2];
+                            else pex += w1[q2];
                             continue;
                         }
                         const long long b = base + kin[q2];
@@ -1201,15 +1221,18 @@ __global__ void __launch_bounds__(kBlock) k_step_node(
                     }
                     acc += w01 * part;
                     emass += w01 * pex;
+                    if constexpr (FC) em0 += w01 * pex0;
                 }
             }
         }
         if (G > 1) {
             acc = group_sum<G>(acc);
             emass = group_sum<G>(emass);
+            if constexpr (FC) em0 = group_sum<G>(em0);
             if (!valid || lane != 0) continue;
         }
-        const T v = uref + acc + emass * (T(1) - uref);
+        T v = uref + acc + emass * (T(1) - uref);
+        if constexpr (FC) v = v - em0 * uref;
         flag_nonfinite(P.flags, v);
         store_node<D, T>(I, idx, node, v, u_out);
     }

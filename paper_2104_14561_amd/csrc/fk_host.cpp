@@ -833,7 +833,9 @@ fk_status build_plan(fk_plan *p)
         bool affine = true;
         for (const fk::DevInst &I : p->inst)
             for (int a = 0; a < p->d; ++a) affine = affine && I.affine[a];
-        if (sk == 2 || !node_ok || p->faces) p->step_kind = 1;   // faces: the lane-group step
+        // faces (other than exit-1) with the R2 interpolant: the lane-group step
+        const bool faces_r2 = p->faces && p->opt.hermite == FK_HERMITE_R2;
+        if (sk == 2 || !node_ok || faces_r2) p->step_kind = 1;
         else if (sk == 3 || (sk == 0 && !large)) p->step_kind = 2;
         else p->step_kind = 0;
         // the separable form by default in 3D only: there a node's Q*^3

@@ -37,16 +37,19 @@ template <typename T, int D, int QS>
 void step_node_launch(const PlanDev &P, int n, const void *packed, void *u_out, hipStream_t s)
 {
     constexpr int GS = (QS <= 2) ? 2 : (QS <= 4) ? 4 : (QS <= 8) ? 8 : 16;
-    // TW: the R2 interpolant (2D), whose records carry the twist field
-#define FK_NODE_TW(G_, AFF_, TW_, grid_, nw_, wl_)                                             \
-    k_step_node<T, D, QS, G_, AFF_, TW_><<<grid_, kBlock, 0, s>>>(                             \
+    // TW: the R2 interpolant, whose records carry the twist field; FC: face
+    // kinds other than exit-1 or node-dependent diffusion (never with R2: the
+    // plan builder sends those plans to the lane-group step)
+#define FK_NODE_TW(G_, AFF_, TW_, FC_, grid_, nw_, wl_)                                        \
+    k_step_node<T, D, QS, G_, AFF_, TW_, FC_><<<grid_, kBlock, 0, s>>>(                        \
         P, n, nw_, P.inst, wl_, P.fw_nodes, P.trig, P.coords, (const T *)packed, (T *)u_out)
 #define FK_NODE(G_, AFF_, grid_, nw_, wl_)                                                     \
     do {                                                                                       \
+        if (P.faces) { FK_NODE_TW(G_, AFF_, false, true, grid_, nw_, wl_); break; }            \
         if constexpr (D >= 2) {                                                                \
-            if (P.hermite2) { FK_NODE_TW(G_, AFF_, true, grid_, nw_, wl_); break; }            \
+            if (P.hermite2) { FK_NODE_TW(G_, AFF_, true, false, grid_, nw_, wl_); break; }     \
         }                                                                                      \
-        FK_NODE_TW(G_, AFF_, false, grid_, nw_, wl_);                                          \
+        FK_NODE_TW(G_, AFF_, false, false, grid_, nw_, wl_);                                   \
     } while (0)
     if (P.n_fw_work > 0) {
         if (P.step_kind == 2) {

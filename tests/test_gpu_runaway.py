@@ -5,7 +5,10 @@ fields FP64 within 1e-12 and FP32 within 1e-5, landing cells and exit flags
 bit-exact, on 1D Brownian exits through one face, a 2D problem with mixed
 faces, the runaway model (time-independent and thermal-quench) on a small
 grid and on the paper's grid (49 x 41 x 128, the radial spacing 0.1 on
-[0, 0.7] and 0.0025 on [0.7, 1]) over the first 48 steps."""
+[0, 0.7] and 0.0025 on [0.7, 1]) over the first 48 steps; every step layout
+(the face-aware thread-per-node kernel whole and split, the lane-group
+kernel), a batch of two runaway instances of different electric fields, and
+the R2 interpolant with faces (the lane-group step)."""
 from __future__ import annotations
 
 import numpy as np
@@ -25,8 +28,8 @@ from paper_2104_14561_amd import FkError, Plan  # noqa: E402
 TOL = {"f64": 1e-12, "f32": 1e-5}
 
 
-def _run(prob, prec, snaps):
-    plan = Plan(prob, precision=prec, use_graph=True)
+def _run(prob, prec, snaps, **kw):
+    plan = Plan(prob, precision=prec, use_graph=True, **kw)
     out = plan.split(plan.forward(snaps))[0].double().cpu().numpy()
     torch.cuda.synchronize()
     assert plan.check_flags() == 0
@@ -91,3 +94,46 @@ def test_faces_refused_outside_what_is_built():
     for kw in ({"form": "ell"}, {"ckpt_every": 4}):
         with pytest.raises(FkError, match="FK_ERR_UNSUPPORTED"):
             Plan(prob, **kw)
+
+
+@pytest.mark.parametrize("kernel", ["node", "split", "group", "box"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("name", ["bm_exit0", "mixed2d", "runaway"])
+def test_faces_every_step_layout_matches_oracle(name, prec, kernel):
+    prob = _cases()[name]
+    snaps = [prob.n_steps, 0]
+    ref = oracle.solve(prob, snaps=snaps)
+    got = _run(prob, prec, snaps, step_kernel=kernel)
+    err = float(np.abs(got - ref).max())
+    print(f"{name} {prec} {kernel}: max|gpu - oracle| {err:.3e}")
+    assert err <= TOL[prec]
+
+
+def test_runaway_batch_of_two_fields():
+    # two instances that differ in the electric field E (coef[0]): the
+    # per-instance coefficient tables of the batched step
+    a = _cases()["runaway"]
+    b = W.runaway3d(n_p=13, n_xi=9, r_axis=W.remark2_axis(0.0, 0.7, 1.0, 0.1, 0.05), dt=1.0,
+                    T=20.0, E=a.coef[0] * 1.5)
+    refs = [oracle.solve(pr, snaps=[0])[0] for pr in (a, b)]
+    assert float(np.abs(refs[0] - refs[1]).max()) > 1e-3
+    for prec in ("f64", "f32"):
+        plan = Plan([a, b], precision=prec, use_graph=True)
+        outs = [o.double().cpu().numpy()[0] for o in plan.split(plan.forward([0]))]
+        torch.cuda.synchronize()
+        assert plan.check_flags() == 0
+        plan.close()
+        for i in range(2):
+            err = float(np.abs(outs[i] - refs[i]).max())
+            print(f"runaway batch [{i}] {prec}: {err:.3e}")
+            assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_faces_with_r2_match_oracle(prec):
+    prob = _cases()["mixed2d"].replace(hermite="r2")
+    ref = oracle.solve(prob, snaps=[0])
+    got = _run(prob, prec, [0], hermite="r2")
+    err = float(np.abs(got - ref).max())
+    print(f"mixed2d R2 {prec}: {err:.3e}")
+    assert err <= TOL[prec]
