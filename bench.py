@@ -512,7 +512,7 @@ def main():
     else:
         ms_k = prof_f["step_fused"][0]
         roof = scope_roofline(d, Q, Ja, ms_k, 1, plan.precision, "k_step_node (fused step)")
-        kname = "void k_step_node<float, 2, 8, 1, true, false>"
+        kname = "void k_step_node<float, 2, 8, 1, true, false, false>"
         share = t_step_kernel / ms_step
     roof["traffic"] = measured_traffic(kname)
     roof["share_of_step"] = round(share, 4)

@@ -1666,8 +1666,11 @@ __device__ inline int fast_div(int n, unsigned long long m)
 // (thread-minor, conflict-free), then the four waves share the rows' 16-byte
 // blocks (wave w: block indices w, w + 4, ..), so that a wave's stores of one
 // block index are 1 KB in one piece and four waves keep stores in flight per
-// set of vectors.  The exit mass is accumulated axis by axis, exactly 0 when
-// nothing leaves.
+// set of vectors.  Which vector entries a block multiplies depends on the
+// instance's box only: the workgroup tabulates it in LDS once per instance
+// (a lane per block, K x D column indices, padding nodes pointing at a zero
+// column), so the block loop reads one table entry and K x D vector values.
+// The exit mass is accumulated axis by axis, exactly 0 when nothing leaves.
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_assemble_ell_sep(PlanDev P, int n,
                                                           const WorkItem *__restrict__ work,
@@ -1677,18 +1680,62 @@ __global__ void __launch_bounds__(256) k_assemble_ell_sep(PlanDev P, int n,
                                                           T *__restrict__ exit_mass)
 {
     constexpr int K = EllBlock<T>::K;
+    static_assert(K * D <= 16, "a table entry holds the K x D column indices of a block");
     using B = EllBlock<T>;
     extern __shared__ unsigned char smem_raw[];
-    T *vec = reinterpret_cast<T *>(smem_raw);   // [D][value, slope][lmax][64]
+    // [D][value, slope][lmax][64], then the zero column zcol (host: zcol <= 255)
+    T *vec = reinterpret_cast<T *>(smem_raw);
+    const int zcol = D * 2 * lmax;
+    // 16 bytes per block of the current instance: column of entry j, axis a at j D + a
+    unsigned char *tab = smem_raw + (size_t)(zcol + 1) * 64 * sizeof(T);
     __shared__ T mass[2][3][64];                // per axis: inside, outside weight
     __shared__ int orgs[3][64];
     const T *w1 = weights1<T>(P);
-    const int t = threadIdx.x % 64, wv = threadIdx.x / 64;
+    // the wave index as a uniform value: the block loop runs on the scalar unit
+    const int t = threadIdx.x % 64, wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     auto V = [&](int a, int v, int l) -> T & { return vec[((a * 2 + v) * lmax + l) * 64 + t]; };
+    if (threadIdx.x < 64) vec[zcol * 64 + threadIdx.x] = T(0);
+    int cur = -1;   // instance the table holds
     const WorkRange wr = work_range(0, n_work);
     for (int w = wr.begin; w < wr.end; w += wr.step) {
         const WorkItem it = work[w];
         const DevInst &I = P.inst[it.inst];
+        const int nbox = I.ell_w / (D + 1);
+        const int bpf = I.ell_nbp / K;
+        const int nblk = (D + 1) * bpf;
+        if (it.inst != cur) {
+            // blocks: field f (0 value, 1 + a slope along a), K box nodes each,
+            // box nodes in order with the last axis fastest; padding nodes hold 0
+            cur = it.inst;
+            unsigned long long rb[3];
+            for (int a = 0; a < D; ++a) rb[a] = fast_recip(I.ell_box[a]);
+            for (int g = threadIdx.x; g < nblk; g += 256) {
+                const int f = g / bpf;
+                int l = (g - f * bpf) * K;
+                int li[3] = {0, 0, 0};
+                int rem = l;
+                for (int a = D - 1; a >= 0; --a) {
+                    const int q = fast_div(rem, rb[a]);
+                    li[a] = rem - q * I.ell_box[a];
+                    rem = q;
+                }
+                unsigned int e[4] = {0u, 0u, 0u, 0u};
+                for (int j = 0; j < K; ++j, ++l) {
+                    for (int a = 0; a < D; ++a) {
+                        const unsigned int col = l < nbox
+                            ? (unsigned int)((a * 2 + (f == a + 1 ? 1 : 0)) * lmax + li[a])
+                            : (unsigned int)zcol;
+                        const int k = j * D + a;
+                        e[k / 4] |= col << (8 * (k % 4));
+                    }
+                    for (int a = D - 1; a >= 0; --a) {
+                        if (++li[a] < I.ell_box[a]) break;
+                        li[a] = 0;
+                    }
+                }
+                *reinterpret_cast<uint4 *>(tab + (size_t)g * 16) = make_uint4(e[0], e[1], e[2], e[3]);
+            }
+        }
         const bool valid = t < it.count;
         const long long r = it.first + t;   // row within the instance
         const long long row = I.act_off + r;
@@ -1706,6 +1753,16 @@ __global__ void __launch_bounds__(256) k_assemble_ell_sep(PlanDev P, int n,
             }
             const int origin = eval_axis(I, P.coords, a, c[a], P.gh_a[0]).k;
             T in_a = T(0), out_a = T(0);
+            // the landing cells rise with q (ascending GH nodes, S >= 0), so the
+            // sums of the two nodes of the current cell stay in registers and
+            // a node's total goes to LDS once, when the cell moves past it
+            // (the same additions in the same order as accumulating in LDS)
+            int wl = -1;                                 // cell of the window
+            T v0 = T(0), d0 = T(0), v1 = T(0), d1 = T(0);   // nodes wl, wl + 1
+            auto flush = [&](int node, T v, T d) {
+                V(a, 0, node) += v;
+                V(a, 1, node) += d;
+            };
             for (int q = 0; q < P.qs; ++q) {
                 const AxisEval e = eval_axis(I, P.coords, a, c[a], P.gh_a[q]);
                 const T wq = w1[q];
@@ -1718,12 +1775,32 @@ __global__ void __launch_bounds__(256) k_assemble_ell_sep(PlanDev P, int n,
                     atomicOr(P.flags, 2);
                     continue;
                 }
+                if (l != wl) {
+                    if (wl >= 0) {
+                        flush(wl, v0, d0);
+                        if (l == wl + 1) {
+                            v0 = v1;
+                            d0 = d1;
+                        } else {
+                            flush(wl + 1, v1, d1);
+                            v0 = T(0);
+                            d0 = T(0);
+                        }
+                        v1 = T(0);
+                        d1 = T(0);
+                    }
+                    wl = l;
+                }
                 const Basis<T> Bq = hermite<T>(e.s, e.h);
-                V(a, 0, l) += wq * Bq.v0;
-                V(a, 0, l + 1) += wq * Bq.v1;
-                V(a, 1, l) += wq * Bq.d0;
-                V(a, 1, l + 1) += wq * Bq.d1;
+                v0 += wq * Bq.v0;
+                v1 += wq * Bq.v1;
+                d0 += wq * Bq.d0;
+                d1 += wq * Bq.d1;
                 in_a += wq;
+            }
+            if (wl >= 0) {
+                flush(wl, v0, d0);
+                flush(wl + 1, v1, d1);
             }
             mass[0][a][t] = in_a;
             mass[1][a][t] = out_a;
@@ -1741,45 +1818,33 @@ __global__ void __launch_bounds__(256) k_assemble_ell_sep(PlanDev P, int n,
                 for (int a = 0; a < 3; ++a) org[row * 3 + a] = a < D ? orgs[a][t] : 0;
                 exit_mass[row] = em;
             }
-            // blocks: field f (0 value, 1 + a slope along a), K box nodes each,
-            // box nodes in order with the last axis fastest; padding nodes hold 0
-            const int nbox = I.ell_w / (D + 1);
-            const int bpf = I.ell_nbp / K;
             const long long rows = I.n_act;
-            unsigned long long rb[3];
-            for (int a = 0; a < D; ++a) rb[a] = fast_recip(I.ell_box[a]);
             B *dst = reinterpret_cast<B *>(vals + I.ell_off) + r;
-            const int nblk = (D + 1) * bpf;
+#pragma unroll 2
             for (int g = wv; g < nblk; g += 4) {
-                const int f = g / bpf, lb = g - f * bpf;
-                int l = lb * K;
-                int li[3] = {0, 0, 0};
-                {
-                    int rem = l;
-                    for (int a = D - 1; a >= 0; --a) {
-                        const int q = fast_div(rem, rb[a]);
-                        li[a] = rem - q * I.ell_box[a];
-                        rem = q;
+                const uint4 e4 = *reinterpret_cast<const uint4 *>(tab + (size_t)g * 16);
+                const unsigned int e[4] = {e4.x, e4.y, e4.z, e4.w};
+                T x[K][D];
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        const int k = j * D + a;
+                        const unsigned int col = (e[k / 4] >> (8 * (k % 4))) & 255u;
+                        x[j][a] = vec[col * 64 + t];
                     }
-                }
                 B blk;
 #pragma unroll
-                for (int j = 0; j < K; ++j, ++l) {
-                    T v = T(0);
-                    if (l < nbox) {
-                        v = T(1);
-                        for (int a = 0; a < D; ++a) v *= V(a, f == a + 1 ? 1 : 0, li[a]);
-                        for (int a = D - 1; a >= 0; --a) {
-                            if (++li[a] < I.ell_box[a]) break;
-                            li[a] = 0;
-                        }
-                    }
+                for (int j = 0; j < K; ++j) {
+                    T v = x[j][0];
+#pragma unroll
+                    for (int a = 1; a < D; ++a) v *= x[j][a];
                     blk.v[j] = v;
                 }
                 store_block_nt(dst + (long long)g * rows, blk);
             }
         }
-        __syncthreads();   // the vectors are rebuilt for the next work item
+        __syncthreads();   // the vectors (and the table) are rebuilt for the next work item
     }
 }
 

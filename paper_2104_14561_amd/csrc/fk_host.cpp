@@ -165,7 +165,7 @@ struct fk_plan {
     int ell_lmax = 1;                     // longest row box axis
     int n_ell_sep_cls = 0;
     int ell_sep_off[fk::kEllClasses] = {}, ell_sep_n[fk::kEllClasses] = {},
-        ell_sep_l[fk::kEllClasses] = {};
+        ell_sep_l[fk::kEllClasses] = {}, ell_sep_tb[fk::kEllClasses] = {};
     int n_ell_cls = 0;
     int ell_cls_off[fk::kEllClasses] = {}, ell_cls_n[fk::kEllClasses] = {},
         ell_cls_w[fk::kEllClasses] = {};
@@ -1104,8 +1104,17 @@ fk_status build_plan(fk_plan *p)
         p->ell_sep_work.clear();
         p->ell_lmax = 1;
         for (int a = 0; a < p->d; ++a) p->ell_lmax = std::max(p->ell_lmax, p->ell_box[a]);
-        // its per-thread axis vectors (d x 2 x lmax, 64 rows) must fit the LDS
-        const bool sep_ok = (size_t)p->d * 2 * p->ell_lmax * 64 * 8 <= 64 * 1024;
+        // its per-thread axis vectors (d x 2 x lmax, 64 rows, and a zero column)
+        // and the block table of an instance (16 bytes per block) must fit the
+        // LDS; the table's column indices are bytes
+        const bool f32e = p->opt.precision == FK_PREC_F32;
+        const int ke = f32e ? 4 : 2;
+        auto sep_table = [&](int i) { return (size_t)(p->d + 1) * (p->inst[i].ell_nbp / ke) * 16; };
+        size_t tb_all = 0;
+        for (int i = 0; i < p->n_inst; ++i) tb_all = std::max(tb_all, sep_table(i));
+        const int zcol = p->d * 2 * p->ell_lmax;
+        const bool sep_ok = zcol <= 255 &&
+                            (size_t)(zcol + 1) * 64 * (f32e ? 4 : 8) + tb_all <= 60 * 1024;
         const int npb_e = kBlock / p->G;
         for (int i = 0; i < p->n_inst; ++i) {
             const std::vector<unsigned char> &sr = inst_seprow[i];
@@ -1135,12 +1144,14 @@ fk_status build_plan(fk_plan *p)
             for (int lb = 8; nsc < fk::kEllClasses; lb *= 2) {
                 const int lo = nsc == 0 ? 0 : lb / 2;
                 int lmax_c = 0, first = (int)p->ell_sep_work.size();
+                size_t tb_c = 0;
                 for (const fk::WorkItem &it : sw) {
                     int li = 1;
                     for (int a = 0; a < p->d; ++a) li = std::max(li, p->inst[it.inst].ell_box[a]);
                     if (li > lo && li <= lb) {
                         p->ell_sep_work.push_back(it);
                         lmax_c = std::max(lmax_c, li);
+                        tb_c = std::max(tb_c, sep_table(it.inst));
                     }
                 }
                 const int cnt = (int)p->ell_sep_work.size() - first;
@@ -1148,6 +1159,7 @@ fk_status build_plan(fk_plan *p)
                     p->ell_sep_off[nsc] = first;
                     p->ell_sep_n[nsc] = cnt;
                     p->ell_sep_l[nsc] = lmax_c;
+                    p->ell_sep_tb[nsc] = (int)tb_c;
                     ++nsc;
                 }
                 if (lb >= p->ell_lmax) break;
@@ -1264,14 +1276,24 @@ void fill_dev(fk_plan *p)
         D.ell_sep_off[c] = p->ell_sep_off[c];
         D.ell_sep_n[c] = p->ell_sep_n[c];
         D.ell_sep_l[c] = p->ell_sep_l[c];
-        D.ell_sep_grid[c] = grid_for(p->ell_sep_n[c]);   // 256 threads share 64 rows
+        D.ell_sep_tb[c] = p->ell_sep_tb[c];
+        // 256 threads share 64 rows; every workgroup resident at once
+        int pc = 8;
+        if (p->ell_sep_n[c] > 0)
+            (void)fk::ell_per_cu(p->d, 1, p->f32, true,
+                                 fk::ell_sep_lds(p->d, p->ell_sep_l[c], p->ell_sep_tb[c], p->f32), &pc);
+        D.ell_sep_grid[c] = grid_for(p->ell_sep_n[c], pc);
     }
     D.n_ell_cls = p->n_ell_cls;
     for (int c = 0; c < fk::kEllClasses; ++c) {
         D.ell_cls_off[c] = p->ell_cls_off[c];
         D.ell_cls_n[c] = p->ell_cls_n[c];
         D.ell_cls_w[c] = p->ell_cls_w[c];
-        D.ell_cls_grid[c] = grid_for(p->ell_cls_n[c]);
+        int pc = 8;
+        if (p->ell_cls_n[c] > 0)
+            (void)fk::ell_per_cu(p->d, p->G, p->f32, false,
+                                 (size_t)(kBlock / p->G) * p->ell_cls_w[c] * sizeof(double), &pc);
+        D.ell_cls_grid[c] = grid_for(p->ell_cls_n[c], pc);
     }
     D.row_work = (const fk::WorkItem *)p->at("row_work");
     D.split_work = (const fk::WorkItem *)p->at("split_work");

@@ -174,6 +174,7 @@ struct PlanDev {
     int ell_sep_off[kEllClasses];
     int ell_sep_n[kEllClasses];
     int ell_sep_l[kEllClasses];     // longest box axis in the class (LDS vectors)
+    int ell_sep_tb[kEllClasses];    // bytes of the class's largest block table
     int ell_sep_grid[kEllClasses];
     int n_ell_cls;
     int ell_cls_off[kEllClasses];
@@ -191,6 +192,17 @@ hipError_t launch_tables(const PlanDev &P, int n, hipStream_t s);
 hipError_t launch_step_fused(const PlanDev &P, bool f32, int n, const void *packed,
                              void *u_out, hipStream_t s);
 bool step_node_compiled(int d, int qs);
+// LDS bytes of a separable-assembly launch: the axis vectors of 64 rows
+// (d x 2 x lm columns) and a zero column, then the class's block table
+inline size_t ell_sep_lds(int d, int lm, int tb, bool f32)
+{
+    return (size_t)(d * 2 * lm + 1) * 64 * (f32 ? 4 : 8) + (size_t)tb;
+}
+// Workgroups of an assembly kernel resident per CU at an LDS size, at most 8
+// (the persistent grids of the assembly are sized so that every workgroup is
+// resident at once): sep = the separable kernel (256 threads), else the
+// LDS-box kernel with lane groups of G.  *out = 8 when the query fails.
+hipError_t ell_per_cu(int d, int G, bool f32, bool sep, size_t lds, int *out);
 // the separable-box form: d >= 2, affine axes, a compiled Q*
 bool box_compiled(int d, int qs);
 

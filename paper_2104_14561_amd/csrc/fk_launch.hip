@@ -132,6 +132,25 @@ hipError_t launch_step_fused(const PlanDev &P, bool f32, int n, const void *pack
     return hipSuccess;
 }
 
+hipError_t ell_per_cu(int d, int G_, bool f32, bool sep, size_t lds, int *out)
+{
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    *out = 8;
+    if (sep) {
+        FK_DISPATCH_D(d,
+            if (f32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_assemble_ell_sep<float, D>, 256, lds);
+            else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_assemble_ell_sep<double, D>, 256, lds));
+    } else {
+        FK_DISPATCH_D(d, FK_DISPATCH_G(G_,
+            if (f32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_assemble_ell<float, D, G>, kBlock, lds);
+            else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_assemble_ell<double, D, G>, kBlock, lds)));
+    }
+    if (e != hipSuccess) return e;
+    if (nb >= 1 && nb < 8) *out = nb;
+    return hipSuccess;
+}
+
 hipError_t launch_assemble_ell(const PlanDev &P, bool f32, int n, int *org, void *vals,
                                void *exit_mass, hipStream_t s)
 {
@@ -140,7 +159,7 @@ hipError_t launch_assemble_ell(const PlanDev &P, bool f32, int n, int *org, void
     for (int c = 0; c < P.n_ell_sep_cls; ++c) {
         const WorkItem *work = P.ell_sep_work + P.ell_sep_off[c];
         const int nw = P.ell_sep_n[c], lm = P.ell_sep_l[c], grid = P.ell_sep_grid[c];
-        const size_t lds = (size_t)P.d * 2 * lm * 64 * (f32 ? sizeof(float) : sizeof(double));
+        const size_t lds = ell_sep_lds(P.d, lm, P.ell_sep_tb[c], f32);
         FK_DISPATCH_D(P.d,
             if (f32) k_assemble_ell_sep<float, D><<<grid, 256, lds, s>>>(P, n, work, nw, lm, org, (float *)vals, (float *)exit_mass);
             else k_assemble_ell_sep<double, D><<<grid, 256, lds, s>>>(P, n, work, nw, lm, org, (double *)vals, (double *)exit_mass));
