@@ -387,6 +387,9 @@ def main():
                     help="only the assembled (ELL) form on the batch, as its own JSON line")
     ap.add_argument("--abc3d-only", action="store_true",
                     help="only the 129^3 ABC batch leg, as its own JSON line")
+    ap.add_argument("--extensions-only", action="store_true",
+                    help="only the forward passes of the extensions (roll flow, R2, runaway "
+                         "model), as their own JSON line")
     ap.add_argument("--force-fp64", default=None,
                     help="comma-separated instances to compute in FP64 instead of running the "
                          "precision probe (profiling runs: the probe's selection given "
@@ -428,6 +431,9 @@ def main():
         return
     if args.abc3d_only:
         print(json.dumps({"abc3d_batch8": abc3d_leg(stream, log)}), flush=True)
+        return
+    if args.extensions_only:
+        print(json.dumps({"extensions_forward": extra_rows_leg(stream, log)}), flush=True)
         return
     log(f"workload cell2d_batch64: {len(probs)} instances, N={N}, FP32 apply, forward + adjoint")
 
