@@ -175,7 +175,9 @@ typedef struct {
                         (FK_ERR_UNSUPPORTED otherwise).  auto picks 4 for 3D
                         plans with many active nodes, 1 for other large plans,
                         3 for small ones, 2 when the others are not compiled
-                        for gh_q; fk_tune measures them instead */
+                        for gh_q; fk_tune measures them instead.  Plans with
+                        faces other than exit-1 (or the runaway model) take 4
+                        as 1, and with FK_HERMITE_R2 always run 2 */
     int columns;     /* fk_forward_horizons: most columns one launch of the
                         FK_FORM_ELL product takes (1..4; 0 = 1); the workspace
                         holds that many record planes */
