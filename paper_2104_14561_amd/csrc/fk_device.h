@@ -1026,9 +1026,12 @@ __global__ void __launch_bounds__(kBlock) k_step_fused(
 // FC: face kinds other than exit-1 and node-dependent diffusion (the
 // runaway model): the node's own per-axis scales, reflecting faces mirrored
 // by the axis evaluation, and a second exit mass for exits with value 0 (the
-// lowest exiting axis decides a point's value, as in the loops' order).
+// lowest exiting axis decides a point's value, as in the loops' order).  In
+// FP32 up to Q* = 4 it is held to 3 waves per SIMD (167 VGPRs, a few spilled;
+// measured on the runaway model at Q* = 4: 124 against 140 us per step at the
+// 2 waves of its 183 VGPRs).
 template <typename T, int D, int QS, int G, bool AFF, bool TW = false, bool FC = false>
-__global__ void __launch_bounds__(kBlock) k_step_node(
+__global__ void __launch_bounds__(kBlock, (FC && sizeof(T) == 4 && QS <= 4) ? 3 : 1) k_step_node(
     const PlanDev P, int n, int n_work, const DevInst *__restrict__ insts,
     const WorkItem *__restrict__ work, const int *__restrict__ nodes,
     const double2 *__restrict__ trig, const double *__restrict__ coords,
