@@ -146,7 +146,10 @@ hipError_t ell_per_cu(int d, int G_, bool f32, bool sep, size_t lds, int *out)
             if (f32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_assemble_ell<float, D, G>, kBlock, lds);
             else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_assemble_ell<double, D, G>, kBlock, lds)));
     }
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) {
+        (void)hipGetLastError();   // a failed query must not surface at a later launch check
+        return e;
+    }
     if (nb >= 1 && nb < 8) *out = nb;
     return hipSuccess;
 }
